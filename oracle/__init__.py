@@ -1,0 +1,231 @@
+"""CPU oracle of the LUT-weighted Monte Carlo scatter estimator.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg import this package.  It shares no code with the
+HIP library (``paper_2509_05047_amd``) and never imports it.
+
+``simulate`` drives the plain C implementation in ``sse_oracle.c``;
+``post`` holds the binary64 numpy definitions of the sensitivity multiply and
+the Gaussian smoothing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ST_NAMES = ["histories", "steps", "real", "compton", "rayleigh", "absorbed", "killed", "capped",
+            "escaped", "detected", "in_window", "scatter", "true", "rej_window", "rej_same",
+            "rej_ring", "rej_radial", "rej_tof", "rng_blocks"]
+ST_COUNT = len(ST_NAMES)
+
+FATE = dict(detected=0, absorbed=1, killed=2, capped=3, axial=4)
+OUTCOME = dict(scatter=0, true=1, undetected=2, window=3, same_crystal=4, ring_diff=5, radial=6, tof=7)
+
+_PHOTON_FIELDS = [("hx", "<f4"), ("hy", "<f4"), ("hz", "<f4"), ("dx", "<f4"), ("dy", "<f4"), ("dz", "<f4"),
+                  ("e_kev", "<f4"), ("e_det_kev", "<f4"), ("path_mm", "<f4"), ("crystal_ring", "<u4"),
+                  ("lut_index", "<u4"), ("inter", "<u4")]
+PHOTON_DTYPE = np.dtype(_PHOTON_FIELDS)
+RECORD_DTYPE = np.dtype([("outcome", "<u4"), ("bin_lo", "<u4"), ("bin_hi", "<u4"), ("voxel", "<u4"),
+                         ("weight", "<f4"), ("tau_mm", "<f4"), ("n_steps", "<u4"), ("reserved", "<u4"),
+                         ("ph", PHOTON_DTYPE, (2,))])
+assert RECORD_DTYPE.itemsize == 128
+
+
+class Scanner(C.Structure):
+    _fields_ = [("n_crystals", C.c_int32), ("n_rings", C.c_int32), ("radius_mm", C.c_float),
+                ("length_mm", C.c_float), ("crystals_per_module", C.c_int32),
+                ("rings_per_block", C.c_int32), ("max_ring_diff", C.c_int32)]
+
+
+class Sino(C.Structure):
+    _fields_ = [("n_rad", C.c_int32), ("n_view", C.c_int32), ("n_plane", C.c_int32), ("n_tof", C.c_int32),
+                ("tof_bin_mm", C.c_float), ("tof_sigma_mm", C.c_float)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("e_lo_kev", C.c_float), ("e_hi_kev", C.c_float), ("e_kill_kev", C.c_float),
+                ("e_fwhm_frac", C.c_float), ("f_compton", C.c_float), ("f_rayleigh", C.c_float),
+                ("f_photo", C.c_float), ("rayleigh_beta", C.c_float), ("mu_majorant", C.c_float),
+                ("max_interactions", C.c_int32)]
+
+
+class Phantom(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("voxel_mm", C.c_float * 3), ("lo_mm", C.c_float * 3)]
+
+
+class Lut(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 5), ("e_min_kev", C.c_float), ("e_max_kev", C.c_float)]
+
+
+_P = C.c_void_p
+_libs = {}
+
+
+def _lib(variant: str = "f32"):
+    if variant not in _libs:
+        path = _build.lib_path(variant)
+        if not os.path.exists(path):
+            _build.build()
+        lib = C.CDLL(path)
+        lib.orc_build_alias.argtypes = [_P, C.c_uint64, _P, _P]
+        lib.orc_build_alias.restype = C.c_int
+        lib.orc_simulate.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64,
+                                     _P, _P, _P, _P, _P, _P, _P]
+        lib.orc_simulate.restype = C.c_int
+        lib.orc_philox.argtypes = [_P, _P, _P]
+        lib.orc_u01.argtypes = [C.c_uint32]
+        lib.orc_u01.restype = C.c_float
+        lib.orc_emit.argtypes = [_P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, _P]
+        lib.orc_sample_compton.argtypes = [C.c_uint64, C.c_double, C.c_uint64, _P, _P]
+        lib.orc_sample_rayleigh.argtypes = [C.c_uint64, C.c_double, C.c_float, C.c_uint64, _P]
+        lib.orc_energy_model.argtypes = [_P, C.c_double, _P]
+        lib.orc_lor.argtypes = [C.c_int32, C.c_int32, C.c_int32, _P, _P, _P]
+        lib.orc_real_size.restype = C.c_int
+        _libs[variant] = lib
+    return _libs[variant]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# descriptor conversion (from the workloads dataclasses / dicts)
+# --------------------------------------------------------------------------
+
+def scanner_struct(s) -> Scanner:
+    return Scanner(s.n_crystals, s.n_rings, s.radius_mm, s.length_mm, s.crystals_per_module,
+                   s.rings_per_block, s.max_ring_diff)
+
+
+def sino_struct(s) -> Sino:
+    return Sino(s.n_rad, s.n_view, s.n_plane, s.n_tof, s.tof_bin_mm, s.tof_sigma_mm)
+
+
+def physics_struct(p: dict) -> Physics:
+    return Physics(p["e_lo_kev"], p["e_hi_kev"], p["e_kill_kev"], p["e_fwhm_frac"], p["f_compton"],
+                   p["f_rayleigh"], p["f_photo"], p["rayleigh_beta"], p["mu_majorant"], p["max_interactions"])
+
+
+def phantom_struct(d) -> Phantom:
+    return Phantom(d.nx, d.ny, d.nz, (C.c_float * 3)(*d.voxel_mm), (C.c_float * 3)(*d.lo_mm))
+
+
+def lut_struct(d) -> Lut:
+    return Lut((C.c_int32 * 5)(*d.dims), d.e_min_kev, d.e_max_kev)
+
+
+# --------------------------------------------------------------------------
+# API
+# --------------------------------------------------------------------------
+
+def philox(ctr, key):
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    _lib().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def u01(x: int) -> float:
+    return float(_lib().orc_u01(x))
+
+
+def build_alias(activity: np.ndarray):
+    a = np.ascontiguousarray(activity, np.float32).ravel()
+    th = np.zeros(a.size, np.uint32)
+    al = np.zeros(a.size, np.uint32)
+    if _lib().orc_build_alias(_ptr(a), a.size, _ptr(th), _ptr(al)) != 0:
+        raise ValueError("invalid activity for the alias table")
+    return th, al
+
+
+def emit(desc, thresh, alias, seed, h, variant="f32"):
+    vox = np.zeros(1, np.uint32)
+    pos = np.zeros(3)
+    d = np.zeros(3)
+    ph = phantom_struct(desc)
+    _lib(variant).orc_emit(C.byref(ph), _ptr(thresh), _ptr(alias), seed, h, _ptr(vox), _ptr(pos), _ptr(d))
+    return int(vox[0]), pos, d
+
+
+def sample_compton(seed, e_kev, n, variant="f32"):
+    ct = np.zeros(n)
+    e = np.zeros(n)
+    _lib(variant).orc_sample_compton(seed, e_kev, n, _ptr(ct), _ptr(e))
+    return ct, e
+
+
+def sample_rayleigh(seed, e_kev, beta, n, variant="f32"):
+    ct = np.zeros(n)
+    _lib(variant).orc_sample_rayleigh(seed, e_kev, beta, n, _ptr(ct))
+    return ct
+
+
+def energy_model(physics: dict, e_kev: float):
+    out = np.zeros(3)
+    p = physics_struct(physics)
+    _lib().orc_energy_model(C.byref(p), e_kev, _ptr(out))
+    return out
+
+
+def lor(n_crystals, c1, c2):
+    v = np.zeros(1, np.int32)
+    r = np.zeros(1, np.int32)
+    a = np.zeros(1, np.int32)
+    _lib().orc_lor(n_crystals, c1, c2, _ptr(v), _ptr(r), _ptr(a))
+    return int(v[0]), int(r[0]), int(a[0])
+
+
+def real_size(variant="f32") -> int:
+    return int(_lib(variant).orc_real_size())
+
+
+def simulate(scanner, sino, physics, pdesc, mu, activity=None, alias=None, lut_desc=None, lut=None,
+             seed=1, h0=0, n=0, h_list=None, sinograms=True, trues=False, records=False,
+             variant="f32"):
+    """Run the oracle.  ``alias`` is (thresh, alias) or built from ``activity``.
+    ``lut`` holds float32 values (dequantised if the LUT is stored narrower).
+    Returns a dict with 'scatter_counts', 'scatter_weights' (flat, sinogram
+    order [tof][plane][view][rad]), optional trues, 'stats' (dict) and
+    'records' (structured array)."""
+    mu = np.ascontiguousarray(mu, np.float32).ravel()
+    if alias is None:
+        alias = build_alias(activity)
+    th, al = alias
+    lut = np.ascontiguousarray(lut, np.float32).ravel()
+    if h_list is not None:
+        h_list = np.ascontiguousarray(h_list, np.uint64)
+        n = h_list.size
+    nb = sino.n_bins
+    out = {}
+    sc_n = np.zeros(nb, np.uint32) if sinograms else None
+    sc_w = np.zeros(nb, np.float64) if sinograms else None
+    tr_n = np.zeros(nb, np.uint32) if trues else None
+    tr_w = np.zeros(nb, np.float64) if trues else None
+    st = np.zeros(ST_COUNT, np.uint64)
+    rec = np.zeros(n, RECORD_DTYPE) if records else None
+    s_sc, s_sn, s_ph = scanner_struct(scanner), sino_struct(sino), physics_struct(physics)
+    s_pd, s_ld = phantom_struct(pdesc), lut_struct(lut_desc)
+    rc = _lib(variant).orc_simulate(C.byref(s_sc), C.byref(s_sn), C.byref(s_ph), C.byref(s_pd), _ptr(mu),
+                                    _ptr(th), _ptr(al), C.byref(s_ld), _ptr(lut), seed, h0, n, _ptr(h_list),
+                                    _ptr(sc_n), _ptr(sc_w), _ptr(tr_n), _ptr(tr_w), _ptr(st), _ptr(rec))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    out["scatter_counts"], out["scatter_weights"] = sc_n, sc_w
+    out["true_counts"], out["true_weights"] = tr_n, tr_w
+    out["stats"] = {k: int(v) for k, v in zip(ST_NAMES, st)}
+    out["records"] = rec
+    return out
+
+
+def record_bins(rec: np.ndarray) -> np.ndarray:
+    """Flat sinogram bin of each record (-1 where none)."""
+    b = rec["bin_lo"].astype(np.int64) | (rec["bin_hi"].astype(np.int64) << 32)
+    b[(rec["bin_lo"] == 0xFFFFFFFF) & (rec["bin_hi"] == 0xFFFFFFFF)] = -1
+    return b

@@ -1,0 +1,109 @@
+"""Binary64 definitions of the sinogram post-processing steps.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* ``apply_sensitivity``: the final scatter estimate is the LUT-weighted
+  simulator sinogram times the LUT-specific scatter-sensitivity sinogram
+  (Methods, "Scatter sensitivity sinogram"), scaled to absolute units
+  (the simulator output is intrinsically scaled, Discussion) and rounded once
+  to binary32.
+* ``gaussian_smooth``: separable Gaussian smoothing of the scatter sinogram
+  along the radial, angular and planar axes (Methods, "Known activity
+  distribution, very limited simulation time"; FWHM given in bins in Results).
+  Readings: the kernel is the normalised Gaussian truncated at
+  ``int(truncate * sigma + 0.5)`` bins; radial and planar edges reflect with
+  the edge sample repeated; the angular axis is periodic over pi with the
+  LOR flipped across the seam (radial index r -> n_rad - 1 - r, TOF bin
+  t -> n_tof - 1 - t); TOF bins are not smoothed.
+* ``emission_scale``: expected emissions per simulated history.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def apply_sensitivity(weights: np.ndarray, scale: float, sens: np.ndarray) -> np.ndarray:
+    """float32(scale * W * sens), evaluated in binary64.  ``sens`` has the
+    sinogram shape or lacks the leading TOF axis (then it is shared by all TOF
+    bins)."""
+    w = np.asarray(weights, np.float64)
+    s = np.asarray(sens, np.float64)
+    if s.ndim == w.ndim - 1:
+        s = s[None]
+    return ((scale * w) * s).astype(np.float32)
+
+
+def gaussian_kernel(sigma: float, truncate: float = 4.0):
+    radius = int(truncate * sigma + 0.5)
+    x = np.arange(-radius, radius + 1, dtype=np.float64)
+    w = np.exp(-0.5 * x * x / (sigma * sigma))
+    return w / w.sum(), radius
+
+
+def reflect_index(i: np.ndarray, n: int) -> np.ndarray:
+    """Half-sample symmetric extension (d c b a | a b c d | d c b a)."""
+    period = 2 * n
+    m = np.mod(i, period)
+    return np.where(m < n, m, period - 1 - m)
+
+
+def _smooth_rad(x, sigma, truncate):
+    w, rad = gaussian_kernel(sigma, truncate)
+    n = x.shape[-1]
+    idx = np.arange(n)
+    out = np.zeros_like(x)
+    for k in range(-rad, rad + 1):
+        out += w[k + rad] * x[..., reflect_index(idx + k, n)]
+    return out
+
+
+def _smooth_plane(x, sigma, truncate):
+    w, rad = gaussian_kernel(sigma, truncate)
+    n = x.shape[1]
+    idx = np.arange(n)
+    out = np.zeros_like(x)
+    for k in range(-rad, rad + 1):
+        out += w[k + rad] * x[:, reflect_index(idx + k, n), :, :]
+    return out
+
+
+def _smooth_view(x, sigma, truncate):
+    w, rad = gaussian_kernel(sigma, truncate)
+    nt, _, nv, nr = x.shape
+    flipped = x[::-1, :, :, ::-1]          # same LOR seen from the other end
+    out = np.zeros_like(x)
+    v = np.arange(nv)
+    for k in range(-rad, rad + 1):
+        m = np.mod(v + k, 2 * nv)
+        is_flip = m >= nv
+        src = np.where(is_flip, m - nv, m)
+        contrib = np.where(is_flip[None, None, :, None], flipped[:, :, src, :], x[:, :, src, :])
+        out += w[k + rad] * contrib
+    return out
+
+
+def gaussian_smooth(sino: np.ndarray, sigma_bins, truncate: float = 4.0) -> np.ndarray:
+    """Smooth a [tof][plane][view][rad] sinogram with per-axis sigma
+    (rad, view, plane) in bins; a sigma of 0 leaves that axis alone.
+    Returns binary64."""
+    x = np.asarray(sino, np.float64)
+    if x.ndim == 3:
+        x = x[None]
+    s_rad, s_view, s_plane = (float(s) for s in sigma_bins)
+    if s_rad > 0:
+        x = _smooth_rad(x, s_rad, truncate)
+    if s_view > 0:
+        x = _smooth_view(x, s_view, truncate)
+    if s_plane > 0:
+        x = _smooth_plane(x, s_plane, truncate)
+    return x
+
+
+def emission_scale(activity: np.ndarray, voxel_mm, n_histories: int, acq_seconds: float = 1.0,
+                   factor: float = 1.0) -> float:
+    """Expected annihilations per simulated history: total activity (per ml)
+    times voxel volume (ml) times acquisition time, over the history count,
+    times a global factor."""
+    vol_ml = float(voxel_mm[0]) * float(voxel_mm[1]) * float(voxel_mm[2]) * 1e-3
+    total = float(np.sum(np.asarray(activity, np.float64)))
+    return total * vol_ml * acq_seconds / n_histories * factor

@@ -1,0 +1,755 @@
+/* CPU oracle of the LUT-weighted Monte Carlo PET scatter estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  It shares no code
+ * with the HIP library.  It is plain, sequential and slow on purpose.
+ *
+ * What it computes (the paper's scatter-simulation pipeline, Methods,
+ * "Scatter simulation", Fig. 3):
+ *   1. emit an annihilation pair from the activity map (emission voxel is part
+ *      of the simulator's list-mode record, "Scatter simulator description");
+ *   2. transport both photons through the attenuation map (Woodcock tracking;
+ *      Compton, Rayleigh, photoabsorption) until they cross the detection
+ *      cylinder: the simulator detects every photon crossing a plain cylinder
+ *      and models no detector physics ("Scatter simulator description");
+ *   3. assign each detected single a transaxial crystal and a ring from its hit
+ *      position ("Scatter simulator description", Fig. 4);
+ *   4. look up its detection probability in the 5D LUT indexed by energy,
+ *      transaxial and axial incidence angle, and in-module / in-block crystal
+ *      ("Photon detection probability LUT", Fig. 5);
+ *   5. a coincidence adds p1 * p2 (instead of one count) to its TOF sinogram
+ *      bin; the TOF bin comes from the difference of the photons' times
+ *      ("Scatter simulator description");
+ *   6. a coincidence is scattered if at least one photon scattered in the
+ *      object (Introduction, footnote on trues and scatters).
+ * Every event is either weighted or dropped, never duplicated ("Edge crystal
+ * assignment LUT", closing paragraph).
+ *
+ * The paper leaves the photon physics, the random number generator and the
+ * sinogram conventions to its simulator; the readings used here are listed in
+ * the design notes and are followed step for step below.
+ *
+ * Precision.  The file is compiled twice.  With ORACLE_REAL=float every step
+ * of the transport that decides an integer (a voxel, an interaction, a
+ * crystal, a bin) is taken in binary32, the kernel's precision, with correctly
+ * rounded + - * / sqrt and no contraction; logarithms, arc tangents and the
+ * cross-section formula are evaluated in binary64 and, where their result
+ * feeds binary32 arithmetic, rounded once to binary32.  With
+ * ORACLE_REAL=double the same steps run in binary64 (the "FP64 oracle" used to
+ * state the error of binary32 transport).  Weights are always accumulated in
+ * binary64, in history order.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef ORACLE_REAL
+#define ORACLE_REAL float
+#endif
+typedef ORACLE_REAL real;
+#define R(x) ((real)(x))
+
+#define MEC2_KEV 510.99895          /* electron rest energy (CODATA 2018) */
+#define PI_D 3.141592653589793
+#define TWO_PI_D 6.283185307179586
+#define HALF_PI_D 1.5707963267948966
+#define MAX_STEPS 100000            /* tentative Woodcock steps per photon */
+#define MAX_TRIES 1000              /* rejection-loop guard (never reached) */
+
+int orc_real_size(void) { return (int)sizeof(real); }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): 10 rounds of two 32x32->64 multiplications with   */
+/* the Weyl key schedule.                                                     */
+/* ------------------------------------------------------------------------ */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* One random stream: history h, substream s (0 emission, 1 photon A,
+ * 2 photon B, 3 coincidence).  Block j has counter (j, h_lo, h_hi, s) and key
+ * (seed_lo, seed_hi); the stream's words are the blocks' words in order. */
+typedef struct {
+  uint32_t key[2];
+  uint32_t ctr[4];
+  uint32_t buf[4];
+  int pos;
+  uint64_t blocks;
+} rng_t;
+
+static void rng_init(rng_t* r, uint64_t seed, uint64_t h, uint32_t s) {
+  r->key[0] = (uint32_t)seed;
+  r->key[1] = (uint32_t)(seed >> 32);
+  r->ctr[0] = 0;
+  r->ctr[1] = (uint32_t)h;
+  r->ctr[2] = (uint32_t)(h >> 32);
+  r->ctr[3] = s;
+  r->pos = 4;
+  r->blocks = 0;
+}
+
+static uint32_t next32(rng_t* r) {
+  if (r->pos == 4) {
+    orc_philox(r->ctr, r->key, r->buf);
+    r->ctr[0] += 1;
+    r->pos = 0;
+    r->blocks += 1;
+  }
+  return r->buf[r->pos++];
+}
+
+/* Uniform in (0, 1): the top 24 bits with the lowest forced to one, times
+ * 2^-24 (exact in binary32, never 0 or 1). */
+float orc_u01(uint32_t x) { return (float)((x >> 8) | 1u) * 5.9604644775390625e-08f; }
+
+static real u01(rng_t* r) { return (real)((next32(r) >> 8) | 1u) * R(5.9604644775390625e-08); }
+
+/* -ln(u), evaluated in binary64 and rounded once to the transport precision. */
+static real neg_log(real u) { return (real)(-log((double)u)); }
+
+/* Standard normal by Marsaglia's polar method (Marsaglia & Bray 1964). */
+static real std_normal(rng_t* r) {
+  for (int i = 0; i < MAX_TRIES; ++i) {
+    real a = R(2) * u01(r) - R(1);
+    real b = R(2) * u01(r) - R(1);
+    real s = a * a + b * b;
+    if (s < R(1)) return a * (real)sqrt(-2.0 * log((double)s) / (double)s);
+  }
+  return R(0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integer alias table over voxels (Walker 1977; Vose 1991).                 */
+/* Activity a_i becomes integer weights q_i summing to V * 2^32:              */
+/*   S = sum a_i (binary64, ascending i), q_i = floor(a_i * (V 2^32 / S)),    */
+/*   residual V 2^32 - sum q_i added to the first voxel of largest q.         */
+/* Columns hold 2^32 each.  Vose's pairing with two LIFO stacks filled in     */
+/* ascending index order: pop l from "small" and g from "large", column l     */
+/* keeps q_l and aliases g, q_g -= 2^32 - q_l, g goes back to "small" if now  */
+/* below 2^32 else to "large".  Leftover columns are full: threshold          */
+/* 0xffffffff, alias = itself.  Sampling column i with a 32-bit draw x keeps i */
+/* if x < thresh[i], else takes alias[i].                                    */
+/* ------------------------------------------------------------------------ */
+int orc_build_alias(const float* activity, uint64_t n, uint32_t* thresh, uint32_t* alias) {
+  if (n == 0) return -1;
+  double sum = 0.0;
+  for (uint64_t i = 0; i < n; ++i) {
+    double a = (double)activity[i];
+    if (!(a >= 0.0) || isinf(a)) return -1;
+    sum += a;
+  }
+  if (!(sum > 0.0) || isinf(sum)) return -1;
+  const uint64_t T = (uint64_t)1 << 32;
+  uint64_t* q = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* small = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* large = (uint64_t*)malloc(n * sizeof(uint64_t));
+  if (!q || !small || !large) { free(q); free(small); free(large); return -1; }
+  double scale = (double)n * 4294967296.0 / sum;
+  uint64_t total = 0, imax = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    q[i] = (uint64_t)floor((double)activity[i] * scale);
+    total += q[i];
+    if (q[i] > q[imax]) imax = i;
+  }
+  q[imax] += n * T - total; /* modular: also right if total overshoots */
+  uint64_t ns = 0, nl = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (q[i] < T) small[ns++] = i; else large[nl++] = i;
+  }
+  while (ns > 0 && nl > 0) {
+    uint64_t l = small[--ns];
+    uint64_t g = large[--nl];
+    thresh[l] = (uint32_t)q[l];
+    alias[l] = (uint32_t)g;
+    q[g] = q[g] - (T - q[l]);
+    if (q[g] < T) small[ns++] = g; else large[nl++] = g;
+  }
+  while (nl > 0) { uint64_t g = large[--nl]; thresh[g] = 0xffffffffu; alias[g] = (uint32_t)g; }
+  while (ns > 0) { uint64_t l = small[--ns]; thresh[l] = 0xffffffffu; alias[l] = (uint32_t)l; }
+  free(q); free(small); free(large);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry and physics context                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct { real x, y, z; } vec3;
+
+typedef struct {
+  const orc_scanner* sc;
+  const orc_sino* sn;
+  const orc_physics* ph;
+  const orc_phantom* pd;
+  const float* mu;
+  const uint32_t* thresh;
+  const uint32_t* alias;
+  const orc_lut* ld;
+  const float* lut;
+  uint64_t nvox;
+  vec3 lo, hi, inv_vox, vox;
+  real mu_maj;       /* Woodcock majorant at 511 keV */
+  real RR, half_len, pitch, e_scale;
+} ctx_t;
+
+/* Total Klein-Nishina cross section in units of 2 pi r_e^2, a = E / m_e c^2
+ * (Klein & Nishina 1929). */
+static double kn_total(double a) {
+  double L = log(1.0 + 2.0 * a);
+  double t1 = (1.0 + a) / (a * a) * (2.0 * (1.0 + a) / (1.0 + 2.0 * a) - L / a);
+  double t2 = L / (2.0 * a);
+  double t3 = (1.0 + 3.0 * a) / ((1.0 + 2.0 * a) * (1.0 + 2.0 * a));
+  return t1 + t2 - t3;
+}
+
+/* Energy-dependent coefficients of the separable attenuation model
+ * mu(x, E) = mu511(x) g(E), g(E) = fC KN(E)/KN(511) + fR (511/E)^2 + fP (511/E)^3. */
+typedef struct { real E, alpha, g, cC, cCR, inv_maj; } ecoef_t;
+
+static void model_parts(const orc_physics* ph, double a, double* fc, double* fr, double* fp) {
+  double k = kn_total(a) / kn_total(1.0);
+  *fc = (double)ph->f_compton * k;
+  *fr = (double)ph->f_rayleigh * (1.0 / (a * a));
+  *fp = (double)ph->f_photo * (1.0 / (a * a * a));
+}
+
+static void set_energy(ecoef_t* c, real E, const ctx_t* C) {
+  double fc, fr, fp;
+  c->E = E;
+  c->alpha = E / R(MEC2_KEV);
+  model_parts(C->ph, (double)c->alpha, &fc, &fr, &fp);
+  c->g = (real)(fc + fr + fp);
+  c->cC = (real)fc;
+  c->cCR = (real)(fc + fr);
+  c->inv_maj = R(1) / (C->mu_maj * c->g);
+}
+
+void orc_energy_model(const orc_physics* ph, double e_kev, double out[3]) {
+  double fc, fr, fp;
+  model_parts(ph, e_kev / MEC2_KEV, &fc, &fr, &fp);
+  out[0] = fc + fr + fp;
+  out[1] = fc;
+  out[2] = fr;
+}
+
+/* Distance along d from p to the exit of the voxel box (slab method). */
+static real box_exit(const ctx_t* C, vec3 p, vec3 d) {
+  real t = R(INFINITY);
+  real s;
+  if (d.x > R(0)) { s = (C->hi.x - p.x) / d.x; if (s < t) t = s; }
+  else if (d.x < R(0)) { s = (C->lo.x - p.x) / d.x; if (s < t) t = s; }
+  if (d.y > R(0)) { s = (C->hi.y - p.y) / d.y; if (s < t) t = s; }
+  else if (d.y < R(0)) { s = (C->lo.y - p.y) / d.y; if (s < t) t = s; }
+  if (d.z > R(0)) { s = (C->hi.z - p.z) / d.z; if (s < t) t = s; }
+  else if (d.z < R(0)) { s = (C->lo.z - p.z) / d.z; if (s < t) t = s; }
+  return t;
+}
+
+static int clamp_index(real f, int n) {
+  if (!(f >= R(0))) return 0;
+  if (f >= (real)n) return n - 1;
+  return (int)f;
+}
+
+static uint64_t voxel_of(const ctx_t* C, vec3 q) {
+  int ix = clamp_index((real)floor((double)((q.x - C->lo.x) * C->inv_vox.x)), C->pd->nx);
+  int iy = clamp_index((real)floor((double)((q.y - C->lo.y) * C->inv_vox.y)), C->pd->ny);
+  int iz = clamp_index((real)floor((double)((q.z - C->lo.z) * C->inv_vox.z)), C->pd->nz);
+  return ((uint64_t)iz * (uint64_t)C->pd->ny + (uint64_t)iy) * (uint64_t)C->pd->nx + (uint64_t)ix;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Emission: voxel by the alias table, uniform position inside it, isotropic */
+/* direction by Marsaglia's method (Marsaglia 1972); photon B = -d.  No      */
+/* positron range, no acollinearity, no decay.                               */
+/* ------------------------------------------------------------------------ */
+static void emit(const ctx_t* C, rng_t* r, uint32_t* voxel, vec3* p, vec3* d) {
+  uint64_t lo = next32(r);
+  uint64_t hi = next32(r);
+  uint64_t x0 = (hi << 32) | lo;
+  uint64_t col = (uint64_t)(((unsigned __int128)x0 * (unsigned __int128)C->nvox) >> 64);
+  uint32_t x1 = next32(r);
+  uint32_t v = (x1 < C->thresh[col]) ? (uint32_t)col : C->alias[col];
+  *voxel = v;
+  uint32_t nx = (uint32_t)C->pd->nx, ny = (uint32_t)C->pd->ny;
+  uint32_t ix = v % nx, iy = (v / nx) % ny, iz = v / (nx * ny);
+  real ux = u01(r);
+  real uy = u01(r);
+  real uz = u01(r);
+  p->x = C->lo.x + ((real)ix + ux) * C->vox.x;
+  p->y = C->lo.y + ((real)iy + uy) * C->vox.y;
+  p->z = C->lo.z + ((real)iz + uz) * C->vox.z;
+  for (int i = 0; i < MAX_TRIES; ++i) {
+    real a = R(2) * u01(r) - R(1);
+    real b = R(2) * u01(r) - R(1);
+    real s = a * a + b * b;
+    if (s < R(1)) {
+      real q = R(2) * (real)sqrt((double)(R(1) - s));
+      d->x = a * q;
+      d->y = b * q;
+      d->z = R(1) - R(2) * s;
+      return;
+    }
+  }
+  d->x = R(0); d->y = R(0); d->z = R(1);
+}
+
+/* Klein-Nishina sampling by Kahn's rejection method (Kahn 1954): samples
+ * x = E / E' in [1, 1 + 2 alpha]. */
+static int sample_kahn(rng_t* r, real alpha, real* x_out) {
+  real twoa = R(2) * alpha;
+  real b1 = R(1) + twoa;
+  real b2 = R(9) + twoa;
+  for (int i = 0; i < MAX_TRIES; ++i) {
+    real r1 = u01(r);
+    real r2 = u01(r);
+    real r3 = u01(r);
+    if (r1 * b2 <= b1) {
+      real x = R(1) + twoa * r2;
+      if (r3 * (x * x) <= R(4) * (x - R(1))) { *x_out = x; return 1; }
+    } else {
+      real x = b1 / (R(1) + twoa * r2);
+      real c = R(1) + (R(1) - x) / alpha;
+      if (R(2) * r3 <= c * c + R(1) / x) { *x_out = x; return 1; }
+    }
+  }
+  return 0;
+}
+
+/* Rayleigh angle: Thomson factor (1 + cos^2)/2 times the analytic squared
+ * form factor (1 + beta' (1 - cos))^-2 with beta' = beta (E/511)^2.  The form
+ * factor part is sampled by inversion in t = 1 - cos, the Thomson factor by
+ * rejection. */
+static int sample_rayleigh(rng_t* r, real alpha, real beta, real* cos_out) {
+  real bp = beta * (alpha * alpha);
+  real C = (R(2) * bp) / (R(1) + R(2) * bp);
+  for (int i = 0; i < MAX_TRIES; ++i) {
+    real r1 = u01(r);
+    real r2 = u01(r);
+    real q = r1 * C;
+    real t = q / ((R(1) - q) * bp);
+    real c = R(1) - t;
+    if (c < R(-1)) c = R(-1);
+    if (R(2) * r2 <= R(1) + c * c) { *cos_out = c; return 1; }
+  }
+  return 0;
+}
+
+/* Uniform azimuth as (cos phi, sin phi) from a point in the unit disk
+ * (von Neumann 1951). */
+static void azimuth(rng_t* r, real* cp, real* sp) {
+  for (int i = 0; i < MAX_TRIES; ++i) {
+    real a = R(2) * u01(r) - R(1);
+    real b = R(2) * u01(r) - R(1);
+    real s = a * a + b * b;
+    if (s < R(1)) {
+      *cp = (a * a - b * b) / s;
+      *sp = (R(2) * a * b) / s;
+      return;
+    }
+  }
+  *cp = R(1); *sp = R(0);
+}
+
+/* New direction after scattering by polar cosine ct and azimuth (cp, sp)
+ * about the old direction. */
+static void rotate(vec3* d, real ct, real cp, real sp) {
+  real st = (real)sqrt((double)((R(1) - ct) * (R(1) + ct)));
+  real ux = d->x, uy = d->y, uz = d->z;
+  if (fabs((double)uz) > (double)R(0.99999)) {
+    real sg = uz > R(0) ? R(1) : R(-1);
+    d->x = st * cp;
+    d->y = st * sp;
+    d->z = sg * ct;
+  } else {
+    real tmp = (real)sqrt((double)((R(1) - uz) * (R(1) + uz)));
+    d->x = ux * ct + st * (ux * uz * cp - uy * sp) / tmp;
+    d->y = uy * ct + st * (uy * uz * cp + ux * sp) / tmp;
+    d->z = uz * ct - tmp * st * cp;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport of one photon to the detection cylinder                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int fate;
+  real E, Edet, path;
+  real hx, hy, hz, dx, dy, dz;
+  int nC, nR;
+  uint32_t steps;
+} photon_t;
+
+static void transport(const ctx_t* C, rng_t* r, vec3 p0, vec3 d, photon_t* o, uint64_t* st) {
+  ecoef_t ec;
+  set_energy(&ec, R(MEC2_KEV), C);
+  real len = R(0);
+  real t = R(0);
+  real texit = box_exit(C, p0, d);
+  int nC = 0, nR = 0, nint = 0;
+  uint32_t steps = 0;
+  int fate = -1;
+  for (;;) {
+    if (steps >= MAX_STEPS) { fate = ORC_FATE_CAPPED; break; }
+    steps += 1;
+    /* Woodcock tentative step with the majorant at the current energy */
+    real s = neg_log(u01(r)) * ec.inv_maj;
+    t = t + s;
+    if (!(t < texit)) break; /* leaves the voxel box: straight to the cylinder */
+    vec3 q;
+    q.x = p0.x + t * d.x;
+    q.y = p0.y + t * d.y;
+    q.z = p0.z + t * d.z;
+    real mu = (real)C->mu[voxel_of(C, q)];
+    if (!(u01(r) * C->mu_maj < mu)) continue; /* null collision */
+    st[ORC_ST_REAL] += 1;
+    p0 = q;
+    len = len + t;
+    t = R(0);
+    nint += 1;
+    if (nint > C->ph->max_interactions) { fate = ORC_FATE_CAPPED; break; }
+    real ug = u01(r) * ec.g;
+    real ct;
+    if (ug < ec.cC) {
+      real x;
+      if (!sample_kahn(r, ec.alpha, &x)) { fate = ORC_FATE_ABSORBED; break; }
+      real E2 = ec.E / x;
+      ct = R(1) - (x - R(1)) / ec.alpha;
+      if (ct < R(-1)) ct = R(-1);
+      if (ct > R(1)) ct = R(1);
+      nC += 1;
+      st[ORC_ST_COMPTON] += 1;
+      if (E2 < (real)C->ph->e_kill_kev) { fate = ORC_FATE_KILLED; break; }
+      set_energy(&ec, E2, C);
+    } else if (ug < ec.cCR) {
+      if (!sample_rayleigh(r, ec.alpha, (real)C->ph->rayleigh_beta, &ct)) { fate = ORC_FATE_ABSORBED; break; }
+      nR += 1;
+      st[ORC_ST_RAYLEIGH] += 1;
+    } else {
+      fate = ORC_FATE_ABSORBED;
+      break;
+    }
+    real cp, sp;
+    azimuth(r, &cp, &sp);
+    rotate(&d, ct, cp, sp);
+    texit = box_exit(C, p0, d);
+  }
+  st[ORC_ST_STEPS] += steps;
+  o->steps = steps;
+  o->nC = nC;
+  o->nR = nR;
+  o->E = ec.E;
+  o->Edet = ec.E;
+  o->path = R(0);
+  o->hx = o->hy = o->hz = R(0);
+  o->dx = d.x; o->dy = d.y; o->dz = d.z;
+  if (fate >= 0) {
+    o->fate = fate;
+    if (fate == ORC_FATE_ABSORBED) st[ORC_ST_ABSORBED] += 1;
+    else if (fate == ORC_FATE_KILLED) st[ORC_ST_KILLED] += 1;
+    else st[ORC_ST_CAPPED] += 1;
+    return;
+  }
+  st[ORC_ST_ESCAPED] += 1;
+  /* Crossing of the cylinder x^2 + y^2 = R^2 ahead of p0 (the larger root of
+   * a t^2 + 2 b t + c = 0, in the form without cancellation). */
+  real a = d.x * d.x + d.y * d.y;
+  if (!(a > R(0))) { o->fate = ORC_FATE_AXIAL; return; }
+  real b = p0.x * d.x + p0.y * d.y;
+  real c = p0.x * p0.x + p0.y * p0.y - C->RR;
+  real D = b * b - a * c;
+  real sq = (real)sqrt((double)D);
+  real tc = (b > R(0)) ? (-c) / (b + sq) : (sq - b) / a;
+  real hz = p0.z + tc * d.z;
+  if (!(hz >= -C->half_len && hz < C->half_len)) { o->fate = ORC_FATE_AXIAL; return; }
+  o->fate = ORC_FATE_DETECTED;
+  o->hx = p0.x + tc * d.x;
+  o->hy = p0.y + tc * d.y;
+  o->hz = hz;
+  o->path = len + tc;
+  st[ORC_ST_DETECTED] += 1;
+  if (C->ph->e_fwhm_frac > 0.0f) {
+    real n = std_normal(r);
+    real sig = ((real)C->ph->e_fwhm_frac / R(2.35482)) * (real)sqrt((double)(R(MEC2_KEV) / ec.E));
+    o->Edet = ec.E * (R(1) + sig * n);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single -> crystal, ring, LUT entry                                        */
+/* ------------------------------------------------------------------------ */
+static int bin_angle(double th, int n) {
+  double f = floor((th + HALF_PI_D) * (double)n / PI_D);
+  if (!(f >= 0.0)) return 0;
+  if (f >= (double)n) return n - 1;
+  return (int)f;
+}
+
+static void single_index(const ctx_t* C, const photon_t* o, int* crystal, int* ring, uint32_t* lut_index) {
+  const orc_scanner* sc = C->sc;
+  /* crystal c covers azimuth [2 pi c / Nc, 2 pi (c + 1) / Nc) */
+  double phi = atan2((double)o->hy, (double)o->hx);
+  if (phi < 0.0) phi += TWO_PI_D;
+  double fc = floor(phi * (double)sc->n_crystals / TWO_PI_D);
+  int c = (fc >= (double)sc->n_crystals) ? sc->n_crystals - 1 : (fc < 0.0 ? 0 : (int)fc);
+  /* rings tile [-L/2, L/2) */
+  int rg = clamp_index((real)floor((double)((o->hz + C->half_len) / C->pitch)), sc->n_rings);
+  *crystal = c;
+  *ring = rg;
+  /* LUT axes: energy, transaxial angle, axial angle, crystal in module,
+   * crystal in block.  The angles are those between the path and the hit
+   * point's position vector, projected in the transaxial and axial planes,
+   * over [-90, 90] degrees (Fig. 5 caption). */
+  const int* dm = C->ld->dims;
+  int iE = clamp_index((real)floor((double)((o->E - (real)C->ld->e_min_kev) * C->e_scale)), dm[0]);
+  double hx = (double)o->hx, hy = (double)o->hy;
+  double rho = sqrt(hx * hx + hy * hy);
+  double dr = (hx * (double)o->dx + hy * (double)o->dy) / rho;
+  double tt = (hx * (double)o->dy - hy * (double)o->dx) / rho;
+  int it = bin_angle(atan2(tt, dr), dm[1]);
+  int ia = bin_angle(atan2((double)o->dz, dr), dm[2]);
+  int ct = ((c % sc->crystals_per_module) * dm[3]) / sc->crystals_per_module;
+  int ca = ((rg % sc->rings_per_block) * dm[4]) / sc->rings_per_block;
+  *lut_index = (uint32_t)((((iE * dm[1] + it) * dm[2] + ia) * dm[3] + ct) * dm[4] + ca);
+}
+
+/* Sinogram coordinates of the LOR between crystals c1 and c2: the view angle
+ * is pi k / Nc with k = c1 + c2 + 1 folded into [0, Nc), the signed radial
+ * index rho = Nc/2 - |c1 - c2| (sign flips with the fold), two neighbouring k
+ * share one view.  The TOF-positive end is the crystal lying on the positive
+ * side of the LOR direction (-sin, cos) of the view angle. */
+void orc_lor(int32_t n, int32_t c1, int32_t c2, int32_t* view, int32_t* rho, int32_t* a_is_pos) {
+  int k = c1 + c2 + 1;
+  int dc = c1 > c2 ? c1 - c2 : c2 - c1;
+  int rh = n / 2 - dc;
+  if (k >= n) { k -= n; rh = -rh; }
+  *view = k >> 1;
+  *rho = rh;
+  int m = ((2 * c1 + 1 - k) % (2 * n) + 2 * n) % (2 * n);
+  *a_is_pos = (m > 0 && m < n) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One history                                                               */
+/* ------------------------------------------------------------------------ */
+static void fill_photon_rec(orc_photon_rec* pr, const photon_t* o) {
+  pr->hx = (float)o->hx; pr->hy = (float)o->hy; pr->hz = (float)o->hz;
+  pr->dx = (float)o->dx; pr->dy = (float)o->dy; pr->dz = (float)o->dz;
+  pr->e_kev = (float)o->E;
+  pr->e_det_kev = (float)o->Edet;
+  pr->path_mm = (float)o->path;
+  pr->crystal_ring = 0xffffffffu;
+  pr->lut_index = 0xffffffffu;
+  pr->inter = (uint32_t)o->nC | ((uint32_t)o->nR << 8) | ((uint32_t)o->fate << 16);
+}
+
+static void history(const ctx_t* C, uint64_t seed, uint64_t h,
+                    uint32_t* sc_n, double* sc_w, uint32_t* tr_n, double* tr_w,
+                    uint64_t* st, orc_record* rec) {
+  rng_t r0, r1, r2, r3;
+  rng_init(&r0, seed, h, 0);
+  rng_init(&r1, seed, h, 1);
+  rng_init(&r2, seed, h, 2);
+  rng_init(&r3, seed, h, 3);
+  uint32_t voxel;
+  vec3 p, d, dm;
+  emit(C, &r0, &voxel, &p, &d);
+  dm.x = -d.x; dm.y = -d.y; dm.z = -d.z;
+  photon_t A, B;
+  transport(C, &r1, p, d, &A, st);
+  transport(C, &r2, p, dm, &B, st);
+  st[ORC_ST_HISTORIES] += 1;
+
+  uint32_t outcome;
+  uint64_t bin = ~(uint64_t)0;
+  real w = R(0), tau = R(0);
+  int cA = -1, rA = -1, cB = -1, rB = -1;
+  uint32_t lA = 0xffffffffu, lB = 0xffffffffu;
+  int inwinA = A.fate == ORC_FATE_DETECTED && A.Edet >= (real)C->ph->e_lo_kev && A.Edet <= (real)C->ph->e_hi_kev;
+  int inwinB = B.fate == ORC_FATE_DETECTED && B.Edet >= (real)C->ph->e_lo_kev && B.Edet <= (real)C->ph->e_hi_kev;
+  if (inwinA) { single_index(C, &A, &cA, &rA, &lA); st[ORC_ST_IN_WINDOW] += 1; }
+  if (inwinB) { single_index(C, &B, &cB, &rB, &lB); st[ORC_ST_IN_WINDOW] += 1; }
+  int scattered = (A.nC + A.nR + B.nC + B.nR) > 0;
+  if (A.fate != ORC_FATE_DETECTED || B.fate != ORC_FATE_DETECTED) {
+    outcome = ORC_OUT_UNDETECTED;
+  } else if (!inwinA || !inwinB) {
+    outcome = ORC_OUT_WINDOW;
+    st[ORC_ST_REJ_WINDOW] += 1;
+  } else if (cA == cB) {
+    outcome = ORC_OUT_SAME_CRYSTAL;
+    st[ORC_ST_REJ_SAME] += 1;
+  } else if (C->sc->max_ring_diff >= 0 && abs(rA - rB) > C->sc->max_ring_diff) {
+    outcome = ORC_OUT_RING_DIFF;
+    st[ORC_ST_REJ_RING] += 1;
+  } else {
+    int view, rho, apos;
+    orc_lor(C->sc->n_crystals, cA, cB, &view, &rho, &apos);
+    int half = (C->sn->n_rad - 1) / 2;
+    if (abs(rho) > half) {
+      outcome = ORC_OUT_RADIAL;
+      st[ORC_ST_REJ_RADIAL] += 1;
+    } else {
+      /* TOF offset toward the TOF-positive end: half the path difference */
+      tau = apos ? (B.path - A.path) * R(0.5) : (A.path - B.path) * R(0.5);
+      if (C->sn->tof_sigma_mm > 0.0f) tau = tau + (real)C->sn->tof_sigma_mm * std_normal(&r3);
+      real xt = tau / (real)C->sn->tof_bin_mm + (real)C->sn->n_tof * R(0.5);
+      if (!(xt >= R(0)) || !(xt < (real)C->sn->n_tof)) {
+        outcome = ORC_OUT_TOF;
+        st[ORC_ST_REJ_TOF] += 1;
+      } else {
+        uint64_t tof = (uint64_t)floor((double)xt);
+        uint64_t plane = (uint64_t)(rA + rB);
+        uint64_t rad = (uint64_t)(rho + half);
+        bin = ((tof * (uint64_t)C->sn->n_plane + plane) * (uint64_t)C->sn->n_view + (uint64_t)view)
+              * (uint64_t)C->sn->n_rad + rad;
+        w = (real)C->lut[lA] * (real)C->lut[lB];
+        if (scattered) {
+          outcome = ORC_OUT_SCATTER;
+          st[ORC_ST_SCATTER] += 1;
+          if (sc_n) sc_n[bin] += 1u;
+          if (sc_w) sc_w[bin] += (double)w;
+        } else {
+          outcome = ORC_OUT_TRUE;
+          st[ORC_ST_TRUE] += 1;
+          if (tr_n) tr_n[bin] += 1u;
+          if (tr_w) tr_w[bin] += (double)w;
+        }
+      }
+    }
+  }
+  st[ORC_ST_RNG_BLOCKS] += r0.blocks + r1.blocks + r2.blocks + r3.blocks;
+  if (rec) {
+    rec->outcome = outcome | (scattered ? 0x100u : 0u);
+    rec->bin_lo = (uint32_t)bin;
+    rec->bin_hi = (uint32_t)(bin >> 32);
+    rec->voxel = voxel;
+    rec->weight = (float)w;
+    rec->tau_mm = (float)tau;
+    rec->n_steps = A.steps + B.steps;
+    rec->reserved = 0;
+    fill_photon_rec(&rec->ph[0], &A);
+    fill_photon_rec(&rec->ph[1], &B);
+    if (inwinA) { rec->ph[0].crystal_ring = (uint32_t)cA | ((uint32_t)rA << 16); rec->ph[0].lut_index = lA; }
+    if (inwinB) { rec->ph[1].crystal_ring = (uint32_t)cB | ((uint32_t)rB << 16); rec->ph[1].lut_index = lB; }
+  }
+}
+
+static int setup(ctx_t* C, const orc_scanner* sc, const orc_sino* sn, const orc_physics* ph,
+                 const orc_phantom* pd, const float* mu, const uint32_t* th, const uint32_t* al,
+                 const orc_lut* ld, const float* lut) {
+  if (!sc || !sn || !ph || !pd || !mu || !th || !al || !ld || !lut) return -1;
+  if (sc->n_crystals <= 0 || sc->n_crystals % 2 || sc->n_rings <= 0) return -1;
+  if (sn->n_view != sc->n_crystals / 2 || sn->n_plane != 2 * sc->n_rings - 1) return -1;
+  if (sn->n_rad <= 0 || sn->n_rad % 2 == 0 || sn->n_rad > sc->n_crystals - 1 || sn->n_tof <= 0) return -1;
+  if (pd->nx <= 0 || pd->ny <= 0 || pd->nz <= 0) return -1;
+  if (!(ph->rayleigh_beta > 0.0f)) return -1;
+  C->sc = sc; C->sn = sn; C->ph = ph; C->pd = pd; C->mu = mu; C->thresh = th; C->alias = al;
+  C->ld = ld; C->lut = lut;
+  C->nvox = (uint64_t)pd->nx * (uint64_t)pd->ny * (uint64_t)pd->nz;
+  C->vox.x = (real)pd->voxel_mm[0]; C->vox.y = (real)pd->voxel_mm[1]; C->vox.z = (real)pd->voxel_mm[2];
+  C->lo.x = (real)pd->lo_mm[0]; C->lo.y = (real)pd->lo_mm[1]; C->lo.z = (real)pd->lo_mm[2];
+  C->hi.x = C->lo.x + (real)pd->nx * C->vox.x;
+  C->hi.y = C->lo.y + (real)pd->ny * C->vox.y;
+  C->hi.z = C->lo.z + (real)pd->nz * C->vox.z;
+  C->inv_vox.x = R(1) / C->vox.x; C->inv_vox.y = R(1) / C->vox.y; C->inv_vox.z = R(1) / C->vox.z;
+  float mmax = 0.0f;
+  for (uint64_t i = 0; i < C->nvox; ++i) {
+    if (!(mu[i] >= 0.0f)) return -1;
+    if (mu[i] > mmax) mmax = mu[i];
+  }
+  if (ph->mu_majorant > 0.0f) {
+    if (ph->mu_majorant < mmax) return -1;
+    mmax = ph->mu_majorant;
+  }
+  C->mu_maj = (real)mmax;
+  C->RR = (real)sc->radius_mm * (real)sc->radius_mm;
+  C->half_len = R(0.5) * (real)sc->length_mm;
+  C->pitch = (real)sc->length_mm / (real)sc->n_rings;
+  C->e_scale = (real)ld->dims[0] / ((real)ld->e_max_kev - (real)ld->e_min_kev);
+  return 0;
+}
+
+int orc_simulate(const orc_scanner* sc, const orc_sino* sn, const orc_physics* ph,
+                 const orc_phantom* pd, const float* mu511,
+                 const uint32_t* alias_thresh, const uint32_t* alias_idx,
+                 const orc_lut* ld, const float* lut,
+                 uint64_t seed, uint64_t h0, uint64_t n, const uint64_t* h_list,
+                 uint32_t* scatter_counts, double* scatter_weights,
+                 uint32_t* true_counts, double* true_weights,
+                 uint64_t* stats, orc_record* records) {
+  ctx_t C;
+  if (setup(&C, sc, sn, ph, pd, mu511, alias_thresh, alias_idx, ld, lut)) return -1;
+  uint64_t local[ORC_ST_COUNT];
+  memset(local, 0, sizeof(local));
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t h = h_list ? h_list[i] : h0 + i;
+    history(&C, seed, h, scatter_counts, scatter_weights, true_counts, true_weights, local,
+            records ? &records[i] : NULL);
+  }
+  if (stats)
+    for (int k = 0; k < ORC_ST_COUNT; ++k) stats[k] += local[k];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Test hooks                                                                */
+/* ------------------------------------------------------------------------ */
+void orc_emit(const orc_phantom* pd, const uint32_t* th, const uint32_t* al,
+              uint64_t seed, uint64_t h, uint32_t* voxel, double pos[3], double dir[3]) {
+  ctx_t C;
+  memset(&C, 0, sizeof(C));
+  C.pd = pd; C.thresh = th; C.alias = al;
+  C.nvox = (uint64_t)pd->nx * (uint64_t)pd->ny * (uint64_t)pd->nz;
+  C.vox.x = (real)pd->voxel_mm[0]; C.vox.y = (real)pd->voxel_mm[1]; C.vox.z = (real)pd->voxel_mm[2];
+  C.lo.x = (real)pd->lo_mm[0]; C.lo.y = (real)pd->lo_mm[1]; C.lo.z = (real)pd->lo_mm[2];
+  rng_t r;
+  rng_init(&r, seed, h, 0);
+  vec3 p, d;
+  emit(&C, &r, voxel, &p, &d);
+  pos[0] = (double)p.x; pos[1] = (double)p.y; pos[2] = (double)p.z;
+  dir[0] = (double)d.x; dir[1] = (double)d.y; dir[2] = (double)d.z;
+}
+
+void orc_sample_compton(uint64_t seed, double e_kev, uint64_t n, double* cos_theta, double* e_out) {
+  real E = (real)e_kev;
+  real alpha = E / R(MEC2_KEV);
+  for (uint64_t i = 0; i < n; ++i) {
+    rng_t r;
+    rng_init(&r, seed, i, 1);
+    real x = R(1);
+    sample_kahn(&r, alpha, &x);
+    real ct = R(1) - (x - R(1)) / alpha;
+    if (ct < R(-1)) ct = R(-1);
+    if (ct > R(1)) ct = R(1);
+    cos_theta[i] = (double)ct;
+    e_out[i] = (double)(E / x);
+  }
+}
+
+void orc_sample_rayleigh(uint64_t seed, double e_kev, float beta, uint64_t n, double* cos_theta) {
+  real alpha = (real)e_kev / R(MEC2_KEV);
+  for (uint64_t i = 0; i < n; ++i) {
+    rng_t r;
+    rng_init(&r, seed, i, 1);
+    real c = R(1);
+    sample_rayleigh(&r, alpha, (real)beta, &c);
+    cos_theta[i] = (double)c;
+  }
+}
