@@ -1,0 +1,151 @@
+"""Throughput benchmark of the LUT-weighted Monte Carlo scatter path on one GPU.
+
+One step = one pass of the whole path over one batch: zero the sinograms,
+simulate the clinical workload's histories (emission, Woodcock transport,
+detection, LUT weighting, TOF sinogram accumulation), then the sensitivity
+multiply (scale * W * sens -> float).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--lut f32|f16|bf16] [--workload clinical|large]
+
+Only one GPU is used; --gpus above 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+# Per-unit VALU cost model of the transport kernel (lane-instructions per
+# unit of the method's work; quarter-rate instructions count 4).  Units are
+# counted by the oracle and the kernel alike (statistics counters).
+COST = dict(rng_block=130, step=70, real=250, detected=150, history=150)
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, pdesc, mu, act, lut_desc, lut_f32, n):
+    """The oracle as it stands, single thread, on the first n histories."""
+    import oracle as O
+    alias = O.build_alias(act)
+    t0 = time.perf_counter()
+    r = O.simulate(w.scanner, w.sino, w.physics, pdesc, mu, alias=alias,
+                   lut_desc=lut_desc, lut=lut_f32, seed=w.seed, n=n, trues=False)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "histories/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name} workload, histories 0..{n} of seed {w.seed}, one thread, {dt:.1f} s",
+            "scatter_coincidences_per_sec": r["stats"]["scatter"] / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="clinical", choices=["clinical", "large"])
+    ap.add_argument("--histories", type=float, default=0, help="override histories per step")
+    ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--cpu-histories", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(histories shard by index; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_05047_amd as sse
+
+    torch.cuda.set_device(0)
+    w = W.WORKLOADS[args.workload]
+    pdesc, mu, act = W.make_phantom(w)
+    lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    lut_dtype = {"f32": sse.F32, "f16": sse.F16, "bf16": sse.BF16}[args.lut]
+    lut_store = {"f32": lut, "f16": lut.astype(np.float16).view(np.uint16), "bf16": W.to_bf16_bits(lut)}[args.lut]
+    n = int(args.histories) if args.histories else w.n_histories
+    sens = W.make_sensitivity(w.sino, seed=3, tof_axis=True)
+    log(f"[bench] workload {w.name}: {n:.3g} histories/step, sinogram {w.sino.shape}, LUT {args.lut}")
+    ctx = sse.Context(w.scanner, w.sino, w.physics)
+    pid = ctx.load_phantom(pdesc, mu, act)
+    ctx.load_lut(lut_desc, lut_store, dtype=lut_dtype)
+    ctx.load_sensitivity(sens, has_tof_axis=True)
+    del sens
+    out = ctx.new_outputs(trues=False, stats=True)
+    final = torch.empty(ctx.n_bins, dtype=torch.float32, device="cuda")
+    scale = ctx.emission_scale(pid, n)
+    stream = torch.cuda.current_stream()
+    tr_start = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    tr_end = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+
+    def step(i=None):
+        out["scatter_counts"].zero_()
+        out["scatter_weights"].zero_()
+        if i is not None:
+            tr_start[i].record(stream)
+        ctx.simulate(pid, n, w.seed, out, stream=stream)
+        if i is not None:
+            tr_end[i].record(stream)
+        ctx.apply_sensitivity(out["scatter_weights"], scale, final, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    out["stats"].zero_()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+        log(f"[bench] step {i + 1}/{args.steps} queued")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = sse.stats_dict(out["stats"])
+    kernel_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+    ctx.close()
+
+    per_hist = {k: stats[v] / stats["histories"] for k, v in
+                (("rng_block", "rng_blocks"), ("step", "steps"), ("real", "real"), ("detected", "detected"))}
+    ops_per_hist = (COST["history"] + sum(COST[k] * per_hist[k] for k in per_hist))
+    kernel_s = float(np.mean(kernel_ms)) / 1e3
+    achieved = ops_per_hist * n / kernel_s
+    result = {
+        "metric": "photon histories/sec",
+        "value": n * args.steps / dt,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {pdesc.nx}x{pdesc.ny}x{pdesc.nz} body phantom, "
+                               f"{w.scanner.n_crystals}x{w.scanner.n_rings} scanner, "
+                               f"{'x'.join(map(str, w.sino.shape[::-1]))} TOF sinogram (rad x view x plane x tof), "
+                               f"{'x'.join(map(str, lut_desc.dims))} {args.lut} LUT",
+                   "histories_per_step": n, "lut_dtype": args.lut, "transport": "f32",
+                   "accumulation": "f64"},
+        "scatter_coincidences_per_sec": stats["scatter"] / dt,
+        "transport_kernel_ms": float(np.mean(kernel_ms)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                     "ops_per_history": ops_per_hist},
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline on {args.cpu_histories} histories")
+        result["cpu_baseline"] = cpu_baseline(w, pdesc, mu, act, lut_desc, lut, args.cpu_histories)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,274 @@
+/* sse.h -- C ABI of the MI355X scatter-estimation library (libsse.so).
+ *
+ * The library computes Monte Carlo scatter estimates for PET in the way of
+ * Noe et al., "Object independent scatter sensitivities for PET, applied to
+ * scatter estimation through fast Monte Carlo simulation" (arXiv 2509.05047):
+ * annihilation pairs are transported through a voxel attenuation / activity
+ * phantom to a plain detection cylinder; every detected single gets a
+ * detection probability from a 5D LUT; each coincidence adds p1 * p2 to its
+ * TOF sinogram bin; the resulting "LUT scatter" sinogram is multiplied by a
+ * LUT-specific scatter-sensitivity sinogram (Methods, "Scatter simulation",
+ * Fig. 3) and may be Gaussian-smoothed first (Methods, "Known activity
+ * distribution, very limited simulation time").
+ *
+ * Conventions for every call:
+ *  - Units: mm, keV.  Positions are relative to the scanner centre, z along
+ *    the scanner axis.
+ *  - Sinograms are C-order arrays [tof][plane][view][rad] (radial fastest).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it and is asynchronous unless stated.
+ *  - Pointers marked "device" must point to device memory of the context's
+ *    GPU; "host" to ordinary host memory.  `mem` arguments (SSE_MEM_HOST or
+ *    SSE_MEM_DEVICE) say which kind an input is.
+ *  - Inputs are borrowed for the duration of the call and copied; the library
+ *    owns everything it allocates; outputs are caller-owned.
+ *  - No C++ exception crosses the ABI.  Every call returns an sse_status;
+ *    sse_last_error() gives a thread-local message for the last failure.
+ *    Device errors of asynchronous work surface at the next synchronising
+ *    call as SSE_EDEVICE.
+ */
+#ifndef SSE_H
+#define SSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSE_ABI_VERSION 1
+
+typedef enum {
+  SSE_OK = 0,
+  SSE_EINVAL = 1,  /* invalid argument or descriptor */
+  SSE_ENOMEM = 2,  /* device or host allocation failed */
+  SSE_EDEVICE = 3, /* HIP runtime error */
+  SSE_ESTATE = 4,  /* call not valid in the current state (e.g. no LUT loaded) */
+  SSE_EBUSY = 5    /* resource in use */
+} sse_status;
+
+typedef enum { SSE_F32 = 0, SSE_F16 = 1, SSE_BF16 = 2 } sse_dtype;
+typedef enum { SSE_MEM_HOST = 0, SSE_MEM_DEVICE = 1 } sse_mem;
+
+typedef struct sse_ctx sse_ctx;
+typedef uint32_t sse_phantom_id;
+
+/* Scanner: a cylinder of radius radius_mm and length length_mm on which every
+ * crossing photon is detected (Methods, "Scatter simulator description").
+ * Crystal c covers azimuth [2 pi c / n, 2 pi (c+1) / n); rings tile
+ * [-L/2, L/2) (Methods, "Signa PET/MR description": 448 crystals in 28
+ * modules of 16, 45 rings in 5 blocks of 9).  max_ring_diff < 0 keeps all. */
+typedef struct {
+  int32_t n_crystals;          /* even, > 0 */
+  int32_t n_rings;             /* > 0 */
+  float radius_mm;             /* > 0 */
+  float length_mm;             /* > 0 */
+  int32_t crystals_per_module; /* > 0; transaxial LUT axis bins c mod this */
+  int32_t rings_per_block;     /* > 0; axial LUT axis bins r mod this */
+  int32_t max_ring_diff;
+} sse_scanner_desc;
+
+/* TOF sinogram: n_view = n_crystals / 2, n_plane = 2 n_rings - 1 (plane =
+ * r1 + r2), n_rad odd <= n_crystals - 1 (radial index rho + (n_rad-1)/2),
+ * TOF bin = floor(tau / tof_bin_mm + n_tof / 2) of the offset tau along the
+ * LOR; tof_sigma_mm is the Gaussian jitter of tau (0 = none).  The paper
+ * takes the TOF bin from the photons' time difference (Methods, "Scatter
+ * simulator description") with 380 ps FWHM resolution (Methods, "Simulated
+ * scans in GATE"). */
+typedef struct {
+  int32_t n_rad, n_view, n_plane, n_tof;
+  float tof_bin_mm;            /* > 0 */
+  float tof_sigma_mm;          /* >= 0 */
+} sse_sino_desc;
+
+/* Photon physics.  Window [e_lo, e_hi] keV (the paper: 300-650 keV with the
+ * LUT at 0.1 % resolution, 425-650 keV without, Methods, "Scatter simulator
+ * description"); photons below e_kill are dropped; e_fwhm_frac is the energy
+ * blur FWHM at 511 keV (0 = none).  Attenuation is separable,
+ * mu(x, E) = mu511(x) g(E), with g(E) = f_compton KN(E)/KN(511) +
+ * f_rayleigh (511/E)^2 + f_photo (511/E)^3; Rayleigh angles follow the
+ * Thomson factor times (1 + beta (E/511)^2 (1 - cos))^-2.  mu_majorant = 0
+ * uses the phantom maximum as the Woodcock majorant at 511 keV. */
+typedef struct {
+  float e_lo_kev, e_hi_kev, e_kill_kev, e_fwhm_frac;
+  float f_compton, f_rayleigh, f_photo; /* >= 0, sum > 0 */
+  float rayleigh_beta;                  /* > 0 */
+  float mu_majorant;                    /* 0 or >= max mu511 (1/mm) */
+  int32_t max_interactions;             /* >= 1 */
+} sse_physics_desc;
+
+/* Voxel phantom: nx * ny * nz voxels, x fastest (index (z*ny + y)*nx + x),
+ * box [lo, lo + n * voxel); air outside.  The box's transaxial corners must
+ * lie inside the cylinder. */
+typedef struct {
+  int32_t nx, ny, nz;
+  float voxel_mm[3];
+  float lo_mm[3];
+} sse_phantom_desc;
+
+/* 5D detection-probability LUT, row-major [E][theta_t][theta_a][ct][ca]
+ * (Methods, "Photon detection probability LUT"): energy bins of
+ * (e_max - e_min) / dims[0] keV from e_min (clamped), transaxial and axial
+ * incidence angle bins of 180/dims deg over [-90, 90] (Fig. 5 caption),
+ * in-module crystal ct = (c mod crystals_per_module) * dims[3] /
+ * crystals_per_module, in-block ring ca = (r mod rings_per_block) * dims[4] /
+ * rings_per_block.  Values in [0, 1]. */
+typedef struct {
+  int32_t dims[5];
+  float e_min_kev, e_max_kev;
+} sse_lut_desc;
+
+/* Statistics counters (unsigned 64-bit each), accumulated by sse_simulate. */
+enum {
+  SSE_ST_HISTORIES = 0, SSE_ST_STEPS, SSE_ST_REAL, SSE_ST_COMPTON, SSE_ST_RAYLEIGH,
+  SSE_ST_ABSORBED, SSE_ST_KILLED, SSE_ST_CAPPED, SSE_ST_ESCAPED, SSE_ST_DETECTED,
+  SSE_ST_IN_WINDOW, SSE_ST_SCATTER, SSE_ST_TRUE, SSE_ST_REJ_WINDOW, SSE_ST_REJ_SAME,
+  SSE_ST_REJ_RING, SSE_ST_REJ_RADIAL, SSE_ST_REJ_TOF, SSE_ST_RNG_BLOCKS, SSE_ST_COUNT
+};
+
+/* Per-history record (128 bytes), for parity checks and list-mode style
+ * inspection.  Word layout:
+ *   0 outcome: 0 scatter, 1 true, 2 a photon undetected, 3 outside the energy
+ *     window, 4 same crystal, 5 ring difference, 6 outside the radial FOV,
+ *     7 outside the TOF range; bit 8 set if either photon scattered
+ *   1,2 flat sinogram bin (low, high word; all ones if none)
+ *   3 emission voxel   4 weight p_A p_B (float)   5 TOF offset tau (float, mm)
+ *   6 Woodcock tentative steps of both photons    7 zero
+ *   8..19 photon A, 20..31 photon B: hit x, y, z, direction x, y, z, energy,
+ *     blurred energy, path length (floats), crystal | ring << 16, flat LUT
+ *     index (all ones if the photon is not detected in the window),
+ *     n_compton | n_rayleigh << 8 | fate << 16 (fate 0 detected, 1 absorbed,
+ *     2 dropped below e_kill, 3 interaction/step cap, 4 missed the cylinder). */
+typedef struct { uint32_t w[32]; } sse_history_record;
+
+/* Outputs of sse_simulate (all device pointers, caller-owned, accumulated
+ * into: zero them before the first call of a run).  scatter_counts and
+ * scatter_weights are required (n_bins entries each, 4- and 8-byte aligned);
+ * the rest may be NULL.  records, if given, receives one record for every
+ * history h with (h - h_offset) % record_stride == 0, at index
+ * (h - h_offset) / record_stride. */
+typedef struct {
+  uint32_t* scatter_counts;
+  double* scatter_weights;
+  uint32_t* true_counts;
+  double* true_weights;
+  unsigned long long* stats;     /* SSE_ST_COUNT entries */
+  sse_history_record* records;
+  uint64_t record_stride;        /* >= 1 when records != NULL */
+} sse_outputs;
+
+/* Version of this ABI (SSE_ABI_VERSION). */
+int sse_abi_version(void);
+
+/* Thread-local message of the last failed call ("" if none).  The pointer is
+ * valid until the next call on the same thread. */
+const char* sse_last_error(void);
+
+/* Create a context on HIP device `device`.  Descriptors are validated and
+ * copied.  *out receives the context (library-owned; free with
+ * sse_destroy).  Errors: SSE_EINVAL for a bad descriptor (odd crystal count,
+ * n_view != n_crystals/2, n_plane != 2 n_rings - 1, even or too large n_rad,
+ * non-positive sizes, invalid physics), SSE_EDEVICE. */
+sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner,
+                      const sse_sino_desc* sino, const sse_physics_desc* physics);
+
+/* Wait for the context's pending work and free everything it owns. */
+sse_status sse_destroy(sse_ctx* ctx);
+
+/* Load a phantom: mu511_per_mm (attenuation at 511 keV, 1/mm) and activity
+ * (any unit, >= 0, not all zero), nx*ny*nz floats each, host or device
+ * (`mem`).  The emission sampler (an integer alias table over voxels) is
+ * built on the host.  The activity and attenuation images are the
+ * simulator's inputs (Fig. 3 caption).  *out receives the phantom id.
+ * Synchronous with respect to the host inputs.  Errors: SSE_EINVAL (bad
+ * descriptor, negative or non-finite values, all-zero activity, box outside
+ * the cylinder), SSE_ENOMEM. */
+sse_status sse_load_phantom(sse_ctx* ctx, const sse_phantom_desc* desc, const float* mu511_per_mm,
+                            const float* activity, int mem, void* stream, sse_phantom_id* out);
+
+/* Replace a loaded phantom's activity (rebuilds its emission sampler); the
+ * iterative estimation loop re-simulates with updated activity (Methods,
+ * "Unknown activity distribution, very limited simulation time"). */
+sse_status sse_update_activity(sse_ctx* ctx, sse_phantom_id id, const float* activity, int mem,
+                               void* stream);
+
+/* Free a phantom.  Errors: SSE_EINVAL (unknown id). */
+sse_status sse_unload_phantom(sse_ctx* ctx, sse_phantom_id id);
+
+/* Load the 5D LUT (see sse_lut_desc) in F32, F16 or BF16 (`dtype`), host or
+ * device.  Values are checked to lie in [0, 1].  Replaces any previous LUT.
+ * Errors: SSE_EINVAL (bad dims, range or values), SSE_ENOMEM. */
+sse_status sse_load_lut(sse_ctx* ctx, const sse_lut_desc* desc, const void* values, int dtype,
+                        int mem, void* stream);
+
+/* Load the scatter-sensitivity sinogram (float, >= 0), with the full
+ * sinogram shape (has_tof_axis = 1) or without the TOF axis (shared by all
+ * TOF bins).  Methods, "Scatter sensitivity sinogram". */
+sse_status sse_load_sensitivity(sse_ctx* ctx, const float* sens, int has_tof_axis, int mem,
+                                void* stream);
+
+/* Simulate histories h_offset .. h_offset + n_histories - 1 of the run
+ * `seed` and accumulate their coincidences into `out`.  A history is one
+ * annihilation: two back-to-back 511 keV photons from a voxel drawn by
+ * activity, uniform inside it.  Each photon is tracked with Woodcock steps,
+ * Compton (Klein-Nishina), Rayleigh and photoabsorption until it leaves the
+ * voxel box, then intersected with the cylinder; a detected single in the
+ * window gets crystal, ring and LUT probability; a coincidence of two
+ * singles in different crystals within the ring-difference, radial and TOF
+ * ranges adds 1 to counts and p_A p_B (binary32 product) to weights
+ * (binary64) of its bin, in the scatter pair if either photon scattered,
+ * else in the trues pair (Methods, "Scatter simulator description";
+ * Introduction, footnote on scatter).  Random numbers: Philox4x32-10 keyed
+ * by the seed, counter (block, h, substream); history results do not depend
+ * on the launch, so runs split over calls or GPUs sum to the same result.
+ * Asynchronous on `stream`.  Errors: SSE_EINVAL (unknown phantom, null or
+ * misaligned outputs, record stride 0), SSE_ESTATE (no LUT loaded). */
+sse_status sse_simulate(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
+                        uint64_t h_offset, const sse_outputs* out, void* stream);
+
+/* Expected annihilations per simulated history: sum(activity) * voxel volume
+ * (ml) * acq_seconds * factor / n_histories (binary64).  The simulator's
+ * output is absolutely scaled (Discussion); `factor` carries a global
+ * correction such as the paper's real-scan factors (Methods, "Real scans").
+ * Errors: SSE_EINVAL. */
+sse_status sse_emission_scale(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories,
+                              double acq_seconds, double factor, double* scale);
+
+/* out[b] = (float)(scale * W[b] * sens[b]) computed in binary64 (device
+ * pointers, n_bins each; W and out must not overlap).  Methods, "Scatter
+ * sensitivity sinogram".  Errors: SSE_EINVAL, SSE_ESTATE (no sensitivity). */
+sse_status sse_apply_sensitivity(sse_ctx* ctx, const double* W, double scale, float* out,
+                                 void* stream);
+
+/* Separable Gaussian smoothing of a float sinogram (device, n_bins each;
+ * in == out allowed) with sigma_bins = {radial, view, plane} (0 skips an
+ * axis), kernel truncated at floor(truncate * sigma + 0.5) bins and
+ * normalised.  Radial and plane edges reflect (edge bin repeated); views are
+ * periodic over 180 degrees, continuing across the seam on the same LORs
+ * seen from the other end (radial and TOF indices reversed); TOF bins are
+ * not smoothed.  Methods, "Known activity distribution, very limited
+ * simulation time" (the paper uses FWHM [9, 6, 10.5] bins).  Uses
+ * library-owned scratch.  Errors: SSE_EINVAL. */
+sse_status sse_gaussian_smooth(sse_ctx* ctx, const float* in, float* out, const float sigma_bins[3],
+                               float truncate, void* stream);
+
+/* Fused post-processing: with sigma_bins NULL, out = scale * W * sens as
+ * sse_apply_sensitivity; otherwise out = sens * G(float(scale * W)), the
+ * smoothed LUT scatter times the sensitivity sinogram (the paper multiplies
+ * by the sensitivity after smoothing, Methods, "Known activity distribution,
+ * very limited simulation time").  Errors: as the two calls above. */
+sse_status sse_finalize(sse_ctx* ctx, const double* W, double scale, const float* sigma_bins,
+                        float truncate, float* out, void* stream);
+
+/* Host helper: the integer alias table the library samples emission voxels
+ * with.  Activity is quantised to integer masses q_i summing to n 2^32
+ * (q_i = floor(a_i n 2^32 / sum a), remainder to the first largest voxel);
+ * Vose's pairing with LIFO small/large stacks filled in index order.  A
+ * column i keeps i for a 32-bit draw below thresh[i], else takes alias[i].
+ * Host pointers, n entries each.  Errors: SSE_EINVAL. */
+sse_status sse_build_alias_table(const float* activity, uint64_t n, uint32_t* thresh, uint32_t* alias);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,571 @@
+// C ABI of libsse.so: context and resource management, argument validation,
+// emission alias tables, and launches of the transport and post-processing
+// kernels.  Declarations and documentation: include/sse.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sse.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+sse_status fail(sse_status st, const std::string& msg) {
+  g_error = msg;
+  return st;
+}
+
+sse_status hip_fail(hipError_t e, const char* what) {
+  g_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SSE_ENOMEM : SSE_EDEVICE;
+}
+
+#define HIP_TRY(expr, what)                    \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+struct Phantom {
+  bool used = false;
+  sse_phantom_desc desc{};
+  uint64_t nvox = 0;
+  float mu_max = 0.0f;
+  double activity_sum = 0.0;
+  float* d_mu = nullptr;
+  uint2* d_alias = nullptr;
+};
+
+}  // namespace
+
+struct sse_ctx {
+  int device = 0;
+  sse_scanner_desc sc{};
+  sse_sino_desc sn{};
+  sse_physics_desc ph{};
+  uint64_t n_bins = 0;
+  double kn511 = 0.0;
+  std::vector<Phantom> phantoms;
+  void* d_lut = nullptr;
+  int lut_type = -1;
+  sse_lut_desc lut{};
+  float* d_sens = nullptr;
+  int sens_tof = 0;
+  float* d_scratch[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void release(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+sse_status check_descs(const sse_scanner_desc* s, const sse_sino_desc* n, const sse_physics_desc* p) {
+  if (!s || !n || !p) return fail(SSE_EINVAL, "null descriptor");
+  if (s->n_crystals <= 0 || s->n_crystals % 2) return fail(SSE_EINVAL, "n_crystals must be even and positive");
+  if (s->n_rings <= 0) return fail(SSE_EINVAL, "n_rings must be positive");
+  if (!finite_pos(s->radius_mm) || !finite_pos(s->length_mm)) return fail(SSE_EINVAL, "radius and length must be positive");
+  if (s->crystals_per_module <= 0 || s->rings_per_block <= 0)
+    return fail(SSE_EINVAL, "crystals_per_module and rings_per_block must be positive");
+  if (n->n_view != s->n_crystals / 2) return fail(SSE_EINVAL, "n_view must equal n_crystals / 2");
+  if (n->n_plane != 2 * s->n_rings - 1) return fail(SSE_EINVAL, "n_plane must equal 2 n_rings - 1");
+  if (n->n_rad <= 0 || n->n_rad % 2 == 0 || n->n_rad > s->n_crystals - 1)
+    return fail(SSE_EINVAL, "n_rad must be odd and at most n_crystals - 1");
+  if (n->n_tof <= 0) return fail(SSE_EINVAL, "n_tof must be positive");
+  if (!finite_pos(n->tof_bin_mm) || !(n->tof_sigma_mm >= 0.0f) || !std::isfinite(n->tof_sigma_mm))
+    return fail(SSE_EINVAL, "bad TOF bin width or jitter");
+  if (!(p->e_lo_kev <= p->e_hi_kev) || !std::isfinite(p->e_lo_kev) || !std::isfinite(p->e_hi_kev))
+    return fail(SSE_EINVAL, "bad energy window");
+  if (!(p->e_kill_kev >= 0.0f) || !std::isfinite(p->e_kill_kev)) return fail(SSE_EINVAL, "bad kill energy");
+  if (!(p->e_fwhm_frac >= 0.0f) || !std::isfinite(p->e_fwhm_frac)) return fail(SSE_EINVAL, "bad energy blur");
+  if (!(p->f_compton >= 0.0f) || !(p->f_rayleigh >= 0.0f) || !(p->f_photo >= 0.0f) ||
+      !(p->f_compton + p->f_rayleigh + p->f_photo > 0.0f) || !std::isfinite(p->f_compton + p->f_rayleigh + p->f_photo))
+    return fail(SSE_EINVAL, "bad interaction fractions");
+  if (!finite_pos(p->rayleigh_beta)) return fail(SSE_EINVAL, "rayleigh_beta must be positive");
+  if (!(p->mu_majorant >= 0.0f) || !std::isfinite(p->mu_majorant)) return fail(SSE_EINVAL, "bad majorant");
+  if (p->max_interactions < 1) return fail(SSE_EINVAL, "max_interactions must be >= 1");
+  const uint64_t bins = static_cast<uint64_t>(n->n_rad) * n->n_view * n->n_plane * n->n_tof;
+  if (bins >= (static_cast<uint64_t>(1) << 62)) return fail(SSE_EINVAL, "sinogram too large");
+  return SSE_OK;
+}
+
+// Copy n floats of host or device memory to a host vector.
+sse_status fetch_floats(const float* src, uint64_t n, int mem, hipStream_t s, std::vector<float>& dst) {
+  dst.resize(n);
+  if (mem == SSE_MEM_HOST) {
+    std::memcpy(dst.data(), src, n * sizeof(float));
+    return SSE_OK;
+  }
+  if (mem != SSE_MEM_DEVICE) return fail(SSE_EINVAL, "mem must be SSE_MEM_HOST or SSE_MEM_DEVICE");
+  HIP_TRY(hipMemcpyAsync(dst.data(), src, n * sizeof(float), hipMemcpyDeviceToHost, s), "copy input to host");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise input copy");
+  return SSE_OK;
+}
+
+// Integer alias table (see sse_build_alias_table); returns false on bad input.
+bool build_alias(const float* act, uint64_t n, uint32_t* thresh, uint32_t* alias, double* sum_out) {
+  if (n == 0 || n > 0xffffffffull) return false;
+  double sum = 0.0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const double a = static_cast<double>(act[i]);
+    if (!(a >= 0.0) || std::isinf(a)) return false;
+    sum += a;
+  }
+  if (!(sum > 0.0) || std::isinf(sum)) return false;
+  const uint64_t T = static_cast<uint64_t>(1) << 32;
+  std::vector<uint64_t> mass(n), small, large;
+  small.reserve(n);
+  large.reserve(n);
+  const double scale = static_cast<double>(n) * 4294967296.0 / sum;
+  uint64_t total = 0, imax = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    mass[i] = static_cast<uint64_t>(std::floor(static_cast<double>(act[i]) * scale));
+    total += mass[i];
+    if (mass[i] > mass[imax]) imax = i;
+  }
+  mass[imax] += n * T - total;
+  for (uint64_t i = 0; i < n; ++i) (mass[i] < T ? small : large).push_back(i);
+  while (!small.empty() && !large.empty()) {
+    const uint64_t l = small.back();
+    small.pop_back();
+    const uint64_t g = large.back();
+    large.pop_back();
+    thresh[l] = static_cast<uint32_t>(mass[l]);
+    alias[l] = static_cast<uint32_t>(g);
+    mass[g] -= T - mass[l];
+    (mass[g] < T ? small : large).push_back(g);
+  }
+  for (uint64_t g : large) { thresh[g] = 0xffffffffu; alias[g] = static_cast<uint32_t>(g); }
+  for (uint64_t l : small) { thresh[l] = 0xffffffffu; alias[l] = static_cast<uint32_t>(l); }
+  if (sum_out) *sum_out = sum;
+  return true;
+}
+
+sse_status upload_alias(const float* act_host, uint64_t n, hipStream_t s, uint2* d_alias, double* sum) {
+  std::vector<uint32_t> th(n), al(n);
+  if (!build_alias(act_host, n, th.data(), al.data(), sum))
+    return fail(SSE_EINVAL, "activity must be finite, non-negative and not all zero");
+  std::vector<uint2> packed(n);
+  for (uint64_t i = 0; i < n; ++i) packed[i] = make_uint2(th[i], al[i]);
+  HIP_TRY(hipMemcpyAsync(d_alias, packed.data(), n * sizeof(uint2), hipMemcpyHostToDevice, s), "upload alias table");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise alias upload");
+  return SSE_OK;
+}
+
+Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
+  if (!c || id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1].used) return nullptr;
+  return &c->phantoms[id - 1];
+}
+
+sse::PostParams post_params(const sse_ctx* c) {
+  return sse::PostParams{c->sn.n_rad, c->sn.n_view, c->sn.n_plane, c->sn.n_tof};
+}
+
+sse_status ensure_scratch(sse_ctx* c) {
+  for (int i = 0; i < 2; ++i)
+    if (!c->d_scratch[i]) HIP_TRY(hipMalloc(&c->d_scratch[i], c->n_bins * sizeof(float)), "allocate smoothing scratch");
+  return SSE_OK;
+}
+
+sse_status smooth(sse_ctx* c, const float* in, float* out, const float* sigma, float truncate, hipStream_t s) {
+  if (!sigma) return fail(SSE_EINVAL, "null sigma");
+  if (!in || !out) return fail(SSE_EINVAL, "null buffer");
+  if (!(truncate > 0.0f) || !std::isfinite(truncate)) return fail(SSE_EINVAL, "truncate must be positive");
+  sse::Taps taps[3];
+  int axes[3], na = 0;
+  for (int a = 0; a < 3; ++a) {
+    const float sg = sigma[a];
+    if (!(sg >= 0.0f) || !std::isfinite(sg)) return fail(SSE_EINVAL, "sigma must be finite and >= 0");
+    if (sg == 0.0f) continue;
+    const double sd = sg;
+    const int radius = static_cast<int>(static_cast<double>(truncate) * sd + 0.5);
+    if (radius > sse::kMaxSmoothRadius) return fail(SSE_EINVAL, "smoothing kernel wider than 127 taps");
+    double w[2 * sse::kMaxSmoothRadius + 1], tot = 0.0;
+    for (int k = -radius; k <= radius; ++k) {
+      w[k + radius] = std::exp(-0.5 * k * k / (sd * sd));
+      tot += w[k + radius];
+    }
+    std::memset(&taps[na], 0, sizeof(sse::Taps));
+    taps[na].radius = radius;
+    for (int k = 0; k <= 2 * radius; ++k) taps[na].w[k] = static_cast<float>(w[k] / tot);
+    axes[na++] = a;
+  }
+  const sse::PostParams g = post_params(c);
+  if (na == 0) {
+    if (in != out) HIP_TRY(hipMemcpyAsync(out, in, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
+    return SSE_OK;
+  }
+  sse_status st = ensure_scratch(c);
+  if (st != SSE_OK) return st;
+  // A pass never reads and writes the same buffer: with in == out and one
+  // active axis the result goes through scratch.
+  const float* src = in;
+  for (int i = 0; i < na; ++i) {
+    const bool last = i == na - 1;
+    float* dst = (last && !(na == 1 && in == out)) ? out : c->d_scratch[i % 2];
+    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, dst, taps[i], s), "smoothing kernel");
+    src = dst;
+  }
+  if (src != out)
+    HIP_TRY(hipMemcpyAsync(out, src, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy smoothed");
+  return SSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sse_abi_version(void) { return SSE_ABI_VERSION; }
+
+const char* sse_last_error(void) { return g_error.c_str(); }
+
+sse_status sse_build_alias_table(const float* activity, uint64_t n, uint32_t* thresh, uint32_t* alias) {
+  if (!activity || !thresh || !alias) return fail(SSE_EINVAL, "null pointer");
+  if (!build_alias(activity, n, thresh, alias, nullptr))
+    return fail(SSE_EINVAL, "activity must be finite, non-negative and not all zero");
+  return SSE_OK;
+}
+
+sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner, const sse_sino_desc* sino,
+                      const sse_physics_desc* physics) {
+  if (!out) return fail(SSE_EINVAL, "null output pointer");
+  *out = nullptr;
+  sse_status st = check_descs(scanner, sino, physics);
+  if (st != SSE_OK) return st;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count), "count devices");
+  if (device < 0 || device >= count) return fail(SSE_EINVAL, "no such HIP device");
+  HIP_TRY(hipSetDevice(device), "set device");
+  sse_ctx* c = new (std::nothrow) sse_ctx();
+  if (!c) return fail(SSE_ENOMEM, "host allocation");
+  c->device = device;
+  c->sc = *scanner;
+  c->sn = *sino;
+  c->ph = *physics;
+  c->n_bins = static_cast<uint64_t>(sino->n_rad) * sino->n_view * sino->n_plane * sino->n_tof;
+  c->kn511 = sse::kn_total(1.0);
+  *out = c;
+  return SSE_OK;
+}
+
+sse_status sse_destroy(sse_ctx* c) {
+  if (!c) return SSE_OK;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& p : c->phantoms) {
+    if (p.d_mu) release(p.d_mu);
+    if (p.d_alias) release(p.d_alias);
+  }
+  if (c->d_lut) release(c->d_lut);
+  if (c->d_sens) release(c->d_sens);
+  for (auto* s : c->d_scratch)
+    if (s) release(s);
+  delete c;
+  return SSE_OK;
+}
+
+sse_status sse_load_phantom(sse_ctx* c, const sse_phantom_desc* d, const float* mu, const float* activity, int mem,
+                            void* stream, sse_phantom_id* out) {
+  if (!c || !d || !mu || !activity || !out) return fail(SSE_EINVAL, "null argument");
+  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(SSE_EINVAL, "phantom dimensions must be positive");
+  for (int i = 0; i < 3; ++i)
+    if (!finite_pos(d->voxel_mm[i]) || !std::isfinite(d->lo_mm[i])) return fail(SSE_EINVAL, "bad voxel size or origin");
+  const uint64_t n = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
+  if (n > 0xffffffffull) return fail(SSE_EINVAL, "too many voxels");
+  // the voxel box must lie inside the detection cylinder transaxially
+  const double R = c->sc.radius_mm;
+  for (int cx = 0; cx < 2; ++cx)
+    for (int cy = 0; cy < 2; ++cy) {
+      const double x = d->lo_mm[0] + cx * static_cast<double>(d->nx) * d->voxel_mm[0];
+      const double y = d->lo_mm[1] + cy * static_cast<double>(d->ny) * d->voxel_mm[1];
+      if (!(x * x + y * y < R * R)) return fail(SSE_EINVAL, "phantom box reaches outside the detection cylinder");
+    }
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<float> hmu, hact;
+  sse_status st = fetch_floats(mu, n, mem, s, hmu);
+  if (st != SSE_OK) return st;
+  st = fetch_floats(activity, n, mem, s, hact);
+  if (st != SSE_OK) return st;
+  float mmax = 0.0f;
+  for (float m : hmu) {
+    if (!(m >= 0.0f) || !std::isfinite(m)) return fail(SSE_EINVAL, "attenuation must be finite and >= 0");
+    mmax = m > mmax ? m : mmax;
+  }
+  if (c->ph.mu_majorant > 0.0f && c->ph.mu_majorant < mmax)
+    return fail(SSE_EINVAL, "physics mu_majorant is below the phantom's maximum attenuation");
+  Phantom p;
+  p.used = true;
+  p.desc = *d;
+  p.nvox = n;
+  p.mu_max = mmax;
+  HIP_TRY(hipMalloc(&p.d_mu, n * sizeof(float)), "allocate attenuation map");
+  hipError_t e = hipMalloc(&p.d_alias, n * sizeof(uint2));
+  if (e != hipSuccess) {
+    release(p.d_mu);
+    return hip_fail(e, "allocate alias table");
+  }
+  st = upload_alias(hact.data(), n, s, p.d_alias, &p.activity_sum);
+  if (st == SSE_OK) {
+    e = hipMemcpyAsync(p.d_mu, hmu.data(), n * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "upload attenuation map");
+  }
+  if (st != SSE_OK) {
+    release(p.d_mu);
+    release(p.d_alias);
+    return st;
+  }
+  for (size_t i = 0; i < c->phantoms.size(); ++i)
+    if (!c->phantoms[i].used) {
+      c->phantoms[i] = p;
+      *out = static_cast<sse_phantom_id>(i + 1);
+      return SSE_OK;
+    }
+  c->phantoms.push_back(p);
+  *out = static_cast<sse_phantom_id>(c->phantoms.size());
+  return SSE_OK;
+}
+
+sse_status sse_update_activity(sse_ctx* c, sse_phantom_id id, const float* activity, int mem, void* stream) {
+  Phantom* p = get_phantom(c, id);
+  if (!p) return fail(SSE_EINVAL, "unknown phantom id");
+  if (!activity) return fail(SSE_EINVAL, "null activity");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<float> hact;
+  sse_status st = fetch_floats(activity, p->nvox, mem, s, hact);
+  if (st != SSE_OK) return st;
+  return upload_alias(hact.data(), p->nvox, s, p->d_alias, &p->activity_sum);
+}
+
+sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {
+  Phantom* p = get_phantom(c, id);
+  if (!p) return fail(SSE_EINVAL, "unknown phantom id");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
+  release(p->d_mu);
+  release(p->d_alias);
+  *p = Phantom();
+  return SSE_OK;
+}
+
+sse_status sse_load_lut(sse_ctx* c, const sse_lut_desc* d, const void* values, int dtype, int mem, void* stream) {
+  if (!c || !d || !values) return fail(SSE_EINVAL, "null argument");
+  uint64_t n = 1;
+  for (int i = 0; i < 5; ++i) {
+    if (d->dims[i] <= 0) return fail(SSE_EINVAL, "LUT dimensions must be positive");
+    n *= static_cast<uint64_t>(d->dims[i]);
+  }
+  if (n >= 0xffffffffull) return fail(SSE_EINVAL, "LUT too large");
+  if (!(d->e_max_kev > d->e_min_kev) || !std::isfinite(d->e_min_kev) || !std::isfinite(d->e_max_kev))
+    return fail(SSE_EINVAL, "LUT energy range must be increasing");
+  size_t esz;
+  if (dtype == SSE_F32) esz = 4;
+  else if (dtype == SSE_F16 || dtype == SSE_BF16) esz = 2;
+  else return fail(SSE_EINVAL, "LUT dtype must be SSE_F32, SSE_F16 or SSE_BF16");
+  if (mem != SSE_MEM_HOST && mem != SSE_MEM_DEVICE) return fail(SSE_EINVAL, "bad mem kind");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<unsigned char> host(n * esz);
+  if (mem == SSE_MEM_HOST) {
+    std::memcpy(host.data(), values, n * esz);
+  } else {
+    HIP_TRY(hipMemcpyAsync(host.data(), values, n * esz, hipMemcpyDeviceToHost, s), "copy LUT to host");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise LUT copy");
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    float v;
+    if (dtype == SSE_F32) {
+      std::memcpy(&v, &host[i * 4], 4);
+    } else {
+      uint16_t b;
+      std::memcpy(&b, &host[i * 2], 2);
+      if (dtype == SSE_BF16) {
+        const uint32_t u = static_cast<uint32_t>(b) << 16;
+        std::memcpy(&v, &u, 4);
+      } else {
+        v = static_cast<float>(__builtin_bit_cast(_Float16, b));
+      }
+    }
+    if (!(v >= 0.0f && v <= 1.0f)) return fail(SSE_EINVAL, "LUT values must lie in [0, 1]");
+  }
+  void* dptr = nullptr;
+  HIP_TRY(hipMalloc(&dptr, n * esz), "allocate LUT");
+  hipError_t e = hipMemcpyAsync(dptr, host.data(), n * esz, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release(dptr);
+    return hip_fail(e, "upload LUT");
+  }
+  if (c->d_lut) {
+    HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
+    release(c->d_lut);
+  }
+  c->d_lut = dptr;
+  c->lut_type = dtype;
+  c->lut = *d;
+  return SSE_OK;
+}
+
+sse_status sse_load_sensitivity(sse_ctx* c, const float* sens, int has_tof_axis, int mem, void* stream) {
+  if (!c || !sens) return fail(SSE_EINVAL, "null argument");
+  const uint64_t n = has_tof_axis ? c->n_bins : c->n_bins / static_cast<uint64_t>(c->sn.n_tof);
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<float> h;
+  sse_status st = fetch_floats(sens, n, mem, s, h);
+  if (st != SSE_OK) return st;
+  for (float v : h)
+    if (!(v >= 0.0f) || !std::isfinite(v)) return fail(SSE_EINVAL, "sensitivity must be finite and >= 0");
+  float* d = nullptr;
+  HIP_TRY(hipMalloc(&d, n * sizeof(float)), "allocate sensitivity");
+  hipError_t e = hipMemcpyAsync(d, h.data(), n * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release(d);
+    return hip_fail(e, "upload sensitivity");
+  }
+  if (c->d_sens) {
+    HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
+    release(c->d_sens);
+  }
+  c->d_sens = d;
+  c->sens_tof = has_tof_axis ? 1 : 0;
+  return SSE_OK;
+}
+
+sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uint64_t seed, uint64_t h_offset,
+                        const sse_outputs* out, void* stream) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  Phantom* ph = get_phantom(c, id);
+  if (!ph) return fail(SSE_EINVAL, "unknown phantom id");
+  if (!c->d_lut) return fail(SSE_ESTATE, "no LUT loaded");
+  if (!out || !out->scatter_counts || !out->scatter_weights) return fail(SSE_EINVAL, "scatter outputs are required");
+  if (reinterpret_cast<uintptr_t>(out->scatter_counts) % 4 || reinterpret_cast<uintptr_t>(out->scatter_weights) % 8 ||
+      reinterpret_cast<uintptr_t>(out->true_counts) % 4 || reinterpret_cast<uintptr_t>(out->true_weights) % 8 ||
+      reinterpret_cast<uintptr_t>(out->stats) % 8 || reinterpret_cast<uintptr_t>(out->records) % 4)
+    return fail(SSE_EINVAL, "misaligned output buffer");
+  if (out->records && out->record_stride == 0) return fail(SSE_EINVAL, "record_stride must be >= 1");
+  if (n_histories > ~static_cast<uint64_t>(0) - h_offset) return fail(SSE_EINVAL, "history range overflows");
+  if (n_histories == 0) return SSE_OK;
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  sse::TransportParams p{};
+  const sse_phantom_desc& d = ph->desc;
+  p.mu = ph->d_mu;
+  p.alias = ph->d_alias;
+  p.nvox = ph->nvox;
+  p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.vx = d.voxel_mm[0]; p.vy = d.voxel_mm[1]; p.vz = d.voxel_mm[2];
+  p.lox = d.lo_mm[0]; p.loy = d.lo_mm[1]; p.loz = d.lo_mm[2];
+  p.hix = p.lox + static_cast<float>(d.nx) * p.vx;
+  p.hiy = p.loy + static_cast<float>(d.ny) * p.vy;
+  p.hiz = p.loz + static_cast<float>(d.nz) * p.vz;
+  p.ivx = 1.0f / p.vx; p.ivy = 1.0f / p.vy; p.ivz = 1.0f / p.vz;
+  p.mu_maj = c->ph.mu_majorant > 0.0f ? c->ph.mu_majorant : ph->mu_max;
+  p.n_crystals = c->sc.n_crystals;
+  p.n_rings = c->sc.n_rings;
+  p.cmod = c->sc.crystals_per_module;
+  p.rblk = c->sc.rings_per_block;
+  p.max_ring_diff = c->sc.max_ring_diff;
+  p.rr = c->sc.radius_mm * c->sc.radius_mm;
+  p.half_len = 0.5f * c->sc.length_mm;
+  p.pitch = c->sc.length_mm / static_cast<float>(c->sc.n_rings);
+  p.n_rad = c->sn.n_rad; p.n_view = c->sn.n_view; p.n_plane = c->sn.n_plane; p.n_tof = c->sn.n_tof;
+  p.tof_bin = c->sn.tof_bin_mm;
+  p.tof_sigma = c->sn.tof_sigma_mm;
+  p.e_lo = c->ph.e_lo_kev; p.e_hi = c->ph.e_hi_kev; p.e_kill = c->ph.e_kill_kev; p.e_fwhm = c->ph.e_fwhm_frac;
+  p.rayleigh_beta = c->ph.rayleigh_beta;
+  p.f_c = static_cast<double>(c->ph.f_compton);
+  p.f_r = static_cast<double>(c->ph.f_rayleigh);
+  p.f_p = static_cast<double>(c->ph.f_photo);
+  p.kn511 = c->kn511;
+  p.max_int = c->ph.max_interactions;
+  {  // coefficients at 511 keV, evaluated once on the host
+    sse::ECoef& e = p.e511;
+    e.E = sse::kMec2;
+    e.alpha = e.E / sse::kMec2;
+    const double a = static_cast<double>(e.alpha);
+    const double fc = p.f_c * (sse::kn_total(a) / p.kn511);
+    const double fr = p.f_r * (1.0 / (a * a));
+    const double fp = p.f_p * (1.0 / (a * a * a));
+    e.g = static_cast<float>(fc + fr + fp);
+    e.cC = static_cast<float>(fc);
+    e.cCR = static_cast<float>(fc + fr);
+    e.inv_maj = 1.0f / (p.mu_maj * e.g);
+  }
+  p.lut = c->d_lut;
+  p.lut_type = c->lut_type;
+  p.d0 = c->lut.dims[0]; p.d1 = c->lut.dims[1]; p.d2 = c->lut.dims[2]; p.d3 = c->lut.dims[3]; p.d4 = c->lut.dims[4];
+  p.e_min = c->lut.e_min_kev;
+  p.e_scale = static_cast<float>(c->lut.dims[0]) / (c->lut.e_max_kev - c->lut.e_min_kev);
+  p.seed = seed;
+  p.h0 = h_offset;
+  p.n = n_histories;
+  p.sc_n = out->scatter_counts;
+  p.sc_w = out->scatter_weights;
+  p.tr_n = out->true_counts;
+  p.tr_w = out->true_weights;
+  p.stats = out->stats;
+  p.rec = reinterpret_cast<uint32_t*>(out->records);
+  p.rec_stride = out->record_stride;
+  HIP_TRY(sse::launch_transport(p, static_cast<hipStream_t>(stream)), "transport kernel launch");
+  return SSE_OK;
+}
+
+sse_status sse_emission_scale(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, double acq_seconds, double factor,
+                              double* scale) {
+  Phantom* p = get_phantom(c, id);
+  if (!p) return fail(SSE_EINVAL, "unknown phantom id");
+  if (!scale || n_histories == 0 || !std::isfinite(acq_seconds) || !std::isfinite(factor))
+    return fail(SSE_EINVAL, "bad arguments");
+  const double vol_ml = static_cast<double>(p->desc.voxel_mm[0]) * static_cast<double>(p->desc.voxel_mm[1]) *
+                        static_cast<double>(p->desc.voxel_mm[2]) * 1e-3;
+  *scale = p->activity_sum * vol_ml * acq_seconds / static_cast<double>(n_histories) * factor;
+  return SSE_OK;
+}
+
+sse_status sse_apply_sensitivity(sse_ctx* c, const double* W, double scale, float* out, void* stream) {
+  if (!c || !W || !out) return fail(SSE_EINVAL, "null argument");
+  if (!c->d_sens) return fail(SSE_ESTATE, "no sensitivity sinogram loaded");
+  if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  HIP_TRY(sse::launch_apply_sensitivity(post_params(c), W, scale, c->d_sens, c->sens_tof, out,
+                                        static_cast<hipStream_t>(stream)),
+          "sensitivity kernel");
+  return SSE_OK;
+}
+
+sse_status sse_gaussian_smooth(sse_ctx* c, const float* in, float* out, const float sigma_bins[3], float truncate,
+                               void* stream) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  return smooth(c, in, out, sigma_bins, truncate, static_cast<hipStream_t>(stream));
+}
+
+sse_status sse_finalize(sse_ctx* c, const double* W, double scale, const float* sigma_bins, float truncate,
+                        float* out, void* stream) {
+  if (!c || !W || !out) return fail(SSE_EINVAL, "null argument");
+  if (!sigma_bins) return sse_apply_sensitivity(c, W, scale, out, stream);
+  if (!c->d_sens) return fail(SSE_ESTATE, "no sensitivity sinogram loaded");
+  if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const sse::PostParams g = post_params(c);
+  HIP_TRY(sse::launch_scale_to_float(g, W, scale, out, s), "scale kernel");
+  sse_status st = smooth(c, out, out, sigma_bins, truncate, s);
+  if (st != SSE_OK) return st;
+  HIP_TRY(sse::launch_multiply_sens(g, out, c->d_sens, c->sens_tof, out, s), "sensitivity kernel");
+  return SSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/sse.h declares, rejects bad descriptors before
+touching a device, and its host alias table equals the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2509_05047_amd as sse
+import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sse.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sse_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 15
+    lib = sse.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sse.SIGNATURES), set(names) ^ set(sse.SIGNATURES)
+
+
+def test_abi_version():
+    assert sse.lib().sse_abi_version() == 1
+
+
+def test_structure_sizes_match_header_layout():
+    assert C.sizeof(sse.ScannerDesc) == 28
+    assert C.sizeof(sse.SinoDesc) == 24
+    assert C.sizeof(sse.PhysicsDesc) == 40
+    assert C.sizeof(sse.PhantomDesc) == 36
+    assert C.sizeof(sse.LutDesc) == 28
+    assert C.sizeof(sse.Outputs) == 56
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_host_alias_table_equals_oracle(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 3000))
+    act = rng.uniform(0, 3, n).astype(np.float32)
+    act[rng.random(n) < 0.4] = 0.0
+    act[int(rng.integers(0, n))] = 1.0
+    th, al = sse.build_alias_table(act)
+    oth, oal = O.build_alias(act)
+    assert np.array_equal(th, oth) and np.array_equal(al, oal)
+
+
+def test_host_alias_table_equals_oracle_on_clinical_phantom():
+    _, _, act = W.clinical_body()
+    th, al = sse.build_alias_table(act)
+    oth, oal = O.build_alias(act)
+    assert np.array_equal(th, oth) and np.array_equal(al, oal)
+
+
+def test_alias_table_rejects_bad_activity():
+    with pytest.raises(sse.SseError) as e:
+        sse.build_alias_table(np.zeros(5, np.float32))
+    assert e.value.status == sse.EINVAL
+    with pytest.raises(sse.SseError):
+        sse.build_alias_table(np.array([1.0, np.inf], np.float32))
+
+
+def _create(scanner, sino, physics):
+    h = C.c_void_p()
+    sc, sn, ph = sse.scanner_desc(scanner), sse.sino_desc(sino), sse.physics_desc(physics)
+    return sse.lib().sse_create(C.byref(h), 0, C.byref(sc), C.byref(sn), C.byref(ph))
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda s, n, p: setattr(s, "n_crystals", 63),
+    lambda s, n, p: setattr(n, "n_view", 31),
+    lambda s, n, p: setattr(n, "n_plane", 8),
+    lambda s, n, p: setattr(n, "n_rad", 62),
+    lambda s, n, p: setattr(n, "n_rad", 65),
+    lambda s, n, p: setattr(n, "tof_bin_mm", 0.0),
+    lambda s, n, p: p.update(rayleigh_beta=0.0),
+    lambda s, n, p: p.update(e_lo_kev=700.0),
+    lambda s, n, p: p.update(max_interactions=0),
+    lambda s, n, p: p.update(f_compton=-1.0),
+])
+def test_create_rejects_bad_descriptors(mutate):
+    w = W.WORKLOADS["tiny"]
+    s = W.Scanner(**w.scanner.__dict__)
+    n = W.Sinogram(**w.sino.__dict__)
+    p = dict(w.physics)
+    mutate(s, n, p)
+    assert _create(s, n, p) == sse.EINVAL
+    assert sse.lib().sse_last_error() != b""
