@@ -55,7 +55,9 @@ def main():
     ap.add_argument("--workload", default="clinical", choices=["clinical", "large"])
     ap.add_argument("--histories", type=float, default=0, help="override histories per step")
     ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--cpu-histories", type=int, default=3_000_000)
+    ap.add_argument("--cpu-histories", type=int, default=20_000_000)
+    ap.add_argument("--copy-bytes", type=float, default=0,
+                    help="only run a plain device copy of this many bytes 3 times (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -67,6 +69,14 @@ def main():
     import paper_2509_05047_amd as sse
 
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        src = torch.ones(int(args.copy_bytes) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {src.numel() * 4} bytes 3 times")
+        return
     w = W.WORKLOADS[args.workload]
     pdesc, mu, act = W.make_phantom(w)
     lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
@@ -80,7 +90,16 @@ def main():
     ctx.load_lut(lut_desc, lut_store, dtype=lut_dtype)
     ctx.load_sensitivity(sens, has_tof_axis=True)
     del sens
-    out = ctx.new_outputs(trues=False, stats=True)
+    # per-history work units for the cost model, from an instrumented run on
+    # a sample of the same histories (the timed steps run the production
+    # kernel, which collects no statistics)
+    sample = min(n, 100_000_000)
+    probe = ctx.new_outputs(trues=False, stats=True)
+    ctx.simulate(pid, sample, w.seed, probe)
+    torch.cuda.synchronize()
+    stats = sse.stats_dict(probe["stats"])
+    del probe
+    out = ctx.new_outputs(trues=False, stats=False)
     final = torch.empty(ctx.n_bins, dtype=torch.float32, device="cuda")
     scale = ctx.emission_scale(pid, n)
     stream = torch.cuda.current_stream()
@@ -100,14 +119,13 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    out["stats"].zero_()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i)
         log(f"[bench] step {i + 1}/{args.steps} queued")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = sse.stats_dict(out["stats"])
+    scatter_per_step = int(out["scatter_counts"].sum(dtype=torch.int64))
     kernel_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
     ctx.close()
 
@@ -135,7 +153,7 @@ def main():
                                f"{'x'.join(map(str, lut_desc.dims))} {args.lut} LUT",
                    "histories_per_step": n, "lut_dtype": args.lut, "transport": "f32",
                    "accumulation": "f64"},
-        "scatter_coincidences_per_sec": stats["scatter"] / dt,
+        "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
         "transport_kernel_ms": float(np.mean(kernel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS, "traffic": None,

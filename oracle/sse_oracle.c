@@ -84,9 +84,10 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* One random stream: history h, substream s (0 emission, 1 photon A,
- * 2 photon B, 3 coincidence).  Block j has counter (j, h_lo, h_hi, s) and key
- * (seed_lo, seed_hi); the stream's words are the blocks' words in order. */
+/* One random stream: history h, substream s.  Block j has counter
+ * (j, h_lo, h_hi, s) and key (seed_lo, seed_hi); the stream's words are the
+ * blocks' words in order.  A history draws everything from substream 0 (the
+ * samplers' test hooks use substream 1). */
 typedef struct {
   uint32_t key[2];
   uint32_t ctr[4];
@@ -563,18 +564,17 @@ static void fill_photon_rec(orc_photon_rec* pr, const photon_t* o) {
 static void history(const ctx_t* C, uint64_t seed, uint64_t h,
                     uint32_t* sc_n, double* sc_w, uint32_t* tr_n, double* tr_w,
                     uint64_t* st, orc_record* rec) {
-  rng_t r0, r1, r2, r3;
-  rng_init(&r0, seed, h, 0);
-  rng_init(&r1, seed, h, 1);
-  rng_init(&r2, seed, h, 2);
-  rng_init(&r3, seed, h, 3);
+  /* one stream per history, consumed in order: emission, photon A,
+   * photon B, TOF jitter */
+  rng_t r;
+  rng_init(&r, seed, h, 0);
   uint32_t voxel;
   vec3 p, d, dm;
-  emit(C, &r0, &voxel, &p, &d);
+  emit(C, &r, &voxel, &p, &d);
   dm.x = -d.x; dm.y = -d.y; dm.z = -d.z;
   photon_t A, B;
-  transport(C, &r1, p, d, &A, st);
-  transport(C, &r2, p, dm, &B, st);
+  transport(C, &r, p, d, &A, st);
+  transport(C, &r, p, dm, &B, st);
   st[ORC_ST_HISTORIES] += 1;
 
   uint32_t outcome;
@@ -608,7 +608,7 @@ static void history(const ctx_t* C, uint64_t seed, uint64_t h,
     } else {
       /* TOF offset toward the TOF-positive end: half the path difference */
       tau = apos ? (B.path - A.path) * R(0.5) : (A.path - B.path) * R(0.5);
-      if (C->sn->tof_sigma_mm > 0.0f) tau = tau + (real)C->sn->tof_sigma_mm * std_normal(&r3);
+      if (C->sn->tof_sigma_mm > 0.0f) tau = tau + (real)C->sn->tof_sigma_mm * std_normal(&r);
       real xt = tau / (real)C->sn->tof_bin_mm + (real)C->sn->n_tof * R(0.5);
       if (!(xt >= R(0)) || !(xt < (real)C->sn->n_tof)) {
         outcome = ORC_OUT_TOF;
@@ -634,7 +634,7 @@ static void history(const ctx_t* C, uint64_t seed, uint64_t h,
       }
     }
   }
-  st[ORC_ST_RNG_BLOCKS] += r0.blocks + r1.blocks + r2.blocks + r3.blocks;
+  st[ORC_ST_RNG_BLOCKS] += r.blocks;
   if (rec) {
     rec->outcome = outcome | (scattered ? 0x100u : 0u);
     rec->bin_lo = (uint32_t)bin;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +42,8 @@ struct Phantom {
   double activity_sum = 0.0;
   float* d_mu = nullptr;
   uint2* d_alias = nullptr;
+  uint8_t* d_mu8 = nullptr;      // palette indices when the map has <= 256 distinct values
+  float* d_mu_table = nullptr;   // the 256-entry palette (exact values)
 };
 
 }  // namespace
@@ -161,6 +164,38 @@ sse_status upload_alias(const float* act_host, uint64_t n, hipStream_t s, uint2*
   return SSE_OK;
 }
 
+// Attenuation maps with at most 256 distinct values (segmented phantoms)
+// are also stored as one-byte indices into a table of the exact values: the
+// kernel reads the same binary32 numbers from a map a quarter of the size,
+// which stays resident in each XCD's L2.
+sse_status upload_palette(const std::vector<float>& mu, hipStream_t s, Phantom& p) {
+  std::map<uint32_t, uint32_t> index;
+  for (float m : mu) {
+    uint32_t bits;
+    std::memcpy(&bits, &m, 4);
+    if (index.emplace(bits, 0u).second && index.size() > 256) return SSE_OK;  // no palette
+  }
+  std::vector<float> table(256, 0.0f);
+  uint32_t k = 0;
+  for (auto& kv : index) {
+    kv.second = k;
+    std::memcpy(&table[k], &kv.first, 4);
+    ++k;
+  }
+  std::vector<uint8_t> idx(mu.size());
+  for (size_t i = 0; i < mu.size(); ++i) {
+    uint32_t bits;
+    std::memcpy(&bits, &mu[i], 4);
+    idx[i] = static_cast<uint8_t>(index[bits]);
+  }
+  HIP_TRY(hipMalloc(&p.d_mu8, mu.size()), "allocate palette map");
+  HIP_TRY(hipMalloc(&p.d_mu_table, 256 * sizeof(float)), "allocate palette");
+  HIP_TRY(hipMemcpyAsync(p.d_mu8, idx.data(), mu.size(), hipMemcpyHostToDevice, s), "upload palette map");
+  HIP_TRY(hipMemcpyAsync(p.d_mu_table, table.data(), 256 * sizeof(float), hipMemcpyHostToDevice, s), "upload palette");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise palette upload");
+  return SSE_OK;
+}
+
 Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
   if (!c || id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1].used) return nullptr;
   return &c->phantoms[id - 1];
@@ -259,11 +294,13 @@ sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner
 
 sse_status sse_destroy(sse_ctx* c) {
   if (!c) return SSE_OK;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
   for (auto& p : c->phantoms) {
-    if (p.d_mu) release(p.d_mu);
-    if (p.d_alias) release(p.d_alias);
+    release(p.d_mu);
+    release(p.d_alias);
+    release(p.d_mu8);
+    release(p.d_mu_table);
   }
   if (c->d_lut) release(c->d_lut);
   if (c->d_sens) release(c->d_sens);
@@ -320,9 +357,12 @@ sse_status sse_load_phantom(sse_ctx* c, const sse_phantom_desc* d, const float* 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = hip_fail(e, "upload attenuation map");
   }
+  if (st == SSE_OK) st = upload_palette(hmu, s, p);
   if (st != SSE_OK) {
     release(p.d_mu);
     release(p.d_alias);
+    release(p.d_mu8);
+    release(p.d_mu_table);
     return st;
   }
   for (size_t i = 0; i < c->phantoms.size(); ++i)
@@ -355,6 +395,8 @@ sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {
   HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
   release(p->d_mu);
   release(p->d_alias);
+  release(p->d_mu8);
+  release(p->d_mu_table);
   *p = Phantom();
   return SSE_OK;
 }
@@ -462,9 +504,13 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   sse::TransportParams p{};
   const sse_phantom_desc& d = ph->desc;
   p.mu = ph->d_mu;
+  p.mu8 = ph->d_mu8;
+  p.mu_table = ph->d_mu_table;
   p.alias = ph->d_alias;
   p.nvox = ph->nvox;
   p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.inv_nx = 1.0f / static_cast<float>(d.nx);
+  p.inv_nxy = 1.0f / static_cast<float>(d.nx * d.ny);
   p.vx = d.voxel_mm[0]; p.vy = d.voxel_mm[1]; p.vz = d.voxel_mm[2];
   p.lox = d.lo_mm[0]; p.loy = d.lo_mm[1]; p.loz = d.lo_mm[2];
   p.hix = p.lox + static_cast<float>(d.nx) * p.vx;

@@ -23,10 +23,13 @@ struct ECoef {
 // Everything one transport launch reads; passed by value as the kernel argument.
 struct TransportParams {
   // phantom
-  const float* mu;          // mu at 511 keV, [nz][ny][nx]
+  const float* mu;          // mu at 511 keV, [nz][ny][nx] (binary32 map)
+  const uint8_t* mu8;       // or palette indices (NULL if not used)
+  const float* mu_table;    // 256-entry palette of exact mu values (NULL if not used)
   const uint2* alias;       // (threshold, alias) per column
   uint64_t nvox;
   int nx, ny, nz;
+  float inv_nx, inv_nxy;   // binary32 reciprocals of nx and nx * ny
   float lox, loy, loz, hix, hiy, hiz;
   float ivx, ivy, ivz, vx, vy, vz;
   float mu_maj;             // Woodcock majorant at 511 keV

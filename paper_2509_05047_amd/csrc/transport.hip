@@ -9,11 +9,21 @@
 // sinogram bin with count 1 and weight p_A p_B (Methods, "Scatter simulator
 // description" and "Photon detection probability LUT").
 //
+// Execution model: a persistent grid; every wavefront owns a contiguous range
+// of histories and every lane runs a small state machine
+//     EMIT -> TRACK (photon A) -> FINISH -> TRACK (photon B) -> FINISH -> EMIT
+// advancing to its next event (a real interaction or the end of the photon)
+// per loop iteration.  A lane whose history ends takes the next history of
+// its wave immediately, so lanes never idle while the slowest lane of the
+// wave finishes, and each expensive branch runs once per iteration for all
+// lanes that need it.
+//
 // Numerics: binary32 transport with IEEE-rounded + - * / sqrt (no
 // contraction); ln, atan2 and the cross-section formula in binary64, rounded
-// once where they feed binary32 values.  Random numbers are Philox4x32-10
-// streams keyed by (seed), countered by (block, history, substream), so a
-// history's result does not depend on the launch geometry.
+// once where they feed binary32 values.  Random numbers: one Philox4x32-10
+// stream per history, keyed by the seed and countered by (block, history),
+// consumed in order by the emission, photon A, photon B and the TOF jitter,
+// so a history's result does not depend on the launch geometry.
 #include "internal.h"
 
 namespace sse {
@@ -22,6 +32,14 @@ namespace {
 constexpr double kPi = 3.141592653589793;
 constexpr double kTwoPi = 6.283185307179586;
 constexpr double kHalfPi = 1.5707963267948966;
+
+enum Phase { kEmit = 0, kTrack = 1, kInteract = 2, kFinish = 3, kDone = 4 };
+enum Fate { kDetected = 0, kAbsorbed = 1, kKilled = 2, kCapped = 3, kAxial = 4, kEscaped = 5 };
+enum Stat {
+  kStHist = 0, kStSteps, kStReal, kStCompton, kStRayleigh, kStAbsorbed, kStKilled, kStCapped, kStEscaped,
+  kStDetected, kStInWindow, kStScatter, kStTrue, kStRejWindow, kStRejSame, kStRejRing, kStRejRadial,
+  kStRejTof, kStRngBlocks
+};
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11)
@@ -44,54 +62,77 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
   o0 = c0; o1 = c1; o2 = c2; o3 = c3;
 }
 
-// A random stream of 32-bit words: the words of blocks 0, 1, 2, ... with
-// counter (block, h_lo, h_hi, substream).  The four words of the current
-// block are shifted out in order (no dynamically indexed registers).
-struct Stream {
-  uint32_t k0, k1, hlo, hhi, sub, blk;
-  uint32_t w0, w1, w2, w3;
-  uint32_t left;
+// Statistics: at each counting site the lowest active lane adds the
+// population count of the wave's ballot to a per-block LDS counter (a
+// wave-uniform accumulator cannot live in a register that divergent lanes
+// update separately).  The predicate is evaluated whether or not statistics
+// are collected.
+#define SSE_COUNT(idx, pred)                                                          \
+  do {                                                                                \
+    const bool v_ = (pred);                                                           \
+    if (kInstr && p.stats) {                                                          \
+      const uint64_t m_ = __ballot(static_cast<int>(v_));                            \
+      if (m_ && lane == static_cast<uint32_t>(__builtin_ctzll(__builtin_amdgcn_read_exec()))) \
+        atomicAdd(&s_stats[idx], static_cast<unsigned long long>(__popcll(m_)));      \
+    }                                                                                 \
+  } while (0)
 
-  __device__ __forceinline__ void init(uint64_t seed, uint64_t h, uint32_t s) {
-    k0 = static_cast<uint32_t>(seed);
-    k1 = static_cast<uint32_t>(seed >> 32);
+// A history's random stream: the 32-bit words of Philox blocks 0, 1, 2, ...
+// with counter (block, h_lo, h_hi, 0).  Up to eight words are buffered in a
+// shift register w0..w7 (w0 next).  refill() appends the next block; a lane
+// may refill whenever it holds at most four words, so a refill that one lane
+// needs is shared by every lane of the wave with room (Philox then runs
+// mostly converged instead of once per lane at scattered points).  No
+// dynamically indexed registers.
+struct Rng {
+  uint32_t hlo, hhi, blk, left;
+  uint32_t w0, w1, w2, w3, w4, w5, w6, w7;
+
+  __device__ __forceinline__ void start(uint64_t h) {
     hlo = static_cast<uint32_t>(h);
     hhi = static_cast<uint32_t>(h >> 32);
-    sub = s;
     blk = 0;
     left = 0;
   }
-  __device__ __forceinline__ uint32_t next() {
-    if (left == 0) {
-      philox(blk, hlo, hhi, sub, k0, k1, w0, w1, w2, w3);
-      ++blk;
-      left = 4;
-    }
+  __device__ __forceinline__ void refill(uint32_t k0, uint32_t k1) {
+    uint32_t b0, b1, b2, b3;
+    philox(blk, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
+    ++blk;
+    const uint32_t L = left;  // 0 .. 4: the new words go to slots L .. L+3
+    w0 = L == 0 ? b0 : w0;
+    w1 = L == 0 ? b1 : (L == 1 ? b0 : w1);
+    w2 = L == 0 ? b2 : (L == 1 ? b1 : (L == 2 ? b0 : w2));
+    w3 = L == 0 ? b3 : (L == 1 ? b2 : (L == 2 ? b1 : (L == 3 ? b0 : w3)));
+    w4 = L == 1 ? b3 : (L == 2 ? b2 : (L == 3 ? b1 : (L == 4 ? b0 : w4)));
+    w5 = L == 2 ? b3 : (L == 3 ? b2 : (L == 4 ? b1 : w5));
+    w6 = L == 3 ? b3 : (L == 4 ? b2 : w6);
+    w7 = L == 4 ? b3 : w7;
+    left = L + 4;
+  }
+  __device__ __forceinline__ uint32_t take() {
     const uint32_t r = w0;
-    w0 = w1;
-    w1 = w2;
-    w2 = w3;
+    w0 = w1; w1 = w2; w2 = w3; w3 = w4; w4 = w5; w5 = w6; w6 = w7;
     --left;
     return r;
   }
   // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
   __device__ __forceinline__ float uniform() {
-    return static_cast<float>((next() >> 8) | 1u) * 5.9604644775390625e-08f;
+    return static_cast<float>((take() >> 8) | 1u) * 5.9604644775390625e-08f;
   }
 };
 
-__device__ __forceinline__ float neg_log(float u) { return static_cast<float>(-log(static_cast<double>(u))); }
+// Make sure every active lane holds at least k (<= 4) words: if any lane is
+// short, all active lanes with room generate one block together.
+#define RNG_NEED(k)                                  \
+  do {                                               \
+    if (__any(r.left < (k))) {                       \
+      const bool g_ = r.left <= 4u;                  \
+      if (g_) r.refill(k0, k1);                      \
+      SSE_COUNT(kStRngBlocks, g_);                   \
+    }                                                \
+  } while (0)
 
-__device__ float normal_polar(Stream& r) {
-  for (int i = 0; i < kMaxTries; ++i) {
-    const float a = 2.0f * r.uniform() - 1.0f;
-    const float b = 2.0f * r.uniform() - 1.0f;
-    const float s = a * a + b * b;
-    if (s < 1.0f)
-      return a * static_cast<float>(sqrt(-2.0 * log(static_cast<double>(s)) / static_cast<double>(s)));
-  }
-  return 0.0f;
-}
+__device__ __forceinline__ float neg_log(float u) { return static_cast<float>(-log(static_cast<double>(u))); }
 
 // ---------------------------------------------------------------------------
 // physics
@@ -107,60 +148,6 @@ __device__ void energy_coefficients(ECoef& c, float E, const TransportParams& p)
   c.cC = static_cast<float>(fc);
   c.cCR = static_cast<float>(fc + fr);
   c.inv_maj = 1.0f / (p.mu_maj * c.g);
-}
-
-// Kahn (1954) rejection sampling of x = E/E' for Klein-Nishina scattering.
-__device__ bool sample_compton(Stream& r, float alpha, float& x_out) {
-  const float twoa = 2.0f * alpha;
-  const float b1 = 1.0f + twoa;
-  const float b2 = 9.0f + twoa;
-  for (int i = 0; i < kMaxTries; ++i) {
-    const float r1 = r.uniform();
-    const float r2 = r.uniform();
-    const float r3 = r.uniform();
-    if (r1 * b2 <= b1) {
-      const float x = 1.0f + twoa * r2;
-      if (r3 * (x * x) <= 4.0f * (x - 1.0f)) { x_out = x; return true; }
-    } else {
-      const float x = b1 / (1.0f + twoa * r2);
-      const float c = 1.0f + (1.0f - x) / alpha;
-      if (2.0f * r3 <= c * c + 1.0f / x) { x_out = x; return true; }
-    }
-  }
-  return false;
-}
-
-// Rayleigh polar angle: (1 + beta' t)^-2 by inversion in t = 1 - cos, then
-// the Thomson factor (1 + cos^2)/2 by rejection.
-__device__ bool sample_rayleigh(Stream& r, float alpha, float beta, float& cos_out) {
-  const float bp = beta * (alpha * alpha);
-  const float cc = (2.0f * bp) / (1.0f + 2.0f * bp);
-  for (int i = 0; i < kMaxTries; ++i) {
-    const float r1 = r.uniform();
-    const float r2 = r.uniform();
-    const float q = r1 * cc;
-    const float t = q / ((1.0f - q) * bp);
-    float c = 1.0f - t;
-    if (c < -1.0f) c = -1.0f;
-    if (2.0f * r2 <= 1.0f + c * c) { cos_out = c; return true; }
-  }
-  return false;
-}
-
-// (cos phi, sin phi) of a uniform azimuth from a point in the unit disk.
-__device__ void sample_azimuth(Stream& r, float& cp, float& sp) {
-  for (int i = 0; i < kMaxTries; ++i) {
-    const float a = 2.0f * r.uniform() - 1.0f;
-    const float b = 2.0f * r.uniform() - 1.0f;
-    const float s = a * a + b * b;
-    if (s < 1.0f) {
-      cp = (a * a - b * b) / s;
-      sp = (2.0f * a * b) / s;
-      return;
-    }
-  }
-  cp = 1.0f;
-  sp = 0.0f;
 }
 
 __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct, float cp, float sp) {
@@ -223,300 +210,493 @@ __device__ __forceinline__ float lut_value(const TransportParams& p, uint32_t i)
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-enum Fate { kDetected = 0, kAbsorbed = 1, kKilled = 2, kCapped = 3, kAxial = 4 };
-
-struct Counters {
-  uint32_t v[kStatCount];
-};
-
-struct Single {
-  float hx, hy, hz, dx, dy, dz, E, Edet, path;
-  int fate, nC, nR;
-  uint32_t steps;
-};
-
-// Track one photon from (px,py,pz) along (dx,dy,dz) at 511 keV to the cylinder.
-__device__ void track(const TransportParams& p, Stream& r, float px, float py, float pz, float dx, float dy,
-                      float dz, Single& o, Counters& cnt) {
-  ECoef ec = p.e511;
-  float len = 0.0f;
-  float t = 0.0f;
-  float texit = box_exit(p, px, py, pz, dx, dy, dz);
-  int nC = 0, nR = 0, nint = 0;
-  uint32_t steps = 0;
-  int fate = -1;
-  for (;;) {
-    if (steps >= static_cast<uint32_t>(kMaxSteps)) { fate = kCapped; break; }
-    ++steps;
-    const float s = neg_log(r.uniform()) * ec.inv_maj;
-    t = t + s;
-    if (!(t < texit)) break;
-    const float qx = px + t * dx;
-    const float qy = py + t * dy;
-    const float qz = pz + t * dz;
-    const float mu = p.mu[voxel_at(p, qx, qy, qz)];
-    if (!(r.uniform() * p.mu_maj < mu)) continue;  // null collision
-    ++cnt.v[2];
-    px = qx; py = qy; pz = qz;
-    len = len + t;
-    t = 0.0f;
-    if (++nint > p.max_int) { fate = kCapped; break; }
-    const float ug = r.uniform() * ec.g;
-    float ct;
-    if (ug < ec.cC) {
-      float x;
-      if (!sample_compton(r, ec.alpha, x)) { fate = kAbsorbed; break; }
-      const float e2 = ec.E / x;
-      ct = 1.0f - (x - 1.0f) / ec.alpha;
-      ct = fminf(fmaxf(ct, -1.0f), 1.0f);
-      ++nC;
-      ++cnt.v[3];
-      if (e2 < p.e_kill) { fate = kKilled; break; }
-      energy_coefficients(ec, e2, p);
-    } else if (ug < ec.cCR) {
-      if (!sample_rayleigh(r, ec.alpha, p.rayleigh_beta, ct)) { fate = kAbsorbed; break; }
-      ++nR;
-      ++cnt.v[4];
-    } else {
-      fate = kAbsorbed;
-      break;
-    }
-    float cp, sp;
-    sample_azimuth(r, cp, sp);
-    rotate(dx, dy, dz, ct, cp, sp);
-    texit = box_exit(p, px, py, pz, dx, dy, dz);
-  }
-  cnt.v[1] += steps;
-  o.steps = steps;
-  o.nC = nC;
-  o.nR = nR;
-  o.E = ec.E;
-  o.Edet = ec.E;
-  o.path = 0.0f;
-  o.hx = o.hy = o.hz = 0.0f;
-  o.dx = dx; o.dy = dy; o.dz = dz;
-  if (fate >= 0) {
-    o.fate = fate;
-    if (fate == kAbsorbed) ++cnt.v[5];
-    else if (fate == kKilled) ++cnt.v[6];
-    else ++cnt.v[7];
-    return;
-  }
-  ++cnt.v[8];
-  // crossing of x^2 + y^2 = R^2 ahead of the last point
-  const float a = dx * dx + dy * dy;
-  if (!(a > 0.0f)) { o.fate = kAxial; return; }
-  const float b = px * dx + py * dy;
-  const float c = px * px + py * py - p.rr;
-  const float disc = b * b - a * c;
-  const float sq = sqrtf(disc);
-  const float tc = (b > 0.0f) ? (-c) / (b + sq) : (sq - b) / a;
-  const float hz = pz + tc * dz;
-  if (!(hz >= -p.half_len && hz < p.half_len)) { o.fate = kAxial; return; }
-  o.fate = kDetected;
-  o.hx = px + tc * dx;
-  o.hy = py + tc * dy;
-  o.hz = hz;
-  o.path = len + tc;
-  ++cnt.v[9];
-  if (p.e_fwhm > 0.0f) {
-    const float nrm = normal_polar(r);
-    const float sig = (p.e_fwhm / 2.35482f) * sqrtf(kMec2 / ec.E);
-    o.Edet = ec.E * (1.0f + sig * nrm);
-  }
-}
-
-// Crystal, ring and flat LUT index of a detected single.
-__device__ void index_single(const TransportParams& p, const Single& o, int& crystal, int& ring, uint32_t& lut) {
-  double phi = atan2(static_cast<double>(o.hy), static_cast<double>(o.hx));
+// Crystal, ring and flat LUT index of a single detected at (hx, hy, hz) with
+// direction (dx, dy, dz) and energy E.
+__device__ void index_single(const TransportParams& p, float hx_, float hy_, float hz, float dx, float dy, float dz,
+                             float E, int& crystal, int& ring, uint32_t& lut) {
+  double phi = atan2(static_cast<double>(hy_), static_cast<double>(hx_));
   if (phi < 0.0) phi += kTwoPi;
   const double fc = floor(phi * static_cast<double>(p.n_crystals) / kTwoPi);
   const int c = fc >= static_cast<double>(p.n_crystals) ? p.n_crystals - 1 : (fc < 0.0 ? 0 : static_cast<int>(fc));
-  const int rg = clamp_floor((o.hz + p.half_len) / p.pitch, p.n_rings);
+  const int rg = clamp_floor((hz + p.half_len) / p.pitch, p.n_rings);
   crystal = c;
   ring = rg;
-  const int ie = clamp_floor((o.E - p.e_min) * p.e_scale, p.d0);
-  const double hx = static_cast<double>(o.hx), hy = static_cast<double>(o.hy);
+  const int ie = clamp_floor((E - p.e_min) * p.e_scale, p.d0);
+  const double hx = static_cast<double>(hx_), hy = static_cast<double>(hy_);
   const double rho = sqrt(hx * hx + hy * hy);
-  const double dr = (hx * static_cast<double>(o.dx) + hy * static_cast<double>(o.dy)) / rho;
-  const double tt = (hx * static_cast<double>(o.dy) - hy * static_cast<double>(o.dx)) / rho;
+  const double dr = (hx * static_cast<double>(dx) + hy * static_cast<double>(dy)) / rho;
+  const double tt = (hx * static_cast<double>(dy) - hy * static_cast<double>(dx)) / rho;
   const int it = angle_bin(atan2(tt, dr), p.d1);
-  const int ia = angle_bin(atan2(static_cast<double>(o.dz), dr), p.d2);
+  const int ia = angle_bin(atan2(static_cast<double>(dz), dr), p.d2);
   const int ct = ((c % p.cmod) * p.d3) / p.cmod;
   const int ca = ((rg % p.rblk) * p.d4) / p.rblk;
   lut = static_cast<uint32_t>((((ie * p.d1 + it) * p.d2 + ia) * p.d3 + ct) * p.d4 + ca);
 }
 
-__device__ void write_single(uint32_t* w, const Single& o, bool inwin, int c, int rg, uint32_t lut) {
-  w[0] = __float_as_uint(o.hx);
-  w[1] = __float_as_uint(o.hy);
-  w[2] = __float_as_uint(o.hz);
-  w[3] = __float_as_uint(o.dx);
-  w[4] = __float_as_uint(o.dy);
-  w[5] = __float_as_uint(o.dz);
-  w[6] = __float_as_uint(o.E);
-  w[7] = __float_as_uint(o.Edet);
-  w[8] = __float_as_uint(o.path);
-  w[9] = inwin ? (static_cast<uint32_t>(c) | (static_cast<uint32_t>(rg) << 16)) : 0xffffffffu;
-  w[10] = inwin ? lut : 0xffffffffu;
-  w[11] = static_cast<uint32_t>(o.nC) | (static_cast<uint32_t>(o.nR) << 8) | (static_cast<uint32_t>(o.fate) << 16);
+// q = v / d for v < 2^24 and d >= 1: binary32 reciprocal estimate (off by at
+// most one) and one integer correction.
+__device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) {
+  uint32_t q = static_cast<uint32_t>(static_cast<float>(v) * inv_d);
+  const int32_t rem = static_cast<int32_t>(v) - static_cast<int32_t>(q * d);
+  if (rem < 0) --q;
+  else if (rem >= static_cast<int32_t>(d)) ++q;
+  return q;
 }
 
-__device__ void simulate_history(const TransportParams& p, uint64_t h, Counters& cnt) {
-  Stream rs;
-  rs.init(p.seed, h, 0);
-  // emission voxel: 64-bit multiply-shift column, 32-bit alias decision
-  const uint64_t lo = rs.next();
-  const uint64_t hi = rs.next();
-  const uint64_t col = __umul64hi((hi << 32) | lo, p.nvox);
-  const uint32_t x1 = rs.next();
-  const uint2 al = p.alias[col];
-  const uint32_t v = (x1 < al.x) ? static_cast<uint32_t>(col) : al.y;
-  const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
-  const uint32_t ix = v % nx, iy = (v / nx) % ny, iz = v / (nx * ny);
-  const float ux = rs.uniform();
-  const float uy = rs.uniform();
-  const float uz = rs.uniform();
-  const float px = p.lox + (static_cast<float>(ix) + ux) * p.vx;
-  const float py = p.loy + (static_cast<float>(iy) + uy) * p.vy;
-  const float pz = p.loz + (static_cast<float>(iz) + uz) * p.vz;
-  // isotropic direction (Marsaglia 1972)
-  float dx = 0.0f, dy = 0.0f, dz = 1.0f;
-  for (int i = 0; i < kMaxTries; ++i) {
-    const float a = 2.0f * rs.uniform() - 1.0f;
-    const float b = 2.0f * rs.uniform() - 1.0f;
-    const float s = a * a + b * b;
-    if (s < 1.0f) {
-      const float q = 2.0f * sqrtf(1.0f - s);
-      dx = a * q;
-      dy = b * q;
-      dz = 1.0f - 2.0f * s;
-      break;
-    }
-  }
-  Single A, B;
-  Stream r1;
-  r1.init(p.seed, h, 1);
-  track(p, r1, px, py, pz, dx, dy, dz, A, cnt);
-  Stream r2;
-  r2.init(p.seed, h, 2);
-  track(p, r2, px, py, pz, -dx, -dy, -dz, B, cnt);
-  ++cnt.v[0];
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+// kInstr = true: the instrumented instantiation (statistics counters and
+// per-history records); false: the production path, with neither.
+template <bool kInstr>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_kernel(TransportParams p) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  const uint64_t per = p.n / nwaves, rem = p.n % nwaves;
+  uint64_t next = p.h0 + wave * per + (wave < rem ? wave : rem);
+  const uint64_t end = next + per + (wave < rem ? 1 : 0);
+  const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
+  const uint64_t below = (1ull << lane) - 1ull;
 
-  const bool winA = A.fate == kDetected && A.Edet >= p.e_lo && A.Edet <= p.e_hi;
-  const bool winB = B.fate == kDetected && B.Edet >= p.e_lo && B.Edet <= p.e_hi;
-  int cA = -1, rA = -1, cB = -1, rB = -1;
-  uint32_t lA = 0xffffffffu, lB = 0xffffffffu;
-  if (winA) { index_single(p, A, cA, rA, lA); ++cnt.v[10]; }
-  if (winB) { index_single(p, B, cB, rB, lB); ++cnt.v[10]; }
-  const bool scattered = (A.nC + A.nR + B.nC + B.nR) > 0;
-  uint32_t outcome;
-  uint64_t bin = ~0ull;
-  float w = 0.0f, tau = 0.0f;
-  Stream r3;
-  r3.init(p.seed, h, 3);
-  if (A.fate != kDetected || B.fate != kDetected) {
-    outcome = 2;
-  } else if (!winA || !winB) {
-    outcome = 3;
-    ++cnt.v[13];
-  } else if (cA == cB) {
-    outcome = 4;
-    ++cnt.v[14];
-  } else if (p.max_ring_diff >= 0 && abs(rA - rB) > p.max_ring_diff) {
-    outcome = 5;
-    ++cnt.v[15];
-  } else {
-    const int n = p.n_crystals;
-    int k = cA + cB + 1;
-    int rho = n / 2 - abs(cA - cB);
-    if (k >= n) { k -= n; rho = -rho; }
-    const int view = k >> 1;
-    int m = (2 * cA + 1 - k) % (2 * n);
-    if (m < 0) m += 2 * n;
-    const bool a_pos = m > 0 && m < n;
-    const int half = (p.n_rad - 1) / 2;
-    if (abs(rho) > half) {
-      outcome = 6;
-      ++cnt.v[16];
-    } else {
-      tau = a_pos ? (B.path - A.path) * 0.5f : (A.path - B.path) * 0.5f;
-      if (p.tof_sigma > 0.0f) tau = tau + p.tof_sigma * normal_polar(r3);
-      const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
-      if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
-        outcome = 7;
-        ++cnt.v[17];
-      } else {
-        const uint64_t tof = static_cast<uint64_t>(floorf(xt));
-        const uint64_t plane = static_cast<uint64_t>(rA + rB);
-        bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
-               static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) + static_cast<uint64_t>(rho + half);
-        w = lut_value(p, lA) * lut_value(p, lB);
-        if (scattered) {
-          outcome = 0;
-          ++cnt.v[11];
-          atomicAdd(p.sc_n + bin, 1u);
-          unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
+  __shared__ unsigned long long s_stats[kStatCount];
+  __shared__ float s_mu_table[256];
+  if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
+  if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
+  __syncthreads();
+
+  int phase = kEmit;
+  int side = 0;                       // 0 photon A, 1 photon B
+  uint64_t h = 0;
+  uint32_t* rec = nullptr;            // this history's record, if sampled
+  float ex = 0.f, ey = 0.f, ez = 0.f, edx = 0.f, edy = 0.f, edz = 0.f;  // emission point, direction of A
+  // photon A summary
+  uint32_t a_cr = 0, a_lut = 0, a_steps = 0;
+  float a_path = 0.f;
+  bool a_det = false, a_win = false, a_scat = false;
+  // photon state
+  float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, texit = 0.f, len = 0.f;
+  ECoef ec = p.e511;
+  int nC = 0, nR = 0, nint = 0, fate = kEscaped;
+  uint32_t steps = 0;
+  Rng r;
+  r.start(0);
+  r.w0 = r.w1 = r.w2 = r.w3 = r.w4 = r.w5 = r.w6 = r.w7 = 0;
+
+  // Standard normal by Marsaglia's polar method from the history's stream.
+  auto polar_normal = [&]() -> float {
+    for (int i = 0; i < kMaxTries; ++i) {
+      RNG_NEED(2u);
+      const float a = 2.0f * r.uniform() - 1.0f;
+      const float b = 2.0f * r.uniform() - 1.0f;
+      const float s = a * a + b * b;
+      if (s < 1.0f) return a * static_cast<float>(sqrt(-2.0 * log(static_cast<double>(s)) / static_cast<double>(s)));
+    }
+    return 0.0f;
+  };
+
+  for (;;) {
+    // ---------------- take new histories ---------------------------------
+    const uint64_t needmask = __ballot(phase == kEmit);
+    bool emitting = false;
+    if (needmask) {
+      if (phase == kEmit) {
+        const uint64_t hh = next + __popcll(needmask & below);
+        if (hh < end) {
+          h = hh;
+          emitting = true;
+          r.start(h);
+          rec = nullptr;
+          if (kInstr && p.rec) {
+            const uint64_t off = h - p.h0;
+            if (off % p.rec_stride == 0) rec = p.rec + (off / p.rec_stride) * kRecordWords;
+          }
         } else {
-          outcome = 1;
-          ++cnt.v[12];
-          if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
-          if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
+          phase = kDone;
+        }
+      }
+      next += __popcll(needmask);
+    }
+    if (__all(phase == kDone)) break;
+    // Converged top-up: every live lane ends with at least five buffered
+    // words (a new history gets eight, enough for its emission).
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (__any(phase != kDone && r.left <= 4u)) {
+        const bool g = phase != kDone && r.left <= 4u;
+        if (g) r.refill(k0, k1);
+        SSE_COUNT(kStRngBlocks, g);
+      }
+    }
+
+    // ---------------- emission --------------------------------------------
+    if (emitting) {
+      // voxel: 64-bit multiply-shift column, 32-bit alias decision
+      RNG_NEED(3u);
+      const uint64_t lo = r.take();
+      const uint64_t hi = r.take();
+      const uint64_t col = __umul64hi((hi << 32) | lo, p.nvox);
+      const uint32_t x1 = r.take();
+      const uint2 al = p.alias[col];
+      const uint32_t v = (x1 < al.x) ? static_cast<uint32_t>(col) : al.y;
+      const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
+      uint32_t ix, iy, iz;
+      if (p.nvox < (1ull << 24)) {
+        const uint32_t q = udiv24(v, nx, p.inv_nx);
+        iz = udiv24(v, nx * ny, p.inv_nxy);
+        ix = v - q * nx;
+        iy = q - iz * ny;
+      } else {
+        ix = v % nx;
+        iy = (v / nx) % ny;
+        iz = v / (nx * ny);
+      }
+      RNG_NEED(3u);
+      const float ux = r.uniform();
+      const float uy = r.uniform();
+      const float uz = r.uniform();
+      ex = p.lox + (static_cast<float>(ix) + ux) * p.vx;
+      ey = p.loy + (static_cast<float>(iy) + uy) * p.vy;
+      ez = p.loz + (static_cast<float>(iz) + uz) * p.vz;
+      // isotropic direction (Marsaglia 1972)
+      edx = 0.0f; edy = 0.0f; edz = 1.0f;
+      for (int i = 0; i < kMaxTries; ++i) {
+        RNG_NEED(2u);
+        const float a = 2.0f * r.uniform() - 1.0f;
+        const float b = 2.0f * r.uniform() - 1.0f;
+        const float s = a * a + b * b;
+        if (s < 1.0f) {
+          const float q = 2.0f * sqrtf(1.0f - s);
+          edx = a * q;
+          edy = b * q;
+          edz = 1.0f - 2.0f * s;
+          break;
+        }
+      }
+      if (kInstr && rec) rec[3] = v;
+      // photon A
+      side = 0;
+      px = ex; py = ey; pz = ez;
+      dx = edx; dy = edy; dz = edz;
+      t = 0.0f; len = 0.0f;
+      texit = box_exit(p, px, py, pz, dx, dy, dz);
+      ec = p.e511;
+      nC = nR = nint = 0;
+      steps = 0;
+      fate = kEscaped;
+      phase = kTrack;
+    }
+
+    // ---------------- Woodcock steps until every lane has an event ---------
+    // The step is cheap; the expensive branches below (interaction, photon
+    // end, emission) then run once per outer iteration for all lanes that
+    // need them, instead of once per step.
+    while (__any(phase == kTrack)) {
+      if (__any(phase == kTrack && r.left < 2u)) {
+        const bool g = phase != kDone && r.left <= 4u;
+        if (g) r.refill(k0, k1);
+        SSE_COUNT(kStRngBlocks, g);
+      }
+      if (phase == kTrack) {
+        if (steps >= static_cast<uint32_t>(kMaxSteps)) {
+          fate = kCapped;
+          phase = kFinish;
+        } else {
+          ++steps;
+          SSE_COUNT(kStSteps, true);
+          const float s = neg_log(r.uniform()) * ec.inv_maj;
+          t = t + s;
+          if (!(t < texit)) {
+            phase = kFinish;  // leaves the voxel box: straight to the cylinder
+          } else {
+            const float qx = px + t * dx;
+            const float qy = py + t * dy;
+            const float qz = pz + t * dz;
+            const uint32_t vox = voxel_at(p, qx, qy, qz);
+            const float mu = p.mu8 ? s_mu_table[p.mu8[vox]] : p.mu[vox];
+            const bool real = r.uniform() * p.mu_maj < mu;
+            SSE_COUNT(kStReal, real);
+            if (real) {
+              px = qx; py = qy; pz = qz;
+              len = len + t;
+              t = 0.0f;
+              phase = kInteract;
+            }
+          }
         }
       }
     }
-  }
-  cnt.v[18] += rs.blk + r1.blk + r2.blk + r3.blk;
-  if (p.rec) {
-    const uint64_t off = h - p.h0;
-    if (off % p.rec_stride == 0) {
-      uint32_t* wr = p.rec + (off / p.rec_stride) * kRecordWords;
-      wr[0] = outcome | (scattered ? 0x100u : 0u);
-      wr[1] = static_cast<uint32_t>(bin);
-      wr[2] = static_cast<uint32_t>(bin >> 32);
-      wr[3] = v;
-      wr[4] = __float_as_uint(w);
-      wr[5] = __float_as_uint(tau);
-      wr[6] = A.steps + B.steps;
-      wr[7] = 0u;
-      write_single(wr + 8, A, winA, cA, rA, lA);
-      write_single(wr + 20, B, winB, cB, rB, lB);
+
+    // ---------------- real interactions ----------------------------------
+    if (phase == kInteract) {
+      if (++nint > p.max_int) {
+        fate = kCapped;
+        phase = kFinish;
+      } else {
+        RNG_NEED(4u);
+        const float ug = r.uniform() * ec.g;
+        float ct = 1.0f;
+        bool alive = true;
+        if (ug < ec.cC) {
+          // Klein-Nishina by Kahn's rejection method: x = E / E'
+          const float twoa = 2.0f * ec.alpha;
+          const float b1 = 1.0f + twoa;
+          const float b2 = 9.0f + twoa;
+          float x = 0.0f;
+          bool ok = false;
+          for (int i = 0; i < kMaxTries && !ok; ++i) {
+            RNG_NEED(3u);
+            const float r1 = r.uniform();
+            const float r2 = r.uniform();
+            const float r3 = r.uniform();
+            if (r1 * b2 <= b1) {
+              const float xx = 1.0f + twoa * r2;
+              if (r3 * (xx * xx) <= 4.0f * (xx - 1.0f)) { x = xx; ok = true; }
+            } else {
+              const float xx = b1 / (1.0f + twoa * r2);
+              const float c = 1.0f + (1.0f - xx) / ec.alpha;
+              if (2.0f * r3 <= c * c + 1.0f / xx) { x = xx; ok = true; }
+            }
+          }
+          if (!ok) {
+            fate = kAbsorbed;
+            alive = false;
+          } else {
+            SSE_COUNT(kStCompton, true);
+            const float e2 = ec.E / x;
+            ct = 1.0f - (x - 1.0f) / ec.alpha;
+            ct = fminf(fmaxf(ct, -1.0f), 1.0f);
+            ++nC;
+            if (e2 < p.e_kill) {
+              fate = kKilled;
+              alive = false;
+            } else {
+              energy_coefficients(ec, e2, p);
+            }
+          }
+        } else if (ug < ec.cCR) {
+          // Rayleigh: form factor by inversion, Thomson factor by rejection
+          const float bp = p.rayleigh_beta * (ec.alpha * ec.alpha);
+          const float cc = (2.0f * bp) / (1.0f + 2.0f * bp);
+          bool ok = false;
+          for (int i = 0; i < kMaxTries && !ok; ++i) {
+            RNG_NEED(2u);
+            const float r1 = r.uniform();
+            const float r2 = r.uniform();
+            const float q = r1 * cc;
+            const float tq = q / ((1.0f - q) * bp);
+            float c = 1.0f - tq;
+            if (c < -1.0f) c = -1.0f;
+            if (2.0f * r2 <= 1.0f + c * c) { ct = c; ok = true; }
+          }
+          if (!ok) {
+            fate = kAbsorbed;
+            alive = false;
+          } else {
+            SSE_COUNT(kStRayleigh, true);
+            ++nR;
+          }
+        } else {
+          fate = kAbsorbed;
+          alive = false;
+        }
+        if (alive) {
+          // uniform azimuth from a point in the unit disk
+          float cp = 1.0f, sp = 0.0f;
+          for (int i = 0; i < kMaxTries; ++i) {
+            RNG_NEED(2u);
+            const float a = 2.0f * r.uniform() - 1.0f;
+            const float b = 2.0f * r.uniform() - 1.0f;
+            const float s2 = a * a + b * b;
+            if (s2 < 1.0f) {
+              cp = (a * a - b * b) / s2;
+              sp = (2.0f * a * b) / s2;
+              break;
+            }
+          }
+          rotate(dx, dy, dz, ct, cp, sp);
+          texit = box_exit(p, px, py, pz, dx, dy, dz);
+          phase = kTrack;
+        } else {
+          phase = kFinish;
+        }
+      }
     }
+
+    // ---------------- photon finished ------------------------------------
+    if (phase == kFinish) {
+      float hx = 0.0f, hy = 0.0f, hz = 0.0f, path = 0.0f, edet = ec.E;
+      if (fate == kEscaped) {
+        // crossing of x^2 + y^2 = R^2 ahead of the last point
+        const float a = dx * dx + dy * dy;
+        fate = kAxial;
+        if (a > 0.0f) {
+          const float b = px * dx + py * dy;
+          const float c = px * px + py * py - p.rr;
+          const float disc = b * b - a * c;
+          const float sq = sqrtf(disc);
+          const float tc = (b > 0.0f) ? (-c) / (b + sq) : (sq - b) / a;
+          const float zz = pz + tc * dz;
+          if (zz >= -p.half_len && zz < p.half_len) {
+            fate = kDetected;
+            hx = px + tc * dx;
+            hy = py + tc * dy;
+            hz = zz;
+            path = len + tc;
+            if (p.e_fwhm > 0.0f) {
+              const float nrm = polar_normal();
+              const float sig = (p.e_fwhm / 2.35482f) * sqrtf(kMec2 / ec.E);
+              edet = ec.E * (1.0f + sig * nrm);
+            }
+          }
+        }
+        SSE_COUNT(kStEscaped, true);
+        SSE_COUNT(kStDetected, fate == kDetected);
+      } else {
+        SSE_COUNT(kStAbsorbed, fate == kAbsorbed);
+        SSE_COUNT(kStKilled, fate == kKilled);
+        SSE_COUNT(kStCapped, fate == kCapped);
+      }
+      const bool det = fate == kDetected;
+      const bool win = det && edet >= p.e_lo && edet <= p.e_hi;
+      int cry = 0, rng = 0;
+      uint32_t lidx = 0xffffffffu;
+      if (win) index_single(p, hx, hy, hz, dx, dy, dz, ec.E, cry, rng, lidx);
+      SSE_COUNT(kStInWindow, win);
+      const uint32_t cr = win ? (static_cast<uint32_t>(cry) | (static_cast<uint32_t>(rng) << 16)) : 0xffffffffu;
+      if (kInstr && rec) {
+        uint32_t* w = rec + 8 + 12 * side;
+        w[0] = __float_as_uint(hx); w[1] = __float_as_uint(hy); w[2] = __float_as_uint(hz);
+        w[3] = __float_as_uint(dx); w[4] = __float_as_uint(dy); w[5] = __float_as_uint(dz);
+        w[6] = __float_as_uint(ec.E); w[7] = __float_as_uint(edet); w[8] = __float_as_uint(path);
+        w[9] = cr;
+        w[10] = win ? lidx : 0xffffffffu;
+        w[11] = static_cast<uint32_t>(nC) | (static_cast<uint32_t>(nR) << 8) | (static_cast<uint32_t>(fate) << 16);
+      }
+      if (side == 0) {
+        a_det = det;
+        a_win = win;
+        a_cr = cr;
+        a_lut = lidx;
+        a_path = path;
+        a_scat = (nC + nR) > 0;
+        a_steps = steps;
+        // photon B: back to back with A
+        side = 1;
+        px = ex; py = ey; pz = ez;
+        dx = -edx; dy = -edy; dz = -edz;
+        t = 0.0f; len = 0.0f;
+        texit = box_exit(p, px, py, pz, dx, dy, dz);
+        ec = p.e511;
+        nC = nR = nint = 0;
+        steps = 0;
+        fate = kEscaped;
+        phase = kTrack;
+      } else {
+        // ---------------- coincidence -------------------------------------
+        const bool scattered = a_scat || (nC + nR) > 0;
+        uint32_t outcome;
+        uint64_t bin = ~0ull;
+        float w = 0.0f, tau = 0.0f;
+        if (!a_det || !det) {
+          outcome = 2;
+        } else if (!a_win || !win) {
+          outcome = 3;
+        } else {
+          const int cA = static_cast<int>(a_cr & 0xffffu), rA = static_cast<int>(a_cr >> 16);
+          if (cA == cry) {
+            outcome = 4;
+          } else if (p.max_ring_diff >= 0 && abs(rA - rng) > p.max_ring_diff) {
+            outcome = 5;
+          } else {
+            const int n = p.n_crystals;
+            int k = cA + cry + 1;
+            int rho = n / 2 - abs(cA - cry);
+            if (k >= n) { k -= n; rho = -rho; }
+            const int view = k >> 1;
+            int m = (2 * cA + 1 - k) % (2 * n);
+            if (m < 0) m += 2 * n;
+            const bool a_pos = m > 0 && m < n;
+            const int half = (p.n_rad - 1) / 2;
+            if (abs(rho) > half) {
+              outcome = 6;
+            } else {
+              tau = a_pos ? (path - a_path) * 0.5f : (a_path - path) * 0.5f;
+              if (p.tof_sigma > 0.0f) {
+                tau = tau + p.tof_sigma * polar_normal();
+              }
+              const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
+              if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
+                outcome = 7;
+              } else {
+                const uint64_t tof = static_cast<uint64_t>(floorf(xt));
+                const uint64_t plane = static_cast<uint64_t>(rA + rng);
+                bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
+                       static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
+                      static_cast<uint64_t>(rho + half);
+                w = lut_value(p, a_lut) * lut_value(p, lidx);
+                if (scattered) {
+                  outcome = 0;
+                  atomicAdd(p.sc_n + bin, 1u);
+                  unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
+                } else {
+                  outcome = 1;
+                  if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
+                  if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
+                }
+              }
+            }
+          }
+        }
+        SSE_COUNT(kStHist, true);
+        SSE_COUNT(kStScatter, outcome == 0);
+        SSE_COUNT(kStTrue, outcome == 1);
+        SSE_COUNT(kStRejWindow, outcome == 3);
+        SSE_COUNT(kStRejSame, outcome == 4);
+        SSE_COUNT(kStRejRing, outcome == 5);
+        SSE_COUNT(kStRejRadial, outcome == 6);
+        SSE_COUNT(kStRejTof, outcome == 7);
+        if (kInstr && rec) {
+          rec[0] = outcome | (scattered ? 0x100u : 0u);
+          rec[1] = static_cast<uint32_t>(bin);
+          rec[2] = static_cast<uint32_t>(bin >> 32);
+          rec[4] = __float_as_uint(w);
+          rec[5] = __float_as_uint(tau);
+          rec[6] = a_steps + steps;
+          rec[7] = 0u;
+        }
+        phase = kEmit;
+      }
+    }
+  }
+  if (kInstr) {
+    __syncthreads();
+    if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
+      atomicAdd(p.stats + threadIdx.x, s_stats[threadIdx.x]);
   }
 }
 
-__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-__global__ void __launch_bounds__(256) transport_kernel(TransportParams p) {
-  Counters cnt;
-#pragma unroll
-  for (int i = 0; i < kStatCount; ++i) cnt.v[i] = 0;
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < p.n; i += stride)
-    simulate_history(p, p.h0 + i, cnt);
-  if (p.stats) {
-    const bool leader = (threadIdx.x & 63) == 0;
-#pragma unroll
-    for (int i = 0; i < kStatCount; ++i) {
-      const uint64_t s = wave_sum(cnt.v[i]);
-      if (leader && s) atomicAdd(p.stats + i, static_cast<unsigned long long>(s));
-    }
-  }
+template <bool kInstr>
+hipError_t launch(const TransportParams& p, hipStream_t stream) {
+  constexpr int kBlock = 256;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, transport_kernel<kInstr>, kBlock, 0);
+  if (e != hipSuccess) return e;
+  const uint64_t resident = static_cast<uint64_t>(cus) * static_cast<uint64_t>(per_cu > 0 ? per_cu : 1);
+  // one resident wave per 64 histories at most: small runs use fewer blocks
+  const uint64_t want = (p.n + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(want < resident ? want : resident);
+  hipLaunchKernelGGL(transport_kernel<kInstr>, dim3(grid), dim3(kBlock), 0, stream, p);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
-  const int block = 256;
-  const uint64_t want = (p.n + block - 1) / block;
-  const int grid = static_cast<int>(want < 16384 ? want : 16384);
-  hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(block), 0, stream, p);
-  return hipGetLastError();
+  return (p.stats || p.rec) ? launch<true>(p, stream) : launch<false>(p, stream);
 }
 
 }  // namespace sse

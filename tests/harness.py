@@ -41,10 +41,11 @@ def case_from(name, tof_sigma=None, lut_dtype=0, physics=None, phantom=None):
     return Case(w.scanner, sino, dict(physics or w.physics), pd, mu, act, ld, seen, store, lut_dtype)
 
 
-def run_gpu(ctx, pid, n, seed, h_offset=0, record_stride=0, trues=True, stream=None):
+def run_gpu(ctx, pid, n, seed, h_offset=0, record_stride=0, trues=True, stream=None, stats=True):
+    """stats=False and record_stride=0 run the production (uninstrumented) kernel."""
     import torch
     n_rec = 0 if not record_stride else (n + record_stride - 1) // record_stride
-    out = ctx.new_outputs(trues=trues, stats=True, records=n_rec, record_stride=record_stride or 1)
+    out = ctx.new_outputs(trues=trues, stats=stats, records=n_rec, record_stride=record_stride or 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.simulate(pid, n, seed, out, h_offset=h_offset, stream=stream)
@@ -54,7 +55,8 @@ def run_gpu(ctx, pid, n, seed, h_offset=0, record_stride=0, trues=True, stream=N
     res["scatter_counts"] = res["scatter_counts"].view(np.uint32)
     if trues:
         res["true_counts"] = res["true_counts"].view(np.uint32)
-    res["stats"] = {k: int(v) for k, v in zip(O.ST_NAMES, res["stats"].view(np.uint64))}
+    if stats:
+        res["stats"] = {k: int(v) for k, v in zip(O.ST_NAMES, res["stats"].view(np.uint64))}
     if n_rec:
         res["records"] = np.ascontiguousarray(res["records"]).view(np.uint32).reshape(-1).view(O.RECORD_DTYPE)
     res["seconds"] = dt

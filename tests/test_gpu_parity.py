@@ -25,6 +25,17 @@ if not torch.cuda.is_available():
 import paper_2509_05047_amd as sse  # noqa: E402
 
 
+def stats_match(g, o):
+    """All statistics equal, except the Philox block count: the kernel
+    generates blocks ahead of need (lanes with buffer room join a refill
+    another lane needs), so it counts at least the oracle's on-demand blocks
+    and at most about one extra block per history."""
+    gs, os_ = dict(g), dict(o)
+    gb, ob = gs.pop("rng_blocks"), os_.pop("rng_blocks")
+    assert gs == os_
+    assert ob <= gb <= ob + 2 * gs["histories"], (gb, ob)
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -56,7 +67,7 @@ def test_tiny_workload_full_parity():
     worst = H.compare_sinograms(g, o, g["records"], o["records"], same)
     say(f"[parity] worst relative weight difference {worst:.3e}")
     if same.all():
-        assert g["stats"] == o["stats"]
+        stats_match(g["stats"], o["stats"])
     assert g["scatter_counts"].sum() > 0
 
 
@@ -65,7 +76,7 @@ def test_clinical_slice_parity_with_offset_and_ragged_count():
     g, o, same = check_case(case, 200_003, 5678, h_offset=123_456_789)
     H.compare_sinograms(g, o, g["records"], o["records"], same)
     if same.all():
-        assert g["stats"] == o["stats"]
+        stats_match(g["stats"], o["stats"])
 
 
 def test_clinical_no_jitter_parity():
@@ -84,9 +95,10 @@ def test_narrow_lut_parity(dtype):
 
 
 def test_full_size_clinical_sampled_histories():
-    """The clinical workload at its full size (1e9 histories) in the launch
-    configuration the benchmark times; every 10 000th history is recorded by
-    the same launch and recomputed by the oracle one by one."""
+    """The clinical workload at its full size (1e9 histories).  The
+    instrumented launch records every 10 000th history, which the oracle
+    recomputes one by one; the production launch the benchmark times (no
+    statistics, no records) must then give the same sinograms."""
     case = H.case_from("clinical")
     w = W.WORKLOADS["clinical"]
     g, o, same = check_case(case, w.n_histories, w.seed, stride=10_000)
@@ -95,7 +107,18 @@ def test_full_size_clinical_sampled_histories():
     assert int(g["scatter_counts"].sum()) == st["scatter"]
     assert int(g["true_counts"].sum()) == st["true"]
     assert np.all(g["scatter_weights"] <= g["scatter_counts"] * (1 + 1e-12))
-    say(f"[full] {w.n_histories / g['seconds']:.3e} histories/s, scatter {st['scatter']}, trues {st['true']}")
+    say(f"[full] instrumented {w.n_histories / g['seconds']:.3e} histories/s, scatter {st['scatter']}, trues {st['true']}")
+    ctx, pid = H.open_context(case)
+    try:
+        prod = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+    finally:
+        ctx.close()
+    say(f"[full] production {w.n_histories / prod['seconds']:.3e} histories/s")
+    for c, wt in (("scatter_counts", "scatter_weights"), ("true_counts", "true_weights")):
+        assert np.array_equal(prod[c], g[c]), c
+        nz = g[wt] != 0
+        assert np.array_equal(prod[wt] != 0, nz)
+        assert np.max(np.abs(prod[wt][nz] - g[wt][nz]) / g[wt][nz]) < 1e-12
 
 
 def test_split_runs_sum_to_whole_run_and_repeat():
@@ -117,6 +140,25 @@ def test_split_runs_sum_to_whole_run_and_repeat():
     nz = whole["scatter_weights"] != 0
     assert np.max(np.abs(parts_w[nz] - whole["scatter_weights"][nz]) / whole["scatter_weights"][nz]) < 1e-12
     ctx.close()
+
+
+def test_results_do_not_depend_on_statistics_output():
+    """Sinograms and records are the same whether or not the statistics
+    counters are requested."""
+    case = H.case_from("clinical")
+    ctx, pid = H.open_context(case)
+    try:
+        a = ctx.new_outputs(trues=True, stats=True, records=2000, record_stride=25)
+        b = ctx.new_outputs(trues=True, stats=False, records=2000, record_stride=25)
+        ctx.simulate(pid, 50_000, 31, a)
+        ctx.simulate(pid, 50_000, 31, b)
+        torch.cuda.synchronize()
+        for k in ("scatter_counts", "true_counts", "records"):
+            assert torch.equal(a[k], b[k]), k
+        for k in ("scatter_weights", "true_weights"):
+            assert torch.allclose(a[k], b[k], rtol=1e-12, atol=0), k
+    finally:
+        ctx.close()
 
 
 def test_edge_cases():
