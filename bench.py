@@ -30,6 +30,34 @@ COST = dict(rng_block=130, step=70, real=250, detected=150, history=150)
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 
 
+def kernel_source_hash() -> str:
+    """First 16 hex digits of sha256 over the transport kernel's sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("transport.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2509_05047_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per transport launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None when the
+    kernel has changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "transport_clinical_hbm_counters.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+): (\S+)$", text, flags=re.M))
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    fetch = float(fields["fetch_kib_per_dispatch"]) * 1024 * float(fields["fetch_factor"])
+    write = float(fields["write_kib_per_dispatch"]) * 1024 * float(fields["write_factor"])
+    return fetch + write
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -156,7 +184,9 @@ def main():
         "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
         "transport_kernel_ms": float(np.mean(kernel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
+                     "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
+                                 and args.lut == "f32" else None),
                      "ops_per_history": ops_per_hist},
     }
     if not args.no_cpu_baseline:
