@@ -211,7 +211,10 @@ sse_status ensure_scratch(sse_ctx* c) {
   return SSE_OK;
 }
 
-sse_status smooth(sse_ctx* c, const float* in, float* out, const float* sigma, float truncate, hipStream_t s) {
+// Separable smoothing of `in` (binary32, or binary64 weights times `scale`
+// rounded on load) into `out`, optionally multiplied by the sensitivity.
+sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, float* out, const float* sigma,
+                  float truncate, const float* sens, hipStream_t s) {
   if (!sigma) return fail(SSE_EINVAL, "null sigma");
   if (!in || !out) return fail(SSE_EINVAL, "null buffer");
   if (!(truncate > 0.0f) || !std::isfinite(truncate)) return fail(SSE_EINVAL, "truncate must be positive");
@@ -236,22 +239,32 @@ sse_status smooth(sse_ctx* c, const float* in, float* out, const float* sigma, f
   }
   const sse::PostParams g = post_params(c);
   if (na == 0) {
-    if (in != out) HIP_TRY(hipMemcpyAsync(out, in, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
+    if (in_is_f64) {
+      HIP_TRY(sse::launch_scale_to_float(g, static_cast<const double*>(in), scale, out, s), "scale kernel");
+    } else if (in != out) {
+      HIP_TRY(hipMemcpyAsync(out, in, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
+    }
+    if (sens) HIP_TRY(sse::launch_multiply_sens(g, out, sens, c->sens_tof, out, s), "sensitivity kernel");
     return SSE_OK;
   }
   sse_status st = ensure_scratch(c);
   if (st != SSE_OK) return st;
   // A pass never reads and writes the same buffer: with in == out and one
   // active axis the result goes through scratch.
-  const float* src = in;
+  const void* src = in;
+  bool src_f64 = in_is_f64;
+  float* dst = nullptr;
   for (int i = 0; i < na; ++i) {
     const bool last = i == na - 1;
-    float* dst = (last && !(na == 1 && in == out)) ? out : c->d_scratch[i % 2];
-    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, dst, taps[i], s), "smoothing kernel");
+    dst = (last && !(na == 1 && in == out)) ? out : c->d_scratch[i % 2];
+    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, src_f64, scale, dst, taps[i], last ? sens : nullptr,
+                                    c->sens_tof, s),
+            "smoothing kernel");
     src = dst;
+    src_f64 = false;
   }
-  if (src != out)
-    HIP_TRY(hipMemcpyAsync(out, src, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy smoothed");
+  if (dst != out)
+    HIP_TRY(hipMemcpyAsync(out, dst, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy smoothed");
   return SSE_OK;
 }
 
@@ -595,7 +608,7 @@ sse_status sse_gaussian_smooth(sse_ctx* c, const float* in, float* out, const fl
                                void* stream) {
   if (!c) return fail(SSE_EINVAL, "null context");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  return smooth(c, in, out, sigma_bins, truncate, static_cast<hipStream_t>(stream));
+  return smooth(c, in, false, 1.0, out, sigma_bins, truncate, nullptr, static_cast<hipStream_t>(stream));
 }
 
 sse_status sse_finalize(sse_ctx* c, const double* W, double scale, const float* sigma_bins, float truncate,
@@ -605,13 +618,7 @@ sse_status sse_finalize(sse_ctx* c, const double* W, double scale, const float* 
   if (!c->d_sens) return fail(SSE_ESTATE, "no sensitivity sinogram loaded");
   if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
   HIP_TRY(hipSetDevice(c->device), "set device");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const sse::PostParams g = post_params(c);
-  HIP_TRY(sse::launch_scale_to_float(g, W, scale, out, s), "scale kernel");
-  sse_status st = smooth(c, out, out, sigma_bins, truncate, s);
-  if (st != SSE_OK) return st;
-  HIP_TRY(sse::launch_multiply_sens(g, out, c->d_sens, c->sens_tof, out, s), "sensitivity kernel");
-  return SSE_OK;
+  return smooth(c, W, true, scale, out, sigma_bins, truncate, c->d_sens, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

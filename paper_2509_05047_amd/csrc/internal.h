@@ -87,8 +87,10 @@ struct Taps {
   float w[2 * kMaxSmoothRadius + 1];
   int radius;
 };
-// axis: 0 radial, 1 view, 2 plane.
-hipError_t launch_smooth_axis(const PostParams& g, int axis, const float* in, float* out, const Taps& taps,
-                              hipStream_t stream);
+// One separable pass along axis (0 radial, 1 view, 2 plane).  The input is
+// binary32, or binary64 weights scaled by `scale` and rounded on load
+// (in_is_f64); if sens is not NULL the output is multiplied by it.
+hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
+                              float* out, const Taps& taps, const float* sens, int sens_tof, hipStream_t stream);
 
 }  // namespace sse

@@ -293,3 +293,25 @@ def test_clinical_finalize_matches_oracle_on_sampled_bins():
     ref = post.gaussian_smooth_at(scaled, (2.0, 2.0, 2.0), pts) * sens[pts[:, 1], pts[:, 2], pts[:, 3]]
     g = got[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]]
     assert np.max(np.abs(g - ref) / np.abs(ref)) < 1e-5
+
+
+def test_precision_forms_against_fp64_oracle():
+    """Narrow-LUT precision forms (config C3) against the FP64 oracle with the
+    FP32 LUT.  Bounds: with the same dequantised LUT the binary32 path equals
+    the binary32 oracle up to binary64 summation order (<= 1e-6 after the
+    binary32 rounding of the estimate); against the FP64 oracle the total
+    scatter moves by at most the LUT rounding (2^-11 for F16, 2^-8 for BF16,
+    twice for a product) and per-bin errors stay within that bound except in
+    the few bins where binary32 and binary64 transport took different
+    decisions."""
+    from tests import precision
+    rep = precision.report(n=400_000)
+    say(f"[precision] {rep}")
+    bound = {"f32": 1e-6, "f16": 2 * 2.0 ** -11, "bf16": 2 * 2.0 ** -8}
+    for name, r in rep["dtypes"].items():
+        same = r["vs_fp32_oracle_same_lut"]
+        assert r["counts_equal_fp32_oracle"]
+        assert same["per_bin_max_rel"] < 1e-6 and same["bins_nonzero_only_in_estimate"] == 0
+        ref = r["vs_fp64_oracle_fp32_lut"]
+        assert ref["total_scatter_rel"] < bound[name] + 1e-4, (name, ref)
+        assert ref["per_bin_median_rel"] <= bound[name] + 1e-6, (name, ref)
