@@ -143,12 +143,100 @@ def large_loop(args):
     print(json.dumps(result), flush=True)
 
 
+def serving(args):
+    """Serving stream: Poisson arrivals of scatter-estimate requests on
+    body-like phantoms of 64^3, 128^3 and 192x192x89 voxels (a pool of
+    seeded phantoms, all resident), budgets log-uniform in [1e7, 5e8]
+    histories, one shared LUT, the Signa scanner and sinogram.  Latency is
+    submit -> sinogram complete on the device."""
+    import threading
+    import torch
+    import paper_2509_05047_amd as sse
+    w = W.WORKLOADS["clinical"]
+    ctx = sse.Context(w.scanner, w.sino, w.physics)
+    lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    ctx.load_lut(lut_desc, lut)
+    n_pool = 12
+    pids = []
+    for k in range(n_pool):
+        pd, mu, act = W.serving_phantom(k)
+        pids.append(ctx.load_phantom(pd, mu, act))
+    log(f"[bench] serving: {n_pool} resident phantoms")
+    # single-stream throughput on the pool (sets the arrival rate)
+    out = ctx.new_outputs(stats=False)
+    ctx.simulate(pids[0], 10_000_000, 1, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    probe = 0
+    for k in range(3):
+        ctx.simulate(pids[k], 100_000_000, 2, out)
+        probe += 100_000_000
+    torch.cuda.synchronize()
+    single = probe / (time.perf_counter() - t0)
+    del out
+    rng = np.random.default_rng(77)
+    nreq = args.requests
+    budgets = np.exp(rng.uniform(np.log(1e7), np.log(5e8), nreq)).astype(np.int64)
+    which = rng.integers(0, n_pool, nreq)
+    mean_budget = (5e8 - 1e7) / np.log(50.0)
+    lam = args.load * single / mean_budget
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, nreq))
+    footprint = ctx.n_bins * 12
+    budget_bytes = 48 * footprint
+    srv = sse.Server(ctx, max_active=32, hbm_budget_bytes=budget_bytes, tick_histories=int(single * 0.01))
+    log(f"[bench] single-stream {single:.3e} histories/s, load {args.load}, {lam:.2f} requests/s")
+    ids = {}
+
+    def generator():
+        start = time.perf_counter()
+        for i in range(nreq):
+            delay = arrivals[i] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            ids[srv.submit(pids[which[i]], int(budgets[i]), 5000 + i)] = i
+
+    gen = threading.Thread(target=generator)
+    t_start = time.perf_counter()
+    gen.start()
+    done = []
+    while len(done) < nreq:
+        for c in srv.poll(wait_ms=100):
+            done.append(c)
+            srv.release(c["id"])
+        if len(done) % 32 == 0 and done:
+            log(f"[bench] {len(done)}/{nreq} requests complete")
+    gen.join()
+    makespan = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.stop()
+    ctx.close()
+    lat = np.array([(c["t_complete"] - c["t_submit"]) * 1e3 for c in done])
+    hist = int(sum(c["histories"] for c in done))
+    result = {
+        "metric": "photon histories/sec and p50/p99 request latency (serving)",
+        "value": hist / makespan, "unit": "histories/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+        "ms_per_step": makespan / nreq * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: {nreq} Poisson requests at load {args.load} of single-stream "
+                               f"throughput, budgets log-uniform 1e7-5e8, {n_pool} body phantoms "
+                               "(64^3 / 128^3 / 192x192x89), Signa scanner, 357x224x89x29 sinogram",
+                   "histories_total": hist},
+        "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
+        "latency_max_ms": float(lat.max()), "single_stream_histories_per_sec": single,
+        "arrival_rate_per_sec": lam, "max_active_seen": st["max_active_seen"], "ticks": st["ticks"],
+        "hbm_budget_bytes": budget_bytes, "bytes_allocated": st["bytes_allocated"],
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="clinical", choices=["clinical", "large"])
+    ap.add_argument("--workload", default="clinical", choices=["clinical", "large", "serving"])
+    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs single-stream throughput")
     ap.add_argument("--histories", type=float, default=0, help="override histories per step")
     ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-histories", type=int, default=40_000_000)
@@ -168,6 +256,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "large":
         return large_loop(args)
+    if args.workload == "serving":
+        return serving(args)
     if args.copy_bytes:
         src = torch.ones(int(args.copy_bytes) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -268,6 +268,94 @@ sse_status sse_finalize(sse_ctx* ctx, const double* W, double scale, const float
  * Host pointers, n entries each.  Errors: SSE_EINVAL. */
 sse_status sse_build_alias_table(const float* activity, uint64_t n, uint32_t* thresh, uint32_t* alias);
 
+/* ------------------------------------------------------------------------ */
+/* Request server (continuous batching of scatter-estimate requests)         */
+/* ------------------------------------------------------------------------ */
+/* The iterative scatter estimation of the paper re-simulates scatter for a
+ * new activity image at every iteration (Methods, "Unknown activity
+ * distribution, very limited simulation time"); a serving system runs many
+ * such requests (different phantoms and history budgets) on one GPU.  The
+ * server admits requests first-in first-out while their output footprint
+ * fits an HBM budget and a slot is free, and every scheduling tick launches
+ * one kernel over a work list of history sub-chunks drawn from the active
+ * requests, shortest remaining work first, so requests that arrive while
+ * others run join the next tick and their work overlaps on the device.  Every random
+ * number is keyed by the history index, so a request's sinograms are the
+ * same alone or in any mix (counts exactly; weights up to the order of
+ * binary64 sums).  Phantoms, LUT and sensitivity stay resident in the
+ * context. */
+typedef struct sse_server sse_server;
+
+typedef struct {
+  int32_t max_active;          /* requests simulated concurrently, 1..256 */
+  int32_t reserved;
+  uint64_t hbm_budget_bytes;   /* cap on library-allocated output buffers; 0 = 90 % of free device memory */
+  uint64_t tick_histories;     /* histories per tick over all active requests; 0 = 32 Mi */
+  uint64_t chunk_histories;    /* histories per work-list sub-chunk (<= 2^31); 0 = about 8 per resident wave per tick */
+} sse_server_cfg;
+
+typedef struct {
+  sse_phantom_id phantom;      /* loaded in the server's context */
+  uint32_t reserved;
+  uint64_t n_histories;        /* >= 1 */
+  uint64_t seed;
+  uint64_t h_offset;           /* histories h_offset .. h_offset + n - 1 */
+  uint32_t* scatter_counts;    /* caller-owned device sinograms (zeroed by the server), or both */
+  double* scatter_weights;     /* NULL: the server allocates them within the budget */
+} sse_request;
+
+enum { SSE_REQ_DONE = 0, SSE_REQ_CANCELLED = 1 };
+
+typedef struct {
+  uint64_t id;
+  int32_t status;              /* SSE_REQ_DONE or SSE_REQ_CANCELLED */
+  int32_t reserved;
+  double t_submit, t_admit, t_complete;  /* seconds since sse_server_start (host steady clock) */
+  uint64_t histories;          /* histories simulated */
+  uint32_t* scatter_counts;    /* the result sinograms (device) */
+  double* scatter_weights;
+} sse_completion;
+
+typedef struct {
+  uint64_t submitted, completed, cancelled, ticks, histories;
+  uint64_t max_active_seen;    /* largest number of requests active in one tick */
+  uint64_t bytes_allocated;    /* library-allocated output buffers (in use or pooled) */
+  uint64_t budget_bytes;
+} sse_server_stats;
+
+/* Start a server on a context (the context must outlive it and have a LUT
+ * loaded).  Spawns one host scheduler thread and one HIP stream. Errors:
+ * SSE_EINVAL, SSE_ESTATE (no LUT), SSE_ENOMEM, SSE_EDEVICE. */
+sse_status sse_server_start(sse_ctx* ctx, const sse_server_cfg* cfg, sse_server** out);
+
+/* Queue a request; *id receives its id.  Thread-safe.  Errors: SSE_EINVAL
+ * (unknown phantom, zero histories, one output pointer NULL, misaligned),
+ * SSE_EBUSY (a request can never fit the budget), SSE_ESTATE (stopping). */
+sse_status sse_server_submit(sse_server* s, const sse_request* req, uint64_t* id);
+
+/* Move up to max completed requests into out (oldest first); *n receives
+ * the count.  Waits up to wait_ms milliseconds for the first one (0: no
+ * wait).  Thread-safe. */
+sse_status sse_server_poll(sse_server* s, sse_completion* out, int32_t max, int32_t* n, int32_t wait_ms);
+
+/* Stop simulating a queued or active request; it completes with status
+ * SSE_REQ_CANCELLED once its work in flight has finished.  Errors:
+ * SSE_EINVAL (unknown or already completed id). */
+sse_status sse_server_cancel(sse_server* s, uint64_t id);
+
+/* Return a completed request's server-allocated sinograms to the pool (the
+ * pointers in its completion become invalid).  No-op for caller-owned
+ * buffers.  Errors: SSE_EINVAL (unknown id or not completed). */
+sse_status sse_server_release(sse_server* s, uint64_t id);
+
+/* Counters of the server (a consistent snapshot). */
+sse_status sse_server_stats_get(sse_server* s, sse_server_stats* out);
+
+/* Drain and stop: waits until every submitted request has completed, joins
+ * the scheduler thread and frees everything the server allocated
+ * (including outputs not yet released). */
+sse_status sse_server_stop(sse_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,30 @@ class Outputs(C.Structure):
                 ("stats", C.c_void_p), ("records", C.c_void_p), ("record_stride", C.c_uint64)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("reserved", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
+                ("tick_histories", C.c_uint64), ("chunk_histories", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("phantom", C.c_uint32), ("reserved", C.c_uint32), ("n_histories", C.c_uint64),
+                ("seed", C.c_uint64), ("h_offset", C.c_uint64), ("scatter_counts", C.c_void_p),
+                ("scatter_weights", C.c_void_p)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_complete", C.c_double), ("histories", C.c_uint64),
+                ("scatter_counts", C.c_void_p), ("scatter_weights", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "cancelled", "ticks", "histories",
+                                          "max_active_seen", "bytes_allocated", "budget_bytes")]
+
+
+REQ_DONE, REQ_CANCELLED = 0, 1
+
 # every entry point of include/sse.h: name -> (argtypes, restype)
 _P = C.c_void_p
 SIGNATURES = {
@@ -83,6 +107,13 @@ SIGNATURES = {
     "sse_gaussian_smooth": ([_P, _P, _P, _P, C.c_float, _P], C.c_int),
     "sse_finalize": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
     "sse_build_alias_table": ([_P, C.c_uint64, _P, _P], C.c_int),
+    "sse_server_start": ([_P, _P, C.POINTER(C.c_void_p)], C.c_int),
+    "sse_server_submit": ([_P, _P, C.POINTER(C.c_uint64)], C.c_int),
+    "sse_server_poll": ([_P, _P, C.c_int32, C.POINTER(C.c_int32), C.c_int32], C.c_int),
+    "sse_server_cancel": ([_P, C.c_uint64], C.c_int),
+    "sse_server_release": ([_P, C.c_uint64], C.c_int),
+    "sse_server_stats_get": ([_P, _P], C.c_int),
+    "sse_server_stop": ([_P], C.c_int),
 }
 
 _lib = None
@@ -113,6 +144,8 @@ def _ptr(t):
     """Device or host address of a torch tensor / numpy array (None -> NULL)."""
     if t is None:
         return None
+    if isinstance(t, int):
+        return t
     if isinstance(t, np.ndarray):
         return t.ctypes.data
     return t.data_ptr()
@@ -274,3 +307,64 @@ def stats_dict(t) -> dict:
     """Statistics tensor -> {name: int}."""
     v = t.cpu().numpy().astype(np.uint64)
     return {k: int(x) for k, x in zip(STAT_NAMES, v)}
+
+
+class Server:
+    """Request server on a context (see sse_server_start): continuous
+    batching of scatter-estimate requests with HBM-footprint admission."""
+
+    def __init__(self, ctx: Context, max_active: int = 16, hbm_budget_bytes: int = 0, tick_histories: int = 0,
+                 chunk_histories: int = 0):
+        self.ctx = ctx
+        cfg = ServerCfg(max_active, 0, int(hbm_budget_bytes), int(tick_histories), int(chunk_histories))
+        h = C.c_void_p()
+        _check(lib().sse_server_start(ctx._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def submit(self, pid: int, n_histories: int, seed: int, h_offset: int = 0, counts=None, weights=None) -> int:
+        r = Request(pid, 0, int(n_histories), int(seed), int(h_offset), _ptr(counts), _ptr(weights))
+        rid = C.c_uint64()
+        _check(lib().sse_server_submit(self._h, C.byref(r), C.byref(rid)))
+        return rid.value
+
+    def poll(self, max_n: int = 64, wait_ms: int = 0) -> list:
+        buf = (Completion * max_n)()
+        n = C.c_int32()
+        _check(lib().sse_server_poll(self._h, buf, max_n, C.byref(n), int(wait_ms)))
+        return [{f[0]: getattr(buf[i], f[0]) for f in Completion._fields_} for i in range(n.value)]
+
+    def cancel(self, rid: int):
+        _check(lib().sse_server_cancel(self._h, rid))
+
+    def release(self, rid: int):
+        _check(lib().sse_server_release(self._h, rid))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().sse_server_stats_get(self._h, C.byref(st)))
+        return {f[0]: getattr(st, f[0]) for f in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(lib().sse_server_stop(h))
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def copy_device_to_tensor(ptr: int, n: int, dtype):
+    """Copy n elements at a device address into a new torch tensor (used for
+    server-allocated results)."""
+    import torch
+    out = torch.empty(n, dtype=dtype, device="cuda")
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    hip.hipMemcpy.restype = C.c_int
+    err = hip.hipMemcpy(out.data_ptr(), ptr, n * out.element_size(), 3)  # device to device
+    if err != 0:
+        raise SseError(EDEVICE, f"hipMemcpy failed ({err})")
+    return out

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsse.so")
-SOURCES = ["csrc/transport.hip", "csrc/post.hip", "csrc/capi.cpp"]
+SOURCES = ["csrc/transport.hip", "csrc/post.hip", "csrc/capi.cpp", "csrc/serve.cpp"]
 ARCH = os.environ.get("SSE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -11,10 +11,9 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
-#include "sse.h"
+#include "context.h"
 
-namespace {
+namespace sse_detail {
 
 thread_local std::string g_error;
 
@@ -28,47 +27,80 @@ sse_status hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? SSE_ENOMEM : SSE_EDEVICE;
 }
 
-#define HIP_TRY(expr, what)                    \
-  do {                                         \
-    hipError_t e_ = (expr);                    \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
-
-struct Phantom {
-  bool used = false;
-  sse_phantom_desc desc{};
-  uint64_t nvox = 0;
-  float mu_max = 0.0f;
-  double activity_sum = 0.0;
-  float* d_mu = nullptr;
-  uint2* d_alias = nullptr;
-  uint8_t* d_mu8 = nullptr;      // palette indices when the map has <= 256 distinct values
-  float* d_mu_table = nullptr;   // the 256-entry palette (exact values)
-};
-
-}  // namespace
-
-struct sse_ctx {
-  int device = 0;
-  sse_scanner_desc sc{};
-  sse_sino_desc sn{};
-  sse_physics_desc ph{};
-  uint64_t n_bins = 0;
-  double kn511 = 0.0;
-  std::vector<Phantom> phantoms;
-  void* d_lut = nullptr;
-  int lut_type = -1;
-  sse_lut_desc lut{};
-  float* d_sens = nullptr;
-  int sens_tof = 0;
-  float* d_scratch[2] = {nullptr, nullptr};
-};
-
-namespace {
-
 void release(void* p) {
   if (p) (void)hipFree(p);
 }
+
+Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
+  if (!c || id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1].used) return nullptr;
+  return &c->phantoms[id - 1];
+}
+
+void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, uint64_t h0, uint64_t n,
+                            sse::TransportParams& p) {
+  p = sse::TransportParams{};
+  const sse_phantom_desc& d = ph->desc;
+  p.mu = ph->d_mu;
+  p.mu8 = ph->d_mu8;
+  p.mu_table = ph->d_mu_table;
+  p.alias = ph->d_alias;
+  p.nvox = ph->nvox;
+  p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.inv_nx = 1.0f / static_cast<float>(d.nx);
+  p.inv_nxy = 1.0f / static_cast<float>(d.nx * d.ny);
+  p.vx = d.voxel_mm[0]; p.vy = d.voxel_mm[1]; p.vz = d.voxel_mm[2];
+  p.lox = d.lo_mm[0]; p.loy = d.lo_mm[1]; p.loz = d.lo_mm[2];
+  p.hix = p.lox + static_cast<float>(d.nx) * p.vx;
+  p.hiy = p.loy + static_cast<float>(d.ny) * p.vy;
+  p.hiz = p.loz + static_cast<float>(d.nz) * p.vz;
+  p.ivx = 1.0f / p.vx; p.ivy = 1.0f / p.vy; p.ivz = 1.0f / p.vz;
+  p.mu_maj = c->ph.mu_majorant > 0.0f ? c->ph.mu_majorant : ph->mu_max;
+  p.n_crystals = c->sc.n_crystals;
+  p.n_rings = c->sc.n_rings;
+  p.cmod = c->sc.crystals_per_module;
+  p.rblk = c->sc.rings_per_block;
+  p.max_ring_diff = c->sc.max_ring_diff;
+  p.rr = c->sc.radius_mm * c->sc.radius_mm;
+  p.half_len = 0.5f * c->sc.length_mm;
+  p.pitch = c->sc.length_mm / static_cast<float>(c->sc.n_rings);
+  p.n_rad = c->sn.n_rad; p.n_view = c->sn.n_view; p.n_plane = c->sn.n_plane; p.n_tof = c->sn.n_tof;
+  p.tof_bin = c->sn.tof_bin_mm;
+  p.tof_sigma = c->sn.tof_sigma_mm;
+  p.e_lo = c->ph.e_lo_kev; p.e_hi = c->ph.e_hi_kev; p.e_kill = c->ph.e_kill_kev; p.e_fwhm = c->ph.e_fwhm_frac;
+  p.rayleigh_beta = c->ph.rayleigh_beta;
+  p.f_c = static_cast<double>(c->ph.f_compton);
+  p.f_r = static_cast<double>(c->ph.f_rayleigh);
+  p.f_p = static_cast<double>(c->ph.f_photo);
+  p.kn511 = c->kn511;
+  p.max_int = c->ph.max_interactions;
+  {  // coefficients at 511 keV, evaluated once on the host
+    sse::ECoef& e = p.e511;
+    e.E = sse::kMec2;
+    e.alpha = e.E / sse::kMec2;
+    const double a = static_cast<double>(e.alpha);
+    const double fc = p.f_c * (sse::kn_total(a) / p.kn511);
+    const double fr = p.f_r * (1.0 / (a * a));
+    const double fp = p.f_p * (1.0 / (a * a * a));
+    e.g = static_cast<float>(fc + fr + fp);
+    e.cC = static_cast<float>(fc);
+    e.cCR = static_cast<float>(fc + fr);
+    e.inv_maj = 1.0f / (p.mu_maj * e.g);
+  }
+  p.lut = c->d_lut;
+  p.lut_type = c->lut_type;
+  p.d0 = c->lut.dims[0]; p.d1 = c->lut.dims[1]; p.d2 = c->lut.dims[2]; p.d3 = c->lut.dims[3]; p.d4 = c->lut.dims[4];
+  p.e_min = c->lut.e_min_kev;
+  p.e_scale = static_cast<float>(c->lut.dims[0]) / (c->lut.e_max_kev - c->lut.e_min_kev);
+  p.seed = seed;
+  p.h0 = h0;
+  p.n = n;
+}
+
+}  // namespace sse_detail
+
+using namespace sse_detail;
+
+namespace {
 
 bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
 
@@ -194,11 +226,6 @@ sse_status upload_palette(const std::vector<float>& mu, hipStream_t s, Phantom& 
   HIP_TRY(hipMemcpyAsync(p.d_mu_table, table.data(), 256 * sizeof(float), hipMemcpyHostToDevice, s), "upload palette");
   HIP_TRY(hipStreamSynchronize(s), "synchronise palette upload");
   return SSE_OK;
-}
-
-Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
-  if (!c || id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1].used) return nullptr;
-  return &c->phantoms[id - 1];
 }
 
 sse::PostParams post_params(const sse_ctx* c) {
@@ -514,62 +541,8 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   if (n_histories > ~static_cast<uint64_t>(0) - h_offset) return fail(SSE_EINVAL, "history range overflows");
   if (n_histories == 0) return SSE_OK;
   HIP_TRY(hipSetDevice(c->device), "set device");
-  sse::TransportParams p{};
-  const sse_phantom_desc& d = ph->desc;
-  p.mu = ph->d_mu;
-  p.mu8 = ph->d_mu8;
-  p.mu_table = ph->d_mu_table;
-  p.alias = ph->d_alias;
-  p.nvox = ph->nvox;
-  p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
-  p.inv_nx = 1.0f / static_cast<float>(d.nx);
-  p.inv_nxy = 1.0f / static_cast<float>(d.nx * d.ny);
-  p.vx = d.voxel_mm[0]; p.vy = d.voxel_mm[1]; p.vz = d.voxel_mm[2];
-  p.lox = d.lo_mm[0]; p.loy = d.lo_mm[1]; p.loz = d.lo_mm[2];
-  p.hix = p.lox + static_cast<float>(d.nx) * p.vx;
-  p.hiy = p.loy + static_cast<float>(d.ny) * p.vy;
-  p.hiz = p.loz + static_cast<float>(d.nz) * p.vz;
-  p.ivx = 1.0f / p.vx; p.ivy = 1.0f / p.vy; p.ivz = 1.0f / p.vz;
-  p.mu_maj = c->ph.mu_majorant > 0.0f ? c->ph.mu_majorant : ph->mu_max;
-  p.n_crystals = c->sc.n_crystals;
-  p.n_rings = c->sc.n_rings;
-  p.cmod = c->sc.crystals_per_module;
-  p.rblk = c->sc.rings_per_block;
-  p.max_ring_diff = c->sc.max_ring_diff;
-  p.rr = c->sc.radius_mm * c->sc.radius_mm;
-  p.half_len = 0.5f * c->sc.length_mm;
-  p.pitch = c->sc.length_mm / static_cast<float>(c->sc.n_rings);
-  p.n_rad = c->sn.n_rad; p.n_view = c->sn.n_view; p.n_plane = c->sn.n_plane; p.n_tof = c->sn.n_tof;
-  p.tof_bin = c->sn.tof_bin_mm;
-  p.tof_sigma = c->sn.tof_sigma_mm;
-  p.e_lo = c->ph.e_lo_kev; p.e_hi = c->ph.e_hi_kev; p.e_kill = c->ph.e_kill_kev; p.e_fwhm = c->ph.e_fwhm_frac;
-  p.rayleigh_beta = c->ph.rayleigh_beta;
-  p.f_c = static_cast<double>(c->ph.f_compton);
-  p.f_r = static_cast<double>(c->ph.f_rayleigh);
-  p.f_p = static_cast<double>(c->ph.f_photo);
-  p.kn511 = c->kn511;
-  p.max_int = c->ph.max_interactions;
-  {  // coefficients at 511 keV, evaluated once on the host
-    sse::ECoef& e = p.e511;
-    e.E = sse::kMec2;
-    e.alpha = e.E / sse::kMec2;
-    const double a = static_cast<double>(e.alpha);
-    const double fc = p.f_c * (sse::kn_total(a) / p.kn511);
-    const double fr = p.f_r * (1.0 / (a * a));
-    const double fp = p.f_p * (1.0 / (a * a * a));
-    e.g = static_cast<float>(fc + fr + fp);
-    e.cC = static_cast<float>(fc);
-    e.cCR = static_cast<float>(fc + fr);
-    e.inv_maj = 1.0f / (p.mu_maj * e.g);
-  }
-  p.lut = c->d_lut;
-  p.lut_type = c->lut_type;
-  p.d0 = c->lut.dims[0]; p.d1 = c->lut.dims[1]; p.d2 = c->lut.dims[2]; p.d3 = c->lut.dims[3]; p.d4 = c->lut.dims[4];
-  p.e_min = c->lut.e_min_kev;
-  p.e_scale = static_cast<float>(c->lut.dims[0]) / (c->lut.e_max_kev - c->lut.e_min_kev);
-  p.seed = seed;
-  p.h0 = h_offset;
-  p.n = n_histories;
+  sse::TransportParams p;
+  build_transport_params(c, ph, seed, h_offset, n_histories, p);
   p.sc_n = out->scatter_counts;
   p.sc_w = out->scatter_weights;
   p.tr_n = out->true_counts;

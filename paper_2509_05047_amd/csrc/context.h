@@ -1,0 +1,57 @@
+// Library-internal state shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sse.h"
+
+struct Phantom {
+  bool used = false;
+  sse_phantom_desc desc{};
+  uint64_t nvox = 0;
+  float mu_max = 0.0f;
+  double activity_sum = 0.0;
+  float* d_mu = nullptr;
+  uint2* d_alias = nullptr;
+  uint8_t* d_mu8 = nullptr;      // palette indices when the map has <= 256 distinct values
+  float* d_mu_table = nullptr;   // the 256-entry palette (exact values)
+};
+
+struct sse_ctx {
+  int device = 0;
+  sse_scanner_desc sc{};
+  sse_sino_desc sn{};
+  sse_physics_desc ph{};
+  uint64_t n_bins = 0;
+  double kn511 = 0.0;
+  std::vector<Phantom> phantoms;
+  void* d_lut = nullptr;
+  int lut_type = -1;
+  sse_lut_desc lut{};
+  float* d_sens = nullptr;
+  int sens_tof = 0;
+  float* d_scratch[2] = {nullptr, nullptr};
+};
+
+namespace sse_detail {
+
+extern thread_local std::string g_error;
+sse_status fail(sse_status st, const std::string& msg);
+sse_status hip_fail(hipError_t e, const char* what);
+void release(void* p);
+Phantom* get_phantom(sse_ctx* c, sse_phantom_id id);
+// Kernel parameters of histories [h0, h0 + n) of a phantom (outputs unset).
+void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, uint64_t h0, uint64_t n,
+                            sse::TransportParams& p);
+
+}  // namespace sse_detail
+
+#define HIP_TRY(expr, what)                                       \
+  do {                                                            \
+    hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) return sse_detail::hip_fail(e_, what);  \
+  } while (0)

@@ -71,6 +71,23 @@ __host__ __device__ inline double kn_total(double a) {
 
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream);
 
+// One sub-chunk of a request: histories [h0, h0 + n) of items[item].
+struct WorkChunk {
+  uint64_t h0;
+  uint32_t n;
+  uint32_t item;
+};
+
+// A list of sub-chunks over several requests, simulated by one launch.
+struct BatchParams {
+  const TransportParams* items;  // device array, one per request slot
+  const WorkChunk* chunks;       // device array
+  uint32_t n_chunks;
+  uint32_t* counter;             // device, reset by the launcher
+};
+
+hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
+
 struct PostParams {
   int n_rad, n_view, n_plane, n_tof;
 };

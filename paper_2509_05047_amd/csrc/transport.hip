@@ -248,22 +248,15 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // ---------------------------------------------------------------------------
 // kInstr = true: the instrumented instantiation (statistics counters and
 // per-history records); false: the production path, with neither.
+// Simulate histories [next, end) of one wavefront.  mu_tab is the palette
+// (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
+// only when kInstr).
 template <bool kInstr>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_kernel(TransportParams p) {
+__device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
+                                              unsigned long long* s_stats, const float* mu_tab) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-  const uint64_t per = p.n / nwaves, rem = p.n % nwaves;
-  uint64_t next = p.h0 + wave * per + (wave < rem ? wave : rem);
-  const uint64_t end = next + per + (wave < rem ? 1 : 0);
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
-
-  __shared__ unsigned long long s_stats[kStatCount];
-  __shared__ float s_mu_table[256];
-  if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
-  if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
-  __syncthreads();
 
   int phase = kEmit;
   int side = 0;                       // 0 photon A, 1 photon B
@@ -413,7 +406,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
             const float qy = py + t * dy;
             const float qz = pz + t * dz;
             const uint32_t vox = voxel_at(p, qx, qy, qz);
-            const float mu = p.mu8 ? s_mu_table[p.mu8[vox]] : p.mu[vox];
+            const float mu = p.mu8 ? mu_tab[p.mu8[vox]] : p.mu[vox];
             const bool real = r.uniform() * p.mu_maj < mu;
             SSE_COUNT(kStReal, real);
             if (real) {
@@ -669,10 +662,55 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
       }
     }
   }
+}
+
+// kInstr = true: the instrumented instantiation (statistics counters and
+// per-history records); false: the production path, with neither.  Every
+// wavefront owns a contiguous share of [h0, h0 + n).
+template <bool kInstr>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_kernel(TransportParams p) {
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  const uint64_t per = p.n / nwaves, rem = p.n % nwaves;
+  const uint64_t begin = p.h0 + wave * per + (wave < rem ? wave : rem);
+  const uint64_t end = begin + per + (wave < rem ? 1 : 0);
+  __shared__ unsigned long long s_stats[kStatCount];
+  __shared__ float s_mu_table[256];
+  if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
+  if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
+  __syncthreads();
+  run_histories<kInstr>(p, begin, end, s_stats, s_mu_table);
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
       atomicAdd(p.stats + threadIdx.x, s_stats[threadIdx.x]);
+  }
+}
+
+// Work-list form for the request server: wavefronts claim sub-chunks
+// (request, history range) from a device counter until the list is
+// exhausted; each sub-chunk carries its own request's parameters.  The
+// palette table is per wavefront because neighbouring wavefronts may work
+// on different requests.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_batch_kernel(BatchParams b) {
+  __shared__ float s_tab[4][256];
+  const uint32_t lane = threadIdx.x & 63u;
+  float* tab = s_tab[threadIdx.x >> 6];
+  for (;;) {
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(b.counter, 1u);
+    c = __builtin_amdgcn_readfirstlane(__shfl(c, 0, 64));
+    if (c >= b.n_chunks) break;
+    const WorkChunk ch = b.chunks[c];
+    const TransportParams& p = b.items[ch.item];
+    if (p.mu8) {
+      for (uint32_t i = lane; i < 256u; i += 64u) tab[i] = p.mu_table[i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, tab);
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -697,6 +735,24 @@ hipError_t launch(const TransportParams& p, hipStream_t stream) {
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
   return (p.stats || p.rec) ? launch<true>(p, stream) : launch<false>(p, stream);
+}
+
+__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+
+hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
+  if (b.n_chunks == 0) return hipSuccess;
+  constexpr int kBlock = 256;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, transport_batch_kernel, kBlock, 0);
+  if (e != hipSuccess) return e;
+  const uint64_t resident = static_cast<uint64_t>(cus) * static_cast<uint64_t>(per_cu > 0 ? per_cu : 1);
+  const uint64_t want = (static_cast<uint64_t>(b.n_chunks) + 3) / 4;  // one chunk per wave at least
+  const int grid = static_cast<int>(want < resident ? want : resident);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
+  hipLaunchKernelGGL(transport_batch_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
+  return hipGetLastError();
 }
 
 }  // namespace sse

@@ -23,7 +23,7 @@ def declared_symbols():
 
 def test_library_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) >= 15
+    assert len(names) >= 22
     lib = sse.lib()
     for n in names:
         assert hasattr(lib, n), n
@@ -41,6 +41,10 @@ def test_structure_sizes_match_header_layout():
     assert C.sizeof(sse.PhantomDesc) == 36
     assert C.sizeof(sse.LutDesc) == 28
     assert C.sizeof(sse.Outputs) == 56
+    assert C.sizeof(sse.ServerCfg) == 32
+    assert C.sizeof(sse.Request) == 48
+    assert C.sizeof(sse.Completion) == 64
+    assert C.sizeof(sse.ServerStats) == 64
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
