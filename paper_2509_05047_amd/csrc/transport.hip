@@ -210,18 +210,27 @@ __device__ __forceinline__ float lut_value(const TransportParams& p, uint32_t i)
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-// Crystal, ring and flat LUT index of a single detected at (hx, hy, hz) with
-// direction (dx, dy, dz) and energy E.
-__device__ void index_single(const TransportParams& p, float hx_, float hy_, float hz, float dx, float dy, float dz,
-                             float E, int& crystal, int& ring, uint32_t& lut) {
-  double phi = atan2(static_cast<double>(hy_), static_cast<double>(hx_));
+// Crystal of a single detected at (hx, hy): azimuth in [0, 2 pi) in binary64.
+__device__ __forceinline__ int crystal_of(const TransportParams& p, float hx, float hy) {
+  double phi = atan2(static_cast<double>(hy), static_cast<double>(hx));
   if (phi < 0.0) phi += kTwoPi;
   const double fc = floor(phi * static_cast<double>(p.n_crystals) / kTwoPi);
-  const int c = fc >= static_cast<double>(p.n_crystals) ? p.n_crystals - 1 : (fc < 0.0 ? 0 : static_cast<int>(fc));
-  const int rg = clamp_floor((hz + p.half_len) / p.pitch, p.n_rings);
-  crystal = c;
-  ring = rg;
-  const int ie = clamp_floor((E - p.e_min) * p.e_scale, p.d0);
+  return fc >= static_cast<double>(p.n_crystals) ? p.n_crystals - 1 : (fc < 0.0 ? 0 : static_cast<int>(fc));
+}
+
+__device__ __forceinline__ int ring_of(const TransportParams& p, float hz) {
+  return clamp_floor((hz + p.half_len) / p.pitch, p.n_rings);
+}
+
+__device__ __forceinline__ int energy_bin(const TransportParams& p, float E) {
+  return clamp_floor((E - p.e_min) * p.e_scale, p.d0);
+}
+
+// Flat LUT index of a single: energy bin, transaxial and axial incidence
+// angles relative to the radial direction at the hit, crystal-in-module and
+// ring-in-block positions.
+__device__ __forceinline__ uint32_t lut_index(const TransportParams& p, float hx_, float hy_, float dx, float dy,
+                                              float dz, int ie, int c, int rg) {
   const double hx = static_cast<double>(hx_), hy = static_cast<double>(hy_);
   const double rho = sqrt(hx * hx + hy * hy);
   const double dr = (hx * static_cast<double>(dx) + hy * static_cast<double>(dy)) / rho;
@@ -230,7 +239,16 @@ __device__ void index_single(const TransportParams& p, float hx_, float hy_, flo
   const int ia = angle_bin(atan2(static_cast<double>(dz), dr), p.d2);
   const int ct = ((c % p.cmod) * p.d3) / p.cmod;
   const int ca = ((rg % p.rblk) * p.d4) / p.rblk;
-  lut = static_cast<uint32_t>((((ie * p.d1 + it) * p.d2 + ia) * p.d3 + ct) * p.d4 + ca);
+  return static_cast<uint32_t>((((ie * p.d1 + it) * p.d2 + ia) * p.d3 + ct) * p.d4 + ca);
+}
+
+// Crystal, ring and flat LUT index of a single detected at (hx, hy, hz) with
+// direction (dx, dy, dz) and energy E.
+__device__ void index_single(const TransportParams& p, float hx, float hy, float hz, float dx, float dy, float dz,
+                             float E, int& crystal, int& ring, uint32_t& lut) {
+  crystal = crystal_of(p, hx, hy);
+  ring = ring_of(p, hz);
+  lut = lut_index(p, hx, hy, dx, dy, dz, energy_bin(p, E), crystal, ring);
 }
 
 // q = v / d for v < 2^24 and d >= 1: binary32 reciprocal estimate (off by at
@@ -244,16 +262,38 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 }
 
 // ---------------------------------------------------------------------------
+// coincidence queue
+// ---------------------------------------------------------------------------
+// Pairs with both singles in the energy window are rare (about one history in
+// twenty) but their evaluation -- two crystal and LUT look-ups with binary64
+// atan2, the sinogram geometry, the TOF jitter and the atomic update -- is
+// long.  Done where photon B ends, it would run with a few lanes active in
+// almost every iteration.  Instead each wavefront appends such pairs to a
+// ring in LDS and evaluates them 64 at a time, one pair per lane.  The jitter
+// is drawn from the history's own stream at the position photon B left it,
+// so the result is the one an in-place evaluation gives.
+constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
+constexpr int kSingleWords = 7;      // hx, hy, dx, dy, dz, path, ring | energy bin << 16
+enum QueueWord {
+  kQhLo = 0, kQhHi, kQPos, kQFlags, kQA, kQB = kQA + kSingleWords, kQueueWords = kQB + kSingleWords
+};
+struct CoincQueue {
+  uint32_t e[kQueueWords][kQueueCap];  // structure of arrays; entry i at column (head + i) mod cap
+  uint32_t a[kSingleWords][64];        // photon A of each lane's current history
+};
+
+// ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 // kInstr = true: the instrumented instantiation (statistics counters and
 // per-history records); false: the production path, with neither.
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
-// only when kInstr).
+// only when kInstr); cq the wavefront's coincidence queue.
 template <bool kInstr>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
-                                              unsigned long long* s_stats, const float* mu_tab) {
+                                              unsigned long long* s_stats, const float* mu_tab,
+                                              CoincQueue* cq) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
@@ -263,10 +303,13 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   uint64_t h = 0;
   uint32_t* rec = nullptr;            // this history's record, if sampled
   float ex = 0.f, ey = 0.f, ez = 0.f, edx = 0.f, edy = 0.f, edz = 0.f;  // emission point, direction of A
-  // photon A summary
-  uint32_t a_cr = 0, a_lut = 0, a_steps = 0;
-  float a_path = 0.f;
+  // photon A summary (its in-window hit data wait in cq->a)
+  uint32_t a_steps = 0;
   bool a_det = false, a_win = false, a_scat = false;
+  // coincidence queue: head and length are wave-uniform, changed only at
+  // converged points; `pushed` marks a lane that appended in this iteration
+  uint32_t q_head = 0, q_count = 0;
+  bool pushed = false;
   // photon state
   float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, texit = 0.f, len = 0.f;
   ECoef ec = p.e511;
@@ -276,16 +319,121 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   r.start(0);
   r.w0 = r.w1 = r.w2 = r.w3 = r.w4 = r.w5 = r.w6 = r.w7 = 0;
 
-  // Standard normal by Marsaglia's polar method from the history's stream.
-  auto polar_normal = [&]() -> float {
+  // Standard normal by Marsaglia's polar method from stream q (the lane's
+  // own, or a copy re-positioned in a history's stream).  Blocks below
+  // `known` were generated before and are not counted again.
+  auto polar_normal = [&](Rng& q, uint32_t known) -> float {
     for (int i = 0; i < kMaxTries; ++i) {
-      RNG_NEED(2u);
-      const float a = 2.0f * r.uniform() - 1.0f;
-      const float b = 2.0f * r.uniform() - 1.0f;
+      if (__any(q.left < 2u)) {
+        const bool g = q.left <= 4u;
+        if (g) q.refill(k0, k1);
+        SSE_COUNT(kStRngBlocks, g && q.blk > known);
+      }
+      const float a = 2.0f * q.uniform() - 1.0f;
+      const float b = 2.0f * q.uniform() - 1.0f;
       const float s = a * a + b * b;
       if (s < 1.0f) return a * static_cast<float>(sqrt(-2.0 * log(static_cast<double>(s)) / static_cast<double>(s)));
     }
     return 0.0f;
+  };
+
+  // Evaluate queued pairs head .. head+n-1 (n <= 64), one per lane: crystals,
+  // ring difference and radial acceptance, TOF bin with jitter, LUT weight,
+  // sinogram update.  Called at converged points only.
+  auto drain = [&](uint32_t head, uint32_t n) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < n) {
+      const uint32_t c = (head + lane) & (kQueueCap - 1u);
+      const uint64_t hh = static_cast<uint64_t>(cq->e[kQhLo][c]) | (static_cast<uint64_t>(cq->e[kQhHi][c]) << 32);
+      const uint32_t pos = cq->e[kQPos][c], flags = cq->e[kQFlags][c];
+      const float ax = __uint_as_float(cq->e[kQA + 0][c]), ay = __uint_as_float(cq->e[kQA + 1][c]);
+      const float bx = __uint_as_float(cq->e[kQB + 0][c]), by = __uint_as_float(cq->e[kQB + 1][c]);
+      const uint32_t arie = cq->e[kQA + 6][c], brie = cq->e[kQB + 6][c];
+      const bool scattered = (flags & 0x100u) != 0u;
+      const int cA = crystal_of(p, ax, ay), cB = crystal_of(p, bx, by);
+      const int rA = static_cast<int>(arie & 0xffffu), rB = static_cast<int>(brie & 0xffffu);
+      uint32_t outcome;
+      uint64_t bin = ~0ull;
+      float w = 0.0f, tau = 0.0f;
+      if (cA == cB) {
+        outcome = 4;
+      } else if (p.max_ring_diff >= 0 && abs(rA - rB) > p.max_ring_diff) {
+        outcome = 5;
+      } else {
+        const int nc = p.n_crystals;
+        int k = cA + cB + 1;
+        int rho = nc / 2 - abs(cA - cB);
+        if (k >= nc) { k -= nc; rho = -rho; }
+        const int view = k >> 1;
+        int m = (2 * cA + 1 - k) % (2 * nc);
+        if (m < 0) m += 2 * nc;
+        const bool a_pos = m > 0 && m < nc;
+        const int half = (p.n_rad - 1) / 2;
+        if (abs(rho) > half) {
+          outcome = 6;
+        } else {
+          const float apath = __uint_as_float(cq->e[kQA + 5][c]), bpath = __uint_as_float(cq->e[kQB + 5][c]);
+          tau = a_pos ? (bpath - apath) * 0.5f : (apath - bpath) * 0.5f;
+          if (p.tof_sigma > 0.0f) {
+            // the history's stream where photon B left it: word `pos`, with
+            // blocks below (pos + buffered) / 4 generated then
+            Rng q;
+            q.start(hh);
+            q.blk = pos >> 2;
+            const uint32_t known = (pos + (flags & 0xffu)) >> 2;
+            SSE_COUNT(kStRngBlocks, q.blk >= known);
+            q.refill(k0, k1);
+            for (uint32_t i = 0; i < (pos & 3u); ++i) q.take();
+            tau = tau + p.tof_sigma * polar_normal(q, known);
+          }
+          const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
+          if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
+            outcome = 7;
+          } else {
+            const uint64_t tof = static_cast<uint64_t>(floorf(xt));
+            const uint64_t plane = static_cast<uint64_t>(rA + rB);
+            bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
+                   static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
+                  static_cast<uint64_t>(rho + half);
+            const uint32_t la = lut_index(p, ax, ay, __uint_as_float(cq->e[kQA + 2][c]),
+                                          __uint_as_float(cq->e[kQA + 3][c]), __uint_as_float(cq->e[kQA + 4][c]),
+                                          static_cast<int>(arie >> 16), cA, rA);
+            const uint32_t lb = lut_index(p, bx, by, __uint_as_float(cq->e[kQB + 2][c]),
+                                          __uint_as_float(cq->e[kQB + 3][c]), __uint_as_float(cq->e[kQB + 4][c]),
+                                          static_cast<int>(brie >> 16), cB, rB);
+            w = lut_value(p, la) * lut_value(p, lb);
+            if (scattered) {
+              outcome = 0;
+              atomicAdd(p.sc_n + bin, 1u);
+              unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
+            } else {
+              outcome = 1;
+              if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
+              if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
+            }
+          }
+        }
+      }
+      SSE_COUNT(kStScatter, outcome == 0);
+      SSE_COUNT(kStTrue, outcome == 1);
+      SSE_COUNT(kStRejSame, outcome == 4);
+      SSE_COUNT(kStRejRing, outcome == 5);
+      SSE_COUNT(kStRejRadial, outcome == 6);
+      SSE_COUNT(kStRejTof, outcome == 7);
+      if (kInstr && p.rec) {
+        const uint64_t off = hh - p.h0;
+        if (off % p.rec_stride == 0) {
+          uint32_t* rc = p.rec + (off / p.rec_stride) * kRecordWords;
+          rc[0] = outcome | (scattered ? 0x100u : 0u);
+          rc[1] = static_cast<uint32_t>(bin);
+          rc[2] = static_cast<uint32_t>(bin >> 32);
+          rc[4] = __float_as_uint(w);
+          rc[5] = __float_as_uint(tau);
+        }
+      }
+    }
   };
 
   for (;;) {
@@ -310,7 +458,9 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       }
       next += __popcll(needmask);
     }
-    if (__all(phase == kDone)) break;
+    // every lane done: leave once the queue is empty
+    const bool all_done = __all(phase == kDone);
+    if (all_done && q_count == 0u) break;
     // Converged top-up: every live lane ends with at least five buffered
     // words (a new history gets eight, enough for its emission).
 #pragma unroll
@@ -537,7 +687,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             hz = zz;
             path = len + tc;
             if (p.e_fwhm > 0.0f) {
-              const float nrm = polar_normal();
+              const float nrm = polar_normal(r, 0u);
               const float sig = (p.e_fwhm / 2.35482f) * sqrtf(kMec2 / ec.E);
               edet = ec.E * (1.0f + sig * nrm);
             }
@@ -552,28 +702,36 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       }
       const bool det = fate == kDetected;
       const bool win = det && edet >= p.e_lo && edet <= p.e_hi;
-      int cry = 0, rng = 0;
-      uint32_t lidx = 0xffffffffu;
-      if (win) index_single(p, hx, hy, hz, dx, dy, dz, ec.E, cry, rng, lidx);
       SSE_COUNT(kStInWindow, win);
-      const uint32_t cr = win ? (static_cast<uint32_t>(cry) | (static_cast<uint32_t>(rng) << 16)) : 0xffffffffu;
       if (kInstr && rec) {
+        int cry = 0, rng = 0;
+        uint32_t lidx = 0xffffffffu;
+        if (win) index_single(p, hx, hy, hz, dx, dy, dz, ec.E, cry, rng, lidx);
         uint32_t* w = rec + 8 + 12 * side;
         w[0] = __float_as_uint(hx); w[1] = __float_as_uint(hy); w[2] = __float_as_uint(hz);
         w[3] = __float_as_uint(dx); w[4] = __float_as_uint(dy); w[5] = __float_as_uint(dz);
         w[6] = __float_as_uint(ec.E); w[7] = __float_as_uint(edet); w[8] = __float_as_uint(path);
-        w[9] = cr;
+        w[9] = win ? (static_cast<uint32_t>(cry) | (static_cast<uint32_t>(rng) << 16)) : 0xffffffffu;
         w[10] = win ? lidx : 0xffffffffu;
         w[11] = static_cast<uint32_t>(nC) | (static_cast<uint32_t>(nR) << 8) | (static_cast<uint32_t>(fate) << 16);
       }
+      // what the coincidence evaluation needs of an in-window single
+      const uint32_t rie = win ? (static_cast<uint32_t>(ring_of(p, hz)) |
+                                  (static_cast<uint32_t>(energy_bin(p, ec.E)) << 16)) : 0u;
       if (side == 0) {
         a_det = det;
         a_win = win;
-        a_cr = cr;
-        a_lut = lidx;
-        a_path = path;
         a_scat = (nC + nR) > 0;
         a_steps = steps;
+        if (win) {
+          cq->a[0][lane] = __float_as_uint(hx);
+          cq->a[1][lane] = __float_as_uint(hy);
+          cq->a[2][lane] = __float_as_uint(dx);
+          cq->a[3][lane] = __float_as_uint(dy);
+          cq->a[4][lane] = __float_as_uint(dz);
+          cq->a[5][lane] = __float_as_uint(path);
+          cq->a[6][lane] = rie;
+        }
         // photon B: back to back with A
         side = 1;
         px = ex; py = ey; pz = ez;
@@ -587,79 +745,53 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         phase = kTrack;
       } else {
         // ---------------- coincidence -------------------------------------
+        // Not both detected (outcome 2) or not both in the window (3) is
+        // decided here; pairs in the window go to the queue.
         const bool scattered = a_scat || (nC + nR) > 0;
-        uint32_t outcome;
-        uint64_t bin = ~0ull;
-        float w = 0.0f, tau = 0.0f;
-        if (!a_det || !det) {
-          outcome = 2;
-        } else if (!a_win || !win) {
-          outcome = 3;
-        } else {
-          const int cA = static_cast<int>(a_cr & 0xffffu), rA = static_cast<int>(a_cr >> 16);
-          if (cA == cry) {
-            outcome = 4;
-          } else if (p.max_ring_diff >= 0 && abs(rA - rng) > p.max_ring_diff) {
-            outcome = 5;
-          } else {
-            const int n = p.n_crystals;
-            int k = cA + cry + 1;
-            int rho = n / 2 - abs(cA - cry);
-            if (k >= n) { k -= n; rho = -rho; }
-            const int view = k >> 1;
-            int m = (2 * cA + 1 - k) % (2 * n);
-            if (m < 0) m += 2 * n;
-            const bool a_pos = m > 0 && m < n;
-            const int half = (p.n_rad - 1) / 2;
-            if (abs(rho) > half) {
-              outcome = 6;
-            } else {
-              tau = a_pos ? (path - a_path) * 0.5f : (a_path - path) * 0.5f;
-              if (p.tof_sigma > 0.0f) {
-                tau = tau + p.tof_sigma * polar_normal();
-              }
-              const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
-              if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
-                outcome = 7;
-              } else {
-                const uint64_t tof = static_cast<uint64_t>(floorf(xt));
-                const uint64_t plane = static_cast<uint64_t>(rA + rng);
-                bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
-                       static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
-                      static_cast<uint64_t>(rho + half);
-                w = lut_value(p, a_lut) * lut_value(p, lidx);
-                if (scattered) {
-                  outcome = 0;
-                  atomicAdd(p.sc_n + bin, 1u);
-                  unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
-                } else {
-                  outcome = 1;
-                  if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
-                  if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
-                }
-              }
-            }
-          }
+        const bool both = a_win && win;
+        const uint64_t bm = __ballot(both);
+        if (both) {
+          const uint32_t c = (q_head + q_count + static_cast<uint32_t>(__popcll(bm & below))) & (kQueueCap - 1u);
+          cq->e[kQhLo][c] = static_cast<uint32_t>(h);
+          cq->e[kQhHi][c] = static_cast<uint32_t>(h >> 32);
+          cq->e[kQPos][c] = r.blk * 4u - r.left;
+          cq->e[kQFlags][c] = r.left | (scattered ? 0x100u : 0u);
+#pragma unroll
+          for (int i = 0; i < kSingleWords; ++i) cq->e[kQA + i][c] = cq->a[i][lane];
+          cq->e[kQB + 0][c] = __float_as_uint(hx);
+          cq->e[kQB + 1][c] = __float_as_uint(hy);
+          cq->e[kQB + 2][c] = __float_as_uint(dx);
+          cq->e[kQB + 3][c] = __float_as_uint(dy);
+          cq->e[kQB + 4][c] = __float_as_uint(dz);
+          cq->e[kQB + 5][c] = __float_as_uint(path);
+          cq->e[kQB + 6][c] = rie;
         }
+        pushed = both;
         SSE_COUNT(kStHist, true);
-        SSE_COUNT(kStScatter, outcome == 0);
-        SSE_COUNT(kStTrue, outcome == 1);
-        SSE_COUNT(kStRejWindow, outcome == 3);
-        SSE_COUNT(kStRejSame, outcome == 4);
-        SSE_COUNT(kStRejRing, outcome == 5);
-        SSE_COUNT(kStRejRadial, outcome == 6);
-        SSE_COUNT(kStRejTof, outcome == 7);
+        SSE_COUNT(kStRejWindow, a_det && det && !both);
         if (kInstr && rec) {
-          rec[0] = outcome | (scattered ? 0x100u : 0u);
-          rec[1] = static_cast<uint32_t>(bin);
-          rec[2] = static_cast<uint32_t>(bin >> 32);
-          rec[4] = __float_as_uint(w);
-          rec[5] = __float_as_uint(tau);
+          if (!both) {
+            rec[0] = ((a_det && det) ? 3u : 2u) | (scattered ? 0x100u : 0u);
+            rec[1] = 0xffffffffu;
+            rec[2] = 0xffffffffu;
+            rec[4] = 0u;
+            rec[5] = 0u;
+          }
           rec[6] = a_steps + steps;
           rec[7] = 0u;
         }
         phase = kEmit;
       }
+    }
+
+    // ---------------- queue bookkeeping (converged) -----------------------
+    q_count += static_cast<uint32_t>(__popcll(__ballot(pushed)));
+    pushed = false;
+    if (q_count >= 64u || all_done) {
+      const uint32_t n = q_count < 64u ? q_count : 64u;
+      drain(q_head, n);
+      q_head = (q_head + n) & (kQueueCap - 1u);
+      q_count -= n;
     }
   }
 }
@@ -676,10 +808,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
   const uint64_t end = begin + per + (wave < rem ? 1 : 0);
   __shared__ unsigned long long s_stats[kStatCount];
   __shared__ float s_mu_table[256];
+  __shared__ CoincQueue s_queue[4];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
-  run_histories<kInstr>(p, begin, end, s_stats, s_mu_table);
+  run_histories<kInstr>(p, begin, end, s_stats, s_mu_table, &s_queue[threadIdx.x >> 6]);
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
@@ -694,6 +827,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
 // on different requests.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
+  __shared__ CoincQueue s_queue[4];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   for (;;) {
@@ -709,7 +843,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, tab);
+    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, tab, &s_queue[threadIdx.x >> 6]);
     __builtin_amdgcn_wave_barrier();
   }
 }
