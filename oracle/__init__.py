@@ -80,6 +80,7 @@ def _lib(variant: str = "f32"):
         lib.orc_philox.argtypes = [_P, _P, _P]
         lib.orc_u01.argtypes = [C.c_uint32]
         lib.orc_u01.restype = C.c_float
+        lib.orc_neg_log.argtypes = [_P, _P, C.c_uint64]
         lib.orc_emit.argtypes = [_P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, _P]
         lib.orc_sample_compton.argtypes = [C.c_uint64, C.c_double, C.c_uint64, _P, _P]
         lib.orc_sample_rayleigh.argtypes = [C.c_uint64, C.c_double, C.c_float, C.c_uint64, _P]
@@ -165,6 +166,14 @@ def sample_rayleigh(seed, e_kev, beta, n, variant="f32"):
     ct = np.zeros(n)
     _lib(variant).orc_sample_rayleigh(seed, e_kev, beta, n, _ptr(ct))
     return ct
+
+
+def neg_log(u, variant="f32"):
+    """-ln(u) as the free-path sampling of the given oracle build evaluates it."""
+    u = np.ascontiguousarray(u, dtype=np.float32)
+    out = np.empty_like(u)
+    _lib(variant).orc_neg_log(_ptr(u), _ptr(out), u.size)
+    return out
 
 
 def energy_model(physics: dict, e_kev: float):

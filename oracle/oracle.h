@@ -120,6 +120,9 @@ int orc_simulate(const orc_scanner* sc, const orc_sino* sn, const orc_physics* p
 /* Test hooks on the building blocks. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 float orc_u01(uint32_t x);
+/* -ln(u) for n uniforms as the transport's free-path sampling evaluates it
+ * (binary32 build: the faithful binary32 logarithm; binary64: the library's). */
+void orc_neg_log(const float* u, float* out, uint64_t n);
 /* Emission of history h: voxel, position and direction of photon A. */
 void orc_emit(const orc_phantom* pd, const uint32_t* alias_thresh, const uint32_t* alias_idx,
               uint64_t seed, uint64_t h, uint32_t* voxel, double pos[3], double dir[3]);

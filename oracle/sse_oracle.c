@@ -123,8 +123,46 @@ float orc_u01(uint32_t x) { return (float)((x >> 8) | 1u) * 5.9604644775390625e-
 
 static real u01(rng_t* r) { return (real)((next32(r) >> 8) | 1u) * R(5.9604644775390625e-08); }
 
-/* -ln(u), evaluated in binary64 and rounded once to the transport precision. */
-static real neg_log(real u) { return (real)(-log((double)u)); }
+/* -ln(u) of a transport uniform u in (0, 1], the free-path sample of the
+ * Woodcock step (Methods, "Scatter simulator description").
+ *
+ * Binary64 build: the library logarithm.  Binary32 build: a faithful
+ * logarithm (error below one unit in the last place for every uniform the
+ * generator can produce) defined operation by operation, so that any IEEE
+ * binary32 arithmetic without contraction gives the same bits:
+ *   u = f 2^e with f in [sqrt(1/2), sqrt(2))         (frexp, exact)
+ *   s = f - 1                                        (exact)
+ *   r = s / (2 + s),  z = r^2,  ln f = 2 atanh(r)
+ *   2 atanh(r) = 2 r + r R,  R = 2z/3 + 2z^2/5 + 2z^3/7 + 2z^4/9 (Taylor; the
+ *     next term is below 2e-9 relative for |r| <= 0.172)
+ *   ln f = s - (s^2/2 - r (s^2/2 + R))                (the same value,
+ *     arranged so that the exact s is not rounded -- the split used by the
+ *     fdlibm logarithm; it rests on 2 r = s - r s)
+ *   -ln u = n ln2 - ln f,  n = -e,  ln 2 = hi + lo with n * hi exact. */
+static float neg_log_f32(float u) {
+  int e;
+  float f = frexpf(u, &e);
+  if (f < 0.70710678f) {
+    f = f + f;
+    e -= 1;
+  }
+  const float s = f - 1.0f;
+  const float r = s / (2.0f + s);
+  const float z = r * r;
+  const float R = z * (2.0f / 3.0f + z * (2.0f / 5.0f + z * (2.0f / 7.0f + z * (2.0f / 9.0f))));
+  const float hfsq = 0.5f * s * s;
+  const float lnf = s - (hfsq - r * (hfsq + R));
+  const float n = (float)(-e);
+  return n * 0.693145751953125f + (n * 1.4286068e-06f - lnf);
+}
+
+static real neg_log(real u) {
+  return sizeof(real) == sizeof(float) ? (real)neg_log_f32((float)u) : (real)(-log((double)u));
+}
+
+void orc_neg_log(const float* u, float* out, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = (float)neg_log((real)u[i]);
+}
 
 /* Standard normal by Marsaglia's polar method (Marsaglia & Bray 1964). */
 static real std_normal(rng_t* r) {

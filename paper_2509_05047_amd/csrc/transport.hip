@@ -132,7 +132,30 @@ struct Rng {
     }                                                \
   } while (0)
 
-__device__ __forceinline__ float neg_log(float u) { return static_cast<float>(-log(static_cast<double>(u))); }
+// -ln(u) for a uniform u in (0, 1]: a faithful binary32 logarithm (error
+// below one unit in the last place for every uniform the generator makes),
+// fixed operation by operation so that it is reproducible bit for bit:
+// u = f 2^e with f in [sqrt(1/2), sqrt(2)); s = f - 1 (exact);
+// ln f = 2 atanh(r), r = s / (2 + s), whose Taylor series to z^4, z = r^2,
+// is arranged as s - (s^2/2 - r (s^2/2 + R)) so the exact s is not rounded
+// (the split of the fdlibm logarithm); -ln u = n ln 2 - ln f, n = -e, with
+// ln 2 split so that n times its leading part is exact.
+__device__ __forceinline__ float neg_log(float u) {
+  int e;
+  float f = frexpf(u, &e);
+  if (f < 0.70710678f) {
+    f = f + f;
+    e -= 1;
+  }
+  const float s = f - 1.0f;
+  const float r = s / (2.0f + s);
+  const float z = r * r;
+  const float R = z * (2.0f / 3.0f + z * (2.0f / 5.0f + z * (2.0f / 7.0f + z * (2.0f / 9.0f))));
+  const float hfsq = 0.5f * s * s;
+  const float lnf = s - (hfsq - r * (hfsq + R));
+  const float n = static_cast<float>(-e);
+  return n * 0.693145751953125f + (n * 1.4286068e-06f - lnf);
+}
 
 // ---------------------------------------------------------------------------
 // physics
@@ -181,11 +204,9 @@ __device__ __forceinline__ float box_exit(const TransportParams& p, float px, fl
   return t;
 }
 
+// floor(f) clamped to [0, n - 1]; NaN gives 0 (maximum returns the number).
 __device__ __forceinline__ int clamp_floor(float f, int n) {
-  f = floorf(f);
-  if (!(f >= 0.0f)) return 0;
-  if (f >= static_cast<float>(n)) return n - 1;
-  return static_cast<int>(f);
+  return static_cast<int>(fminf(fmaxf(floorf(f), 0.0f), static_cast<float>(n - 1)));
 }
 
 __device__ __forceinline__ uint32_t voxel_at(const TransportParams& p, float x, float y, float z) {
@@ -290,9 +311,13 @@ struct CoincQueue {
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
 // only when kInstr); cq the wavefront's coincidence queue.
+// The palette pointer is typed as LDS so that its reads are LDS reads even
+// where the compiler merges them with the binary32-map path.
+typedef const __attribute__((address_space(3))) float LdsFloat;
+
 template <bool kInstr>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
-                                              unsigned long long* s_stats, const float* mu_tab,
+                                              unsigned long long* s_stats, LdsFloat* mu_tab,
                                               CoincQueue* cq) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
@@ -556,7 +581,9 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             const float qy = py + t * dy;
             const float qz = pz + t * dz;
             const uint32_t vox = voxel_at(p, qx, qy, qz);
-            const float mu = p.mu8 ? mu_tab[p.mu8[vox]] : p.mu[vox];
+            float mu;
+            if (p.mu8) mu = mu_tab[p.mu8[vox]];
+            else mu = p.mu[vox];
             const bool real = r.uniform() * p.mu_maj < mu;
             SSE_COUNT(kStReal, real);
             if (real) {
@@ -812,7 +839,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
-  run_histories<kInstr>(p, begin, end, s_stats, s_mu_table, &s_queue[threadIdx.x >> 6]);
+  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table),
+                        &s_queue[threadIdx.x >> 6]);
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
@@ -843,7 +871,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, tab, &s_queue[threadIdx.x >> 6]);
+    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab),
+                         &s_queue[threadIdx.x >> 6]);
     __builtin_amdgcn_wave_barrier();
   }
 }
