@@ -93,6 +93,7 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
   p.e_scale = static_cast<float>(c->lut.dims[0]) / (c->lut.e_max_kev - c->lut.e_min_kev);
   p.seed = seed;
   p.h0 = h0;
+  p.rec_h0 = h0;
   p.n = n;
 }
 

@@ -58,6 +58,7 @@ struct TransportParams {
   unsigned long long* stats;
   uint32_t* rec;
   uint64_t rec_stride;
+  uint64_t rec_h0;          // record k is history rec_h0 + k * rec_stride
 };
 
 // Total Klein-Nishina cross section in units of 2 pi r_e^2, a = E / m_e c^2.

@@ -78,13 +78,59 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
   } while (0)
 
 // A history's random stream: the 32-bit words of Philox blocks 0, 1, 2, ...
-// with counter (block, h_lo, h_hi, 0).  Up to eight words are buffered in a
-// shift register w0..w7 (w0 next).  refill() appends the next block; a lane
-// may refill whenever it holds at most four words, so a refill that one lane
-// needs is shared by every lane of the wave with room (Philox then runs
-// mostly converged instead of once per lane at scattered points).  No
-// dynamically indexed registers.
-struct Rng {
+// with counter (block, h_lo, h_hi, 0), consumed in order.
+//
+// Lane streams keep up to eight words in LDS, in a column of eight slots per
+// lane (slot i of lane l at word 64 i + l, so a wave's accesses hit distinct
+// banks).  Block b goes to slots 4 (b mod 2) .. +3, and words are read from
+// slot rd, advancing mod 8; a lane may generate its next block whenever it
+// holds at most four words (its other half is then free), so a refill that
+// one lane needs is shared by every lane of the wave with room and Philox
+// runs mostly converged.  Reading a word is one LDS load: no register
+// shuffling and no dynamically indexed registers.
+typedef __attribute__((address_space(3))) uint32_t LdsWord;
+
+__device__ __forceinline__ float to_uniform(uint32_t x) {
+  // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
+  return static_cast<float>((x >> 8) | 1u) * 5.9604644775390625e-08f;
+}
+
+struct LaneRng {
+  LdsWord* col;  // this lane's column
+  uint32_t hlo, hhi, blk, left, rd;
+
+  __device__ __forceinline__ void start(uint64_t h) {
+    hlo = static_cast<uint32_t>(h);
+    hhi = static_cast<uint32_t>(h >> 32);
+    blk = 0;
+    left = 0;
+    rd = 0;
+  }
+  __device__ __forceinline__ bool room() const { return left <= 4u; }
+  __device__ __forceinline__ void refill(uint32_t k0, uint32_t k1) {
+    uint32_t b0, b1, b2, b3;
+    philox(blk, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
+    LdsWord* d = col + ((blk & 1u) << 8);  // slots 4 (blk mod 2) .. +3
+    d[0] = b0;
+    d[64] = b1;
+    d[128] = b2;
+    d[192] = b3;
+    ++blk;
+    left += 4;
+  }
+  __device__ __forceinline__ uint32_t take() {
+    const uint32_t x = col[rd << 6];
+    rd = (rd + 1u) & 7u;
+    --left;
+    return x;
+  }
+  __device__ __forceinline__ float uniform() { return to_uniform(take()); }
+};
+
+// A stream held in registers (a shift register w0..w7, w0 next, with the
+// same refill rule): the re-positioned copy of a history's stream that the
+// coincidence evaluation draws the TOF jitter from.
+struct RegRng {
   uint32_t hlo, hhi, blk, left;
   uint32_t w0, w1, w2, w3, w4, w5, w6, w7;
 
@@ -94,6 +140,7 @@ struct Rng {
     blk = 0;
     left = 0;
   }
+  __device__ __forceinline__ bool room() const { return left <= 4u; }
   __device__ __forceinline__ void refill(uint32_t k0, uint32_t k1) {
     uint32_t b0, b1, b2, b3;
     philox(blk, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
@@ -110,15 +157,12 @@ struct Rng {
     left = L + 4;
   }
   __device__ __forceinline__ uint32_t take() {
-    const uint32_t r = w0;
+    const uint32_t x = w0;
     w0 = w1; w1 = w2; w2 = w3; w3 = w4; w4 = w5; w5 = w6; w6 = w7;
     --left;
-    return r;
+    return x;
   }
-  // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
-  __device__ __forceinline__ float uniform() {
-    return static_cast<float>((take() >> 8) | 1u) * 5.9604644775390625e-08f;
-  }
+  __device__ __forceinline__ float uniform() { return to_uniform(take()); }
 };
 
 // Make sure every active lane holds at least k (<= 4) words: if any lane is
@@ -295,8 +339,11 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // so the result is the one an in-place evaluation gives.
 constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
 constexpr int kSingleWords = 7;      // hx, hy, dx, dy, dz, path, ring | energy bin << 16
+// kQh: history minus the first history of the wavefront's run (a run never
+// spans 2^32 histories); kQPos: stream word where photon B ended; kQFlags:
+// words it held buffered then | scattered << 8.
 enum QueueWord {
-  kQhLo = 0, kQhHi, kQPos, kQFlags, kQA, kQB = kQA + kSingleWords, kQueueWords = kQB + kSingleWords
+  kQh = 0, kQPos, kQFlags, kQA, kQB = kQA + kSingleWords, kQueueWords = kQB + kSingleWords
 };
 struct CoincQueue {
   uint32_t e[kQueueWords][kQueueCap];  // structure of arrays; entry i at column (head + i) mod cap
@@ -318,7 +365,7 @@ typedef const __attribute__((address_space(3))) float LdsFloat;
 template <bool kInstr>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
                                               unsigned long long* s_stats, LdsFloat* mu_tab,
-                                              CoincQueue* cq) {
+                                              CoincQueue* cq, LdsWord* rng_buf) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
@@ -340,17 +387,18 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   ECoef ec = p.e511;
   int nC = 0, nR = 0, nint = 0, fate = kEscaped;
   uint32_t steps = 0;
-  Rng r;
+  const uint64_t base = next;         // queue entries hold h - base (< 2^32)
+  LaneRng r;
+  r.col = rng_buf + lane;
   r.start(0);
-  r.w0 = r.w1 = r.w2 = r.w3 = r.w4 = r.w5 = r.w6 = r.w7 = 0;
 
   // Standard normal by Marsaglia's polar method from stream q (the lane's
   // own, or a copy re-positioned in a history's stream).  Blocks below
   // `known` were generated before and are not counted again.
-  auto polar_normal = [&](Rng& q, uint32_t known) -> float {
+  auto polar_normal = [&](auto& q, uint32_t known) -> float {
     for (int i = 0; i < kMaxTries; ++i) {
       if (__any(q.left < 2u)) {
-        const bool g = q.left <= 4u;
+        const bool g = q.room();
         if (g) q.refill(k0, k1);
         SSE_COUNT(kStRngBlocks, g && q.blk > known);
       }
@@ -371,7 +419,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < n) {
       const uint32_t c = (head + lane) & (kQueueCap - 1u);
-      const uint64_t hh = static_cast<uint64_t>(cq->e[kQhLo][c]) | (static_cast<uint64_t>(cq->e[kQhHi][c]) << 32);
+      const uint64_t hh = base + cq->e[kQh][c];
       const uint32_t pos = cq->e[kQPos][c], flags = cq->e[kQFlags][c];
       const float ax = __uint_as_float(cq->e[kQA + 0][c]), ay = __uint_as_float(cq->e[kQA + 1][c]);
       const float bx = __uint_as_float(cq->e[kQB + 0][c]), by = __uint_as_float(cq->e[kQB + 1][c]);
@@ -404,7 +452,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           if (p.tof_sigma > 0.0f) {
             // the history's stream where photon B left it: word `pos`, with
             // blocks below (pos + buffered) / 4 generated then
-            Rng q;
+            RegRng q;
             q.start(hh);
             q.blk = pos >> 2;
             const uint32_t known = (pos + (flags & 0xffu)) >> 2;
@@ -448,7 +496,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       SSE_COUNT(kStRejRadial, outcome == 6);
       SSE_COUNT(kStRejTof, outcome == 7);
       if (kInstr && p.rec) {
-        const uint64_t off = hh - p.h0;
+        const uint64_t off = hh - p.rec_h0;
         if (off % p.rec_stride == 0) {
           uint32_t* rc = p.rec + (off / p.rec_stride) * kRecordWords;
           rc[0] = outcome | (scattered ? 0x100u : 0u);
@@ -474,7 +522,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           r.start(h);
           rec = nullptr;
           if (kInstr && p.rec) {
-            const uint64_t off = h - p.h0;
+            const uint64_t off = h - p.rec_h0;
             if (off % p.rec_stride == 0) rec = p.rec + (off / p.rec_stride) * kRecordWords;
           }
         } else {
@@ -779,8 +827,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         const uint64_t bm = __ballot(both);
         if (both) {
           const uint32_t c = (q_head + q_count + static_cast<uint32_t>(__popcll(bm & below))) & (kQueueCap - 1u);
-          cq->e[kQhLo][c] = static_cast<uint32_t>(h);
-          cq->e[kQhHi][c] = static_cast<uint32_t>(h >> 32);
+          cq->e[kQh][c] = static_cast<uint32_t>(h - base);
           cq->e[kQPos][c] = r.blk * 4u - r.left;
           cq->e[kQFlags][c] = r.left | (scattered ? 0x100u : 0u);
 #pragma unroll
@@ -836,11 +883,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
   __shared__ unsigned long long s_stats[kStatCount];
   __shared__ float s_mu_table[256];
   __shared__ CoincQueue s_queue[4];
+  __shared__ uint32_t s_rng[4 * 8 * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
-  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table),
-                        &s_queue[threadIdx.x >> 6]);
+  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), &s_queue[threadIdx.x >> 6],
+                        (LdsWord*)(s_rng + (threadIdx.x >> 6) * 512u));
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
@@ -856,6 +904,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
   __shared__ CoincQueue s_queue[4];
+  __shared__ uint32_t s_rng[4 * 8 * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   for (;;) {
@@ -871,8 +920,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab),
-                         &s_queue[threadIdx.x >> 6]);
+    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab), &s_queue[threadIdx.x >> 6],
+                         (LdsWord*)(s_rng + (threadIdx.x >> 6) * 512u));
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -896,8 +945,19 @@ hipError_t launch(const TransportParams& p, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
-  if (p.n == 0) return hipSuccess;
-  return (p.stats || p.rec) ? launch<true>(p, stream) : launch<false>(p, stream);
+  // Runs of 2^32 histories at most per launch, so that a wavefront's share
+  // fits the queue's 32-bit history offsets; results do not depend on the
+  // split.
+  constexpr uint64_t kMaxPerLaunch = 1ull << 32;
+  for (uint64_t done = 0; done < p.n;) {
+    TransportParams q = p;
+    q.h0 = p.h0 + done;
+    q.n = p.n - done < kMaxPerLaunch ? p.n - done : kMaxPerLaunch;
+    const hipError_t e = (p.stats || p.rec) ? launch<true>(q, stream) : launch<false>(q, stream);
+    if (e != hipSuccess) return e;
+    done += q.n;
+  }
+  return hipSuccess;
 }
 
 __global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }

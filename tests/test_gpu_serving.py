@@ -75,10 +75,13 @@ def same(a, b):
 
 def test_requests_are_the_same_alone_and_in_the_mix():
     ctx, pids = tiny_ctx()
-    reqs = [(pids[0], 250_000, 11, 0), (pids[1], 170_000, 12, 0), (pids[2], 90_000, 13, 0),
+    # The first request fills the first two ticks (two are kept in flight);
+    # the small ones, submitted meanwhile, then share the next tick with it,
+    # whatever the kernel's speed.
+    reqs = [(pids[0], 20_000_000, 11, 0), (pids[1], 170_000, 12, 0), (pids[2], 90_000, 13, 0),
             (pids[0], 40_000, 14, 1_000_000), (pids[1], 1, 15, 7)]
     ref = [alone(ctx, *r) for r in reqs]
-    srv = sse.Server(ctx, max_active=4, tick_histories=60_000, chunk_histories=4096)
+    srv = sse.Server(ctx, max_active=4, tick_histories=5_000_000, chunk_histories=4096)
     own_c = torch.full((ctx.n_bins,), 7, dtype=torch.int32, device="cuda")   # caller-owned, not zeroed by us
     own_w = torch.full((ctx.n_bins,), 3.0, dtype=torch.float64, device="cuda")
     ids = []
