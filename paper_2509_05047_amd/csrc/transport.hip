@@ -125,6 +125,12 @@ struct LaneRng {
     return x;
   }
   __device__ __forceinline__ float uniform() { return to_uniform(take()); }
+  // word k ahead of the next one, not consumed (k < left for a valid word)
+  __device__ __forceinline__ uint32_t peek(uint32_t k) const { return col[((rd + k) & 7u) << 6]; }
+  __device__ __forceinline__ void advance(uint32_t k) {
+    rd = (rd + k) & 7u;
+    left -= k;
+  }
 };
 
 // A stream held in registers (a shift register w0..w7, w0 next, with the
@@ -337,6 +343,10 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // ring in LDS and evaluates them 64 at a time, one pair per lane.  The jitter
 // is drawn from the history's own stream at the position photon B left it,
 // so the result is the one an in-place evaluation gives.
+// Lanes left stepping when a wave moves on to its events (measured best
+// between 4 and 10 on the clinical workload).
+constexpr int kStepTail = 6;
+
 constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
 constexpr int kSingleWords = 7;      // hx, hy, dx, dy, dz, path, ring | energy bin << 16
 // kQh: history minus the first history of the wavefront's run (a run never
@@ -603,46 +613,52 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       phase = kTrack;
     }
 
-    // ---------------- Woodcock steps until every lane has an event ---------
+    // ---------------- Woodcock steps until most lanes have an event --------
     // The step is cheap; the expensive branches below (interaction, photon
     // end, emission) then run once per outer iteration for all lanes that
-    // need them, instead of once per step.
-    while (__any(phase == kTrack)) {
+    // need them, instead of once per step.  The loop stops when at most
+    // kStepTail lanes are still stepping (they go on in the next iteration)
+    // rather than waiting for the longest run of steps in the wave -- unless
+    // no lane has anything else to do.
+    while (__any(phase == kTrack) && (__popcll(__ballot(phase == kTrack)) > kStepTail ||
+                                      !__any(phase != kTrack && phase != kDone))) {
       if (__any(phase == kTrack && r.left < 2u)) {
         const bool g = phase != kDone && r.left <= 4u;
         if (g) r.refill(k0, k1);
         SSE_COUNT(kStRngBlocks, g);
       }
-      if (phase == kTrack) {
-        if (steps >= static_cast<uint32_t>(kMaxSteps)) {
-          fate = kCapped;
-          phase = kFinish;
-        } else {
-          ++steps;
-          SSE_COUNT(kStSteps, true);
-          const float s = neg_log(r.uniform()) * ec.inv_maj;
-          t = t + s;
-          if (!(t < texit)) {
-            phase = kFinish;  // leaves the voxel box: straight to the cylinder
-          } else {
-            const float qx = px + t * dx;
-            const float qy = py + t * dy;
-            const float qz = pz + t * dz;
-            const uint32_t vox = voxel_at(p, qx, qy, qz);
-            float mu;
-            if (p.mu8) mu = mu_tab[p.mu8[vox]];
-            else mu = p.mu[vox];
-            const bool real = r.uniform() * p.mu_maj < mu;
-            SSE_COUNT(kStReal, real);
-            if (real) {
-              px = qx; py = qy; pz = qz;
-              len = len + t;
-              t = 0.0f;
-              phase = kInteract;
-            }
-          }
-        }
+      // One tentative step per tracking lane, written with selects rather
+      // than branches (a masked lane costs the same issue slot): the step's
+      // two words are read ahead and consumed only as far as the step uses
+      // them -- the distance word when it steps, the acceptance word when the
+      // point is inside the voxel box.
+      const bool trk = phase == kTrack;
+      const bool go = trk && steps < static_cast<uint32_t>(kMaxSteps);
+      const uint32_t x0 = r.peek(0u), x1 = r.peek(1u);
+      const float tn = t + neg_log(to_uniform(x0)) * ec.inv_maj;
+      const bool inside = go && tn < texit;
+      const float qx = px + tn * dx;
+      const float qy = py + tn * dy;
+      const float qz = pz + tn * dz;
+      const uint32_t vox = voxel_at(p, qx, qy, qz);  // clamped: a valid index for every lane
+      float mu = 0.0f;
+      if (inside) {
+        if (p.mu8) mu = mu_tab[p.mu8[vox]];
+        else mu = p.mu[vox];
       }
+      const bool real = inside && to_uniform(x1) * p.mu_maj < mu;
+      SSE_COUNT(kStSteps, go);
+      SSE_COUNT(kStReal, real);
+      r.advance((go ? 1u : 0u) + (inside ? 1u : 0u));
+      steps += go ? 1u : 0u;
+      fate = (trk && !go) ? static_cast<int>(kCapped) : fate;
+      // capped or out of the voxel box: to the cylinder; real: interaction
+      phase = trk ? (real ? kInteract : (inside ? kTrack : kFinish)) : phase;
+      len = real ? len + tn : len;
+      t = real ? 0.0f : (go ? tn : t);
+      px = real ? qx : px;
+      py = real ? qy : py;
+      pz = real ? qz : pz;
     }
 
     // ---------------- real interactions ----------------------------------
