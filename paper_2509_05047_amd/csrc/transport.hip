@@ -33,7 +33,9 @@ constexpr double kPi = 3.141592653589793;
 constexpr double kTwoPi = 6.283185307179586;
 constexpr double kHalfPi = 1.5707963267948966;
 
-enum Phase { kEmit = 0, kTrack = 1, kInteract = 2, kFinish = 3, kDone = 4 };
+// kCompton and kAzimuth are rejection samplings that may take several
+// iterations of the wave's loop (a bounded number of rounds per iteration).
+enum Phase { kEmit = 0, kTrack = 1, kInteract = 2, kFinish = 3, kDone = 4, kCompton = 5, kAzimuth = 6 };
 enum Fate { kDetected = 0, kAbsorbed = 1, kKilled = 2, kCapped = 3, kAxial = 4, kEscaped = 5 };
 enum Stat {
   kStHist = 0, kStSteps, kStReal, kStCompton, kStRayleigh, kStAbsorbed, kStKilled, kStCapped, kStEscaped,
@@ -346,6 +348,9 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // Lanes left stepping when a wave moves on to its events (measured best
 // between 4 and 10 on the clinical workload).
 constexpr int kStepTail = 6;
+// Rejection rounds per iteration for the Compton and azimuth samplers; a
+// lane still rejecting goes on in the next iteration with its try count.
+constexpr int kRounds = 2;
 
 constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
 constexpr int kSingleWords = 7;      // hx, hy, dx, dy, dz, path, ring | energy bin << 16
@@ -397,6 +402,8 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   ECoef ec = p.e511;
   int nC = 0, nR = 0, nint = 0, fate = kEscaped;
   uint32_t steps = 0;
+  int tries = 0;                      // of the rejection sampling in progress
+  float ct = 1.0f;                    // cosine of the scattering angle, until the azimuth is drawn
   const uint64_t base = next;         // queue entries hold h - base (< 2^32)
   LaneRng r;
   r.col = rng_buf + lane;
@@ -669,45 +676,9 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       } else {
         RNG_NEED(4u);
         const float ug = r.uniform() * ec.g;
-        float ct = 1.0f;
-        bool alive = true;
+        tries = 0;
         if (ug < ec.cC) {
-          // Klein-Nishina by Kahn's rejection method: x = E / E'
-          const float twoa = 2.0f * ec.alpha;
-          const float b1 = 1.0f + twoa;
-          const float b2 = 9.0f + twoa;
-          float x = 0.0f;
-          bool ok = false;
-          for (int i = 0; i < kMaxTries && !ok; ++i) {
-            RNG_NEED(3u);
-            const float r1 = r.uniform();
-            const float r2 = r.uniform();
-            const float r3 = r.uniform();
-            if (r1 * b2 <= b1) {
-              const float xx = 1.0f + twoa * r2;
-              if (r3 * (xx * xx) <= 4.0f * (xx - 1.0f)) { x = xx; ok = true; }
-            } else {
-              const float xx = b1 / (1.0f + twoa * r2);
-              const float c = 1.0f + (1.0f - xx) / ec.alpha;
-              if (2.0f * r3 <= c * c + 1.0f / xx) { x = xx; ok = true; }
-            }
-          }
-          if (!ok) {
-            fate = kAbsorbed;
-            alive = false;
-          } else {
-            SSE_COUNT(kStCompton, true);
-            const float e2 = ec.E / x;
-            ct = 1.0f - (x - 1.0f) / ec.alpha;
-            ct = fminf(fmaxf(ct, -1.0f), 1.0f);
-            ++nC;
-            if (e2 < p.e_kill) {
-              fate = kKilled;
-              alive = false;
-            } else {
-              energy_coefficients(ec, e2, p);
-            }
-          }
+          phase = kCompton;
         } else if (ug < ec.cCR) {
           // Rayleigh: form factor by inversion, Thomson factor by rejection
           const float bp = p.rayleigh_beta * (ec.alpha * ec.alpha);
@@ -725,19 +696,80 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           }
           if (!ok) {
             fate = kAbsorbed;
-            alive = false;
+            phase = kFinish;
           } else {
             SSE_COUNT(kStRayleigh, true);
             ++nR;
+            phase = kAzimuth;
           }
         } else {
           fate = kAbsorbed;
-          alive = false;
+          phase = kFinish;
         }
-        if (alive) {
-          // uniform azimuth from a point in the unit disk
-          float cp = 1.0f, sp = 0.0f;
-          for (int i = 0; i < kMaxTries; ++i) {
+      }
+    }
+
+    // ---------------- Compton: Klein-Nishina by Kahn's method --------------
+    // x = E / E'; at most kMaxTries tries in all, kRounds per iteration.
+    if (__any(phase == kCompton)) {
+      bool acc = false;
+      float x = 0.0f;
+      for (int k = 0; k < kRounds; ++k) {
+        if (!__any(phase == kCompton && !acc)) break;
+        if (phase == kCompton && !acc) {
+          if (tries >= kMaxTries) {
+            fate = kAbsorbed;
+            phase = kFinish;
+          } else {
+            ++tries;
+            RNG_NEED(3u);
+            const float twoa = 2.0f * ec.alpha;
+            const float b1 = 1.0f + twoa;
+            const float b2 = 9.0f + twoa;
+            const float r1 = r.uniform();
+            const float r2 = r.uniform();
+            const float r3 = r.uniform();
+            if (r1 * b2 <= b1) {
+              const float xx = 1.0f + twoa * r2;
+              if (r3 * (xx * xx) <= 4.0f * (xx - 1.0f)) { x = xx; acc = true; }
+            } else {
+              const float xx = b1 / (1.0f + twoa * r2);
+              const float c = 1.0f + (1.0f - xx) / ec.alpha;
+              if (2.0f * r3 <= c * c + 1.0f / xx) { x = xx; acc = true; }
+            }
+          }
+        }
+      }
+      if (acc) {
+        SSE_COUNT(kStCompton, true);
+        const float e2 = ec.E / x;
+        ct = 1.0f - (x - 1.0f) / ec.alpha;
+        ct = fminf(fmaxf(ct, -1.0f), 1.0f);
+        ++nC;
+        if (e2 < p.e_kill) {
+          fate = kKilled;
+          phase = kFinish;
+        } else {
+          energy_coefficients(ec, e2, p);
+          tries = 0;
+          phase = kAzimuth;
+        }
+      }
+    }
+
+    // ---------------- azimuth, new direction -----------------------------
+    // Uniform azimuth from a point in the unit disk (at most kMaxTries tries
+    // in all, then azimuth 0), kRounds tries per iteration.
+    if (__any(phase == kAzimuth)) {
+      bool got = false;
+      float cp = 1.0f, sp = 0.0f;
+      for (int k = 0; k < kRounds; ++k) {
+        if (!__any(phase == kAzimuth && !got)) break;
+        if (phase == kAzimuth && !got) {
+          if (tries >= kMaxTries) {
+            got = true;
+          } else {
+            ++tries;
             RNG_NEED(2u);
             const float a = 2.0f * r.uniform() - 1.0f;
             const float b = 2.0f * r.uniform() - 1.0f;
@@ -745,15 +777,15 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             if (s2 < 1.0f) {
               cp = (a * a - b * b) / s2;
               sp = (2.0f * a * b) / s2;
-              break;
+              got = true;
             }
           }
-          rotate(dx, dy, dz, ct, cp, sp);
-          texit = box_exit(p, px, py, pz, dx, dy, dz);
-          phase = kTrack;
-        } else {
-          phase = kFinish;
         }
+      }
+      if (got) {
+        rotate(dx, dy, dz, ct, cp, sp);
+        texit = box_exit(p, px, py, pz, dx, dy, dz);
+        phase = kTrack;
       }
     }
 
