@@ -81,6 +81,8 @@ def _lib(variant: str = "f32"):
         lib.orc_u01.argtypes = [C.c_uint32]
         lib.orc_u01.restype = C.c_float
         lib.orc_neg_log.argtypes = [_P, _P, C.c_uint64]
+        lib.orc_sincos_2pi.argtypes = [_P, _P, _P, C.c_uint64]
+        lib.orc_transport_coefs.argtypes = [_P, C.c_float, _P]
         lib.orc_emit.argtypes = [_P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, _P]
         lib.orc_sample_compton.argtypes = [C.c_uint64, C.c_double, C.c_uint64, _P, _P]
         lib.orc_sample_rayleigh.argtypes = [C.c_uint64, C.c_double, C.c_float, C.c_uint64, _P]
@@ -173,6 +175,22 @@ def neg_log(u, variant="f32"):
     u = np.ascontiguousarray(u, dtype=np.float32)
     out = np.empty_like(u)
     _lib(variant).orc_neg_log(_ptr(u), _ptr(out), u.size)
+    return out
+
+
+def sincos_2pi(u, variant="f32"):
+    """(sin 2 pi u, cos 2 pi u) as the azimuth sampling of the given build evaluates it."""
+    u = np.ascontiguousarray(u, dtype=np.float32)
+    sn, cs = np.empty_like(u), np.empty_like(u)
+    _lib(variant).orc_sincos_2pi(_ptr(u), _ptr(sn), _ptr(cs), u.size)
+    return sn, cs
+
+
+def transport_coefs(physics: dict, e_kev: float, variant="f32"):
+    """(g, fC, fC + fR) at e_kev as the transport of the given build computes them."""
+    out = np.zeros(3, np.float32)
+    p = physics_struct(physics)
+    _lib(variant).orc_transport_coefs(C.byref(p), e_kev, _ptr(out))
     return out
 
 

@@ -123,6 +123,11 @@ float orc_u01(uint32_t x);
 /* -ln(u) for n uniforms as the transport's free-path sampling evaluates it
  * (binary32 build: the faithful binary32 logarithm; binary64: the library's). */
 void orc_neg_log(const float* u, float* out, uint64_t n);
+/* (sin 2 pi u, cos 2 pi u) as the transport's azimuth sampling evaluates it. */
+void orc_sincos_2pi(const float* u, float* sn, float* cs, uint64_t n);
+/* The transport's coefficients g, fC, fC + fR at energy e_kev in the build's
+ * precision (binary32 build: the binary32 energy model). */
+void orc_transport_coefs(const orc_physics* ph, float e_kev, float out[3]);
 /* Emission of history h: voxel, position and direction of photon A. */
 void orc_emit(const orc_phantom* pd, const uint32_t* alias_thresh, const uint32_t* alias_idx,
               uint64_t seed, uint64_t h, uint32_t* voxel, double pos[3], double dir[3]);

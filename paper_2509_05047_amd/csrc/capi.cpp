@@ -68,24 +68,12 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
   p.tof_sigma = c->sn.tof_sigma_mm;
   p.e_lo = c->ph.e_lo_kev; p.e_hi = c->ph.e_hi_kev; p.e_kill = c->ph.e_kill_kev; p.e_fwhm = c->ph.e_fwhm_frac;
   p.rayleigh_beta = c->ph.rayleigh_beta;
-  p.f_c = static_cast<double>(c->ph.f_compton);
-  p.f_r = static_cast<double>(c->ph.f_rayleigh);
-  p.f_p = static_cast<double>(c->ph.f_photo);
-  p.kn511 = c->kn511;
+  p.kc = c->ph.f_compton / sse::kn_total32(1.0f);
+  p.f_r = c->ph.f_rayleigh;
+  p.f_p = c->ph.f_photo;
   p.max_int = c->ph.max_interactions;
-  {  // coefficients at 511 keV, evaluated once on the host
-    sse::ECoef& e = p.e511;
-    e.E = sse::kMec2;
-    e.alpha = e.E / sse::kMec2;
-    const double a = static_cast<double>(e.alpha);
-    const double fc = p.f_c * (sse::kn_total(a) / p.kn511);
-    const double fr = p.f_r * (1.0 / (a * a));
-    const double fp = p.f_p * (1.0 / (a * a * a));
-    e.g = static_cast<float>(fc + fr + fp);
-    e.cC = static_cast<float>(fc);
-    e.cCR = static_cast<float>(fc + fr);
-    e.inv_maj = 1.0f / (p.mu_maj * e.g);
-  }
+  // coefficients at 511 keV, evaluated once on the host (same binary32 model)
+  sse::energy_coefficients(p.e511, sse::kMec2, p.kc, p.f_r, p.f_p, p.mu_maj);
   p.lut = c->d_lut;
   p.lut_type = c->lut_type;
   p.d0 = c->lut.dims[0]; p.d1 = c->lut.dims[1]; p.d2 = c->lut.dims[2]; p.d3 = c->lut.dims[3]; p.d4 = c->lut.dims[4];
@@ -121,7 +109,8 @@ sse_status check_descs(const sse_scanner_desc* s, const sse_sino_desc* n, const 
     return fail(SSE_EINVAL, "bad TOF bin width or jitter");
   if (!(p->e_lo_kev <= p->e_hi_kev) || !std::isfinite(p->e_lo_kev) || !std::isfinite(p->e_hi_kev))
     return fail(SSE_EINVAL, "bad energy window");
-  if (!(p->e_kill_kev >= 0.0f) || !std::isfinite(p->e_kill_kev)) return fail(SSE_EINVAL, "bad kill energy");
+  if (!(p->e_kill_kev >= 100.0f) || !std::isfinite(p->e_kill_kev))
+    return fail(SSE_EINVAL, "kill energy must be >= 100 keV (range of the binary32 energy model)");
   if (!(p->e_fwhm_frac >= 0.0f) || !std::isfinite(p->e_fwhm_frac)) return fail(SSE_EINVAL, "bad energy blur");
   if (!(p->f_compton >= 0.0f) || !(p->f_rayleigh >= 0.0f) || !(p->f_photo >= 0.0f) ||
       !(p->f_compton + p->f_rayleigh + p->f_photo > 0.0f) || !std::isfinite(p->f_compton + p->f_rayleigh + p->f_photo))
@@ -328,7 +317,6 @@ sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner
   c->sn = *sino;
   c->ph = *physics;
   c->n_bins = static_cast<uint64_t>(sino->n_rad) * sino->n_view * sino->n_plane * sino->n_tof;
-  c->kn511 = sse::kn_total(1.0);
   *out = c;
   return SSE_OK;
 }

@@ -27,7 +27,6 @@ struct sse_ctx {
   sse_sino_desc sn{};
   sse_physics_desc ph{};
   uint64_t n_bins = 0;
-  double kn511 = 0.0;
   std::vector<Phantom> phantoms;
   void* d_lut = nullptr;
   int lut_type = -1;

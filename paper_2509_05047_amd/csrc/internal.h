@@ -40,7 +40,7 @@ struct TransportParams {
   float tof_bin, tof_sigma;
   // physics
   float e_lo, e_hi, e_kill, e_fwhm, rayleigh_beta;
-  double f_c, f_r, f_p, kn511;
+  float kc, f_r, f_p;       // energy model: kc = f_C / KN(1), f_R, f_P
   int max_int;
   ECoef e511;               // coefficients at 511 keV (host-evaluated)
   // LUT
@@ -61,13 +61,64 @@ struct TransportParams {
   uint64_t rec_h0;          // record k is history rec_h0 + k * rec_stride
 };
 
-// Total Klein-Nishina cross section in units of 2 pi r_e^2, a = E / m_e c^2.
-__host__ __device__ inline double kn_total(double a) {
-  double L = log(1.0 + 2.0 * a);
-  double t1 = (1.0 + a) / (a * a) * (2.0 * (1.0 + a) / (1.0 + 2.0 * a) - L / a);
-  double t2 = L / (2.0 * a);
-  double t3 = (1.0 + 3.0 * a) / ((1.0 + 2.0 * a) * (1.0 + 2.0 * a));
-  return t1 + t2 - t3;
+// -ln(u) for a positive normal u: a faithful binary32 logarithm (error below
+// one unit in the last place for the transport's uniforms), fixed operation
+// by operation so that host and device, and any IEEE binary32 arithmetic
+// without contraction, give the same bits:
+// u = f 2^e with f in [sqrt(1/2), sqrt(2)); s = f - 1 (exact);
+// ln f = 2 atanh(r), r = s / (2 + s), whose Taylor series to z^4, z = r^2,
+// is arranged as s - (s^2/2 - r (s^2/2 + R)) so the exact s is not rounded
+// (the split of the fdlibm logarithm); -ln u = n ln 2 - ln f, n = -e, with
+// ln 2 split so that n times its leading part is exact.
+__host__ __device__ inline float neg_log32(float u) {
+  int e;
+  float f = frexpf(u, &e);
+  if (f < 0.70710678f) {
+    f = f + f;
+    e -= 1;
+  }
+  const float s = f - 1.0f;
+  const float r = s / (2.0f + s);
+  const float z = r * r;
+  const float R = z * (2.0f / 3.0f + z * (2.0f / 5.0f + z * (2.0f / 7.0f + z * (2.0f / 9.0f))));
+  const float hfsq = 0.5f * s * s;
+  const float lnf = s - (hfsq - r * (hfsq + R));
+  const float n = static_cast<float>(-e);
+  return n * 0.693145751953125f + (n * 1.4286068e-06f - lnf);
+}
+
+// Total Klein-Nishina cross section in units of 2 pi r_e^2, a = E / m_e c^2
+// (Klein and Nishina 1929), in binary32: ln(1 + 2a) by the logarithm above,
+// the quotients through 1/a and 1/(1 + 2a).  Relative error below 2e-5 for
+// E >= 100 keV, the lowest kill energy accepted (cancellation grows as
+// a -> 0).
+__host__ __device__ inline float kn_total32(float a) {
+  const float ia = 1.0f / a;
+  const float b = 1.0f + 2.0f * a;
+  const float i12 = 1.0f / b;
+  const float L = -neg_log32(b);
+  const float t1 = (((1.0f + a) * ia) * ia) * ((2.0f * (1.0f + a)) * i12 - L * ia);
+  const float t2 = (0.5f * L) * ia;
+  const float t3 = ((1.0f + 3.0f * a) * i12) * i12;
+  return (t1 + t2) - t3;
+}
+
+// Coefficients of the separable attenuation model mu(x, E) = mu511(x) g(E),
+// g = fC + fR + fP with fC = kc KN(a) (kc = f_C / KN(1)), fR = f_R / a^2 and
+// fP = f_P / a^3, in binary32 (host and device evaluate it alike).
+__host__ __device__ inline void energy_coefficients(ECoef& c, float E, float kc, float f_r, float f_p,
+                                                    float mu_maj) {
+  c.E = E;
+  c.alpha = E / kMec2;
+  const float a = c.alpha;
+  const float ia = 1.0f / a;
+  const float fc = kc * kn_total32(a);
+  const float fr = f_r * ia * ia;
+  const float fp = f_p * ia * ia * ia;
+  c.g = (fc + fr) + fp;
+  c.cC = fc;
+  c.cCR = fc + fr;
+  c.inv_maj = 1.0f / (mu_maj * c.g);
 }
 
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream);

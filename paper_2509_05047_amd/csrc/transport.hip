@@ -19,7 +19,9 @@
 // lanes that need it.
 //
 // Numerics: binary32 transport with IEEE-rounded + - * / sqrt (no
-// contraction); ln, atan2 and the cross-section formula in binary64, rounded
+// contraction); the free-path logarithm, the azimuth's sine and cosine and
+// the cross-section model in binary32 by fixed operation sequences; the
+// detector-side atan2 and the TOF jitter's logarithm in binary64, rounded
 // once where they feed binary32 values.  Random numbers: one Philox4x32-10
 // stream per history, keyed by the seed and countered by (block, history),
 // consumed in order by the emission, photon A, photon B and the TOF jitter,
@@ -33,8 +35,9 @@ constexpr double kPi = 3.141592653589793;
 constexpr double kTwoPi = 6.283185307179586;
 constexpr double kHalfPi = 1.5707963267948966;
 
-// kCompton and kAzimuth are rejection samplings that may take several
-// iterations of the wave's loop (a bounded number of rounds per iteration).
+// kCompton is a rejection sampling that may take several iterations of the
+// wave's loop (a bounded number of rounds per iteration); kAzimuth draws the
+// azimuth of a scattered photon and turns it.
 enum Phase { kEmit = 0, kTrack = 1, kInteract = 2, kFinish = 3, kDone = 4, kCompton = 5, kAzimuth = 6 };
 enum Fate { kDetected = 0, kAbsorbed = 1, kKilled = 2, kCapped = 3, kAxial = 4, kEscaped = 5 };
 enum Stat {
@@ -184,46 +187,32 @@ struct RegRng {
     }                                                \
   } while (0)
 
-// -ln(u) for a uniform u in (0, 1]: a faithful binary32 logarithm (error
-// below one unit in the last place for every uniform the generator makes),
-// fixed operation by operation so that it is reproducible bit for bit:
-// u = f 2^e with f in [sqrt(1/2), sqrt(2)); s = f - 1 (exact);
-// ln f = 2 atanh(r), r = s / (2 + s), whose Taylor series to z^4, z = r^2,
-// is arranged as s - (s^2/2 - r (s^2/2 + R)) so the exact s is not rounded
-// (the split of the fdlibm logarithm); -ln u = n ln 2 - ln f, n = -e, with
-// ln 2 split so that n times its leading part is exact.
-__device__ __forceinline__ float neg_log(float u) {
-  int e;
-  float f = frexpf(u, &e);
-  if (f < 0.70710678f) {
-    f = f + f;
-    e -= 1;
-  }
-  const float s = f - 1.0f;
-  const float r = s / (2.0f + s);
-  const float z = r * r;
-  const float R = z * (2.0f / 3.0f + z * (2.0f / 5.0f + z * (2.0f / 7.0f + z * (2.0f / 9.0f))));
-  const float hfsq = 0.5f * s * s;
-  const float lnf = s - (hfsq - r * (hfsq + R));
-  const float n = static_cast<float>(-e);
-  return n * 0.693145751953125f + (n * 1.4286068e-06f - lnf);
+// (sin 2 pi u, cos 2 pi u) for u in [0, 1), fixed operation by operation
+// (error below 1.7 * 2^-24 for the transport's uniforms):
+// 4u = q + f with q the quadrant and f in [0, 1) (exact); h = f, or 1 - f
+// when f > 1/2 (sine and cosine swap; exact); y = h pi/2 in [0, pi/4],
+// z = y^2, and the Taylor series of sin y to y^9 and of cos y to y^10 (the
+// first omitted terms are below 2e-9); then the quadrant's signs.
+__device__ __forceinline__ void sincos_2pi(float u, float& sn, float& cs) {
+  const float v = 4.0f * u;
+  const int q = static_cast<int>(floorf(v));
+  const float f = v - static_cast<float>(q);
+  const bool swap = f > 0.5f;
+  const float h = swap ? 1.0f - f : f;
+  const float y = h * 1.5707963267948966f;
+  const float z = y * y;
+  const float s = y + (y * z) * (-1.0f / 6.0f + z * (1.0f / 120.0f + z * (-1.0f / 5040.0f + z * (1.0f / 362880.0f))));
+  const float c =
+      1.0f + z * (-0.5f + z * (1.0f / 24.0f + z * (-1.0f / 720.0f + z * (1.0f / 40320.0f + z * (-1.0f / 3628800.0f)))));
+  const float sf = swap ? c : s, cf = swap ? s : c;
+  const int qq = q & 3;
+  sn = qq == 0 ? sf : (qq == 1 ? cf : (qq == 2 ? -sf : -cf));
+  cs = qq == 0 ? cf : (qq == 1 ? -sf : (qq == 2 ? -cf : sf));
 }
 
 // ---------------------------------------------------------------------------
 // physics
 // ---------------------------------------------------------------------------
-__device__ void energy_coefficients(ECoef& c, float E, const TransportParams& p) {
-  c.E = E;
-  c.alpha = E / kMec2;
-  const double a = static_cast<double>(c.alpha);
-  const double fc = p.f_c * (kn_total(a) / p.kn511);
-  const double fr = p.f_r * (1.0 / (a * a));
-  const double fp = p.f_p * (1.0 / (a * a * a));
-  c.g = static_cast<float>(fc + fr + fp);
-  c.cC = static_cast<float>(fc);
-  c.cCR = static_cast<float>(fc + fr);
-  c.inv_maj = 1.0f / (p.mu_maj * c.g);
-}
 
 __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct, float cp, float sp) {
   const float st = sqrtf((1.0f - ct) * (1.0f + ct));
@@ -348,8 +337,8 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // Lanes left stepping when a wave moves on to its events (measured best
 // between 4 and 10 on the clinical workload).
 constexpr int kStepTail = 6;
-// Rejection rounds per iteration for the Compton and azimuth samplers; a
-// lane still rejecting goes on in the next iteration with its try count.
+// Rejection rounds per iteration for the Compton sampler; a lane still
+// rejecting goes on in the next iteration with its try count.
 constexpr int kRounds = 2;
 
 constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
@@ -591,20 +580,15 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       ex = p.lox + (static_cast<float>(ix) + ux) * p.vx;
       ey = p.loy + (static_cast<float>(iy) + uy) * p.vy;
       ez = p.loz + (static_cast<float>(iz) + uz) * p.vz;
-      // isotropic direction (Marsaglia 1972)
-      edx = 0.0f; edy = 0.0f; edz = 1.0f;
-      for (int i = 0; i < kMaxTries; ++i) {
-        RNG_NEED(2u);
-        const float a = 2.0f * r.uniform() - 1.0f;
-        const float b = 2.0f * r.uniform() - 1.0f;
-        const float s = a * a + b * b;
-        if (s < 1.0f) {
-          const float q = 2.0f * sqrtf(1.0f - s);
-          edx = a * q;
-          edy = b * q;
-          edz = 1.0f - 2.0f * s;
-          break;
-        }
+      // isotropic direction: cos(theta) = 1 - 2 u (exact), azimuth 2 pi u'
+      RNG_NEED(2u);
+      edz = 1.0f - 2.0f * r.uniform();
+      {
+        const float st = sqrtf((1.0f - edz) * (1.0f + edz));
+        float sp, cp;
+        sincos_2pi(r.uniform(), sp, cp);
+        edx = st * cp;
+        edy = st * sp;
       }
       if (kInstr && rec) rec[3] = v;
       // photon A
@@ -642,7 +626,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       const bool trk = phase == kTrack;
       const bool go = trk && steps < static_cast<uint32_t>(kMaxSteps);
       const uint32_t x0 = r.peek(0u), x1 = r.peek(1u);
-      const float tn = t + neg_log(to_uniform(x0)) * ec.inv_maj;
+      const float tn = t + neg_log32(to_uniform(x0)) * ec.inv_maj;
       const bool inside = go && tn < texit;
       const float qx = px + tn * dx;
       const float qy = py + tn * dy;
@@ -750,7 +734,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           fate = kKilled;
           phase = kFinish;
         } else {
-          energy_coefficients(ec, e2, p);
+          energy_coefficients(ec, e2, p.kc, p.f_r, p.f_p, p.mu_maj);
           tries = 0;
           phase = kAzimuth;
         }
@@ -758,35 +742,13 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     }
 
     // ---------------- azimuth, new direction -----------------------------
-    // Uniform azimuth from a point in the unit disk (at most kMaxTries tries
-    // in all, then azimuth 0), kRounds tries per iteration.
-    if (__any(phase == kAzimuth)) {
-      bool got = false;
-      float cp = 1.0f, sp = 0.0f;
-      for (int k = 0; k < kRounds; ++k) {
-        if (!__any(phase == kAzimuth && !got)) break;
-        if (phase == kAzimuth && !got) {
-          if (tries >= kMaxTries) {
-            got = true;
-          } else {
-            ++tries;
-            RNG_NEED(2u);
-            const float a = 2.0f * r.uniform() - 1.0f;
-            const float b = 2.0f * r.uniform() - 1.0f;
-            const float s2 = a * a + b * b;
-            if (s2 < 1.0f) {
-              cp = (a * a - b * b) / s2;
-              sp = (2.0f * a * b) / s2;
-              got = true;
-            }
-          }
-        }
-      }
-      if (got) {
-        rotate(dx, dy, dz, ct, cp, sp);
-        texit = box_exit(p, px, py, pz, dx, dy, dz);
-        phase = kTrack;
-      }
+    if (phase == kAzimuth) {
+      RNG_NEED(1u);
+      float sp, cp;
+      sincos_2pi(r.uniform(), sp, cp);
+      rotate(dx, dy, dz, ct, cp, sp);
+      texit = box_exit(p, px, py, pz, dx, dy, dz);
+      phase = kTrack;
     }
 
     // ---------------- photon finished ------------------------------------

@@ -90,6 +90,7 @@ def _create(scanner, sino, physics):
     lambda s, n, p: p.update(rayleigh_beta=0.0),
     lambda s, n, p: p.update(e_lo_kev=700.0),
     lambda s, n, p: p.update(max_interactions=0),
+    lambda s, n, p: p.update(e_kill_kev=50.0),   # below the binary32 energy model's range
     lambda s, n, p: p.update(f_compton=-1.0),
 ])
 def test_create_rejects_bad_descriptors(mutate):
