@@ -222,6 +222,37 @@ sse::PostParams post_params(const sse_ctx* c) {
   return sse::PostParams{c->sn.n_rad, c->sn.n_view, c->sn.n_plane, c->sn.n_tof};
 }
 
+// Pair buffer for runs of n histories: the records one launch of n needs,
+// at most 2^25 (2.7 GB; longer runs are split into launches), rounded up to
+// 2^16 and grown when needed (halved down to 2^22 while allocation fails).
+sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
+  constexpr uint64_t kDefaultCap = 1ull << 25;
+  constexpr uint64_t kMinCap = 1ull << 22;
+  const uint64_t want = sse::transport_pairs_needed(n);
+  uint64_t cap = want < kDefaultCap ? want : kDefaultCap;
+  cap = (cap + 0xffffull) & ~0xffffull;
+  if (c->d_pairs && c->pair_cap >= cap) return SSE_OK;
+  if (!c->d_pair_count) HIP_TRY(hipMalloc(&c->d_pair_count, sizeof(uint32_t)), "allocate pair counter");
+  if (!c->pair_done) HIP_TRY(hipEventCreateWithFlags(&c->pair_done, hipEventDisableTiming), "create event");
+  if (c->d_pairs) {  // the freeing waits for the device
+    release(c->d_pairs);
+    c->d_pairs = nullptr;
+    c->pair_cap = 0;
+  }
+  for (;;) {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, static_cast<size_t>(sse::kPairWords) * cap * sizeof(uint32_t)) == hipSuccess) {
+      c->d_pairs = static_cast<uint32_t*>(ptr);
+      break;
+    }
+    (void)hipGetLastError();
+    if (cap <= kMinCap) return fail(SSE_ENOMEM, "cannot allocate the pair buffer");
+    cap /= 2;
+  }
+  c->pair_cap = cap;
+  return SSE_OK;
+}
+
 sse_status ensure_scratch(sse_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (!c->d_scratch[i]) HIP_TRY(hipMalloc(&c->d_scratch[i], c->n_bins * sizeof(float)), "allocate smoothing scratch");
@@ -335,6 +366,9 @@ sse_status sse_destroy(sse_ctx* c) {
   if (c->d_sens) release(c->d_sens);
   for (auto* s : c->d_scratch)
     if (s) release(s);
+  if (c->d_pairs) release(c->d_pairs);
+  if (c->d_pair_count) release(c->d_pair_count);
+  if (c->pair_done) (void)hipEventDestroy(c->pair_done);
   delete c;
   return SSE_OK;
 }
@@ -539,7 +573,16 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   p.stats = out->stats;
   p.rec = reinterpret_cast<uint32_t*>(out->records);
   p.rec_stride = out->record_stride;
-  HIP_TRY(sse::launch_transport(p, static_cast<hipStream_t>(stream)), "transport kernel launch");
+  sse_status st = ensure_pairs(c, n_histories);
+  if (st != SSE_OK) return st;
+  p.pairs = c->d_pairs;
+  p.pair_count = c->d_pair_count;
+  p.pair_cap = c->pair_cap;
+  p.item = 0;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamWaitEvent(s, c->pair_done, 0), "order the pair buffer");
+  HIP_TRY(sse::launch_transport(p, s), "transport kernel launch");
+  HIP_TRY(hipEventRecord(c->pair_done, s), "record pair-buffer use");
   return SSE_OK;
 }
 

@@ -34,6 +34,13 @@ struct sse_ctx {
   float* d_sens = nullptr;
   int sens_tof = 0;
   float* d_scratch[2] = {nullptr, nullptr};
+  // pair buffer of the transport -> coincidence hand-over (kPairWords words
+  // per pair), its counter, and an event after its last use so that a call
+  // on another stream waits for it
+  uint32_t* d_pairs = nullptr;
+  uint32_t* d_pair_count = nullptr;
+  uint64_t pair_cap = 0;
+  hipEvent_t pair_done = nullptr;
 };
 
 namespace sse_detail {

@@ -15,6 +15,32 @@ constexpr int kStatCount = 19;
 
 enum LutType { kLutF32 = 0, kLutF16 = 1, kLutBF16 = 2 };
 
+// A coincidence with both singles in the energy window, as the transport
+// kernel hands it to the coincidence kernel: one 80-byte record per pair
+// (written as five 16-byte stores).
+constexpr int kSingleWords = 7;  // per single: hx, hy, dx, dy, dz, path, ring | energy bin << 16
+enum PairWord {
+  kPhLo = 0,   // history, low and high word
+  kPhHi,
+  kPPos,       // word of the history's stream where photon B ended
+  kPFlags,     // words buffered then | scattered << 8 | request slot << 16, or kEmptyPair
+  kPA,         // photon A, kSingleWords words
+  kPB = kPA + kSingleWords,
+  kPairWords = 20  // with two words of padding
+};
+constexpr uint32_t kEmptyPair = 0xffffffffu;  // flags of a padding record
+// Wavefronts reserve the buffer in blocks of kPairBlock records (one atomic
+// per block); the part of a block a wavefront cannot use is padded with
+// empty records.
+constexpr uint32_t kPairBlock = 512;
+constexpr uint64_t kMaxPairCap = 1ull << 31;
+// Records a launch of n histories may reserve when w wavefronts run it: one
+// pair per history at most, each block padded by at most 63 records, plus
+// one partly used block per wavefront.
+inline uint64_t pair_records_needed(uint64_t n, uint64_t w) {
+  return n + (n / (kPairBlock - 64) + 1) * 64 + w * kPairBlock;
+}
+
 // Energy-dependent transport coefficients of the separable attenuation model.
 struct ECoef {
   float E, alpha, g, cC, cCR, inv_maj;
@@ -59,6 +85,12 @@ struct TransportParams {
   uint32_t* rec;
   uint64_t rec_stride;
   uint64_t rec_h0;          // record k is history rec_h0 + k * rec_stride
+  // pair buffer (device): pair_cap records of kPairWords words and the
+  // count of records reserved
+  uint32_t* pairs;
+  uint32_t* pair_count;
+  uint64_t pair_cap;
+  uint32_t item;            // request slot, for the work-list form
 };
 
 // -ln(u) for a positive normal u: a faithful binary32 logarithm (error below
@@ -121,7 +153,16 @@ __host__ __device__ inline void energy_coefficients(ECoef& c, float E, float kc,
   c.inv_maj = 1.0f / (mu_maj * c.g);
 }
 
+// Transport and coincidence evaluation of histories [h0, h0 + n): launches
+// sized to the pair buffer, each a pair-counter reset, the transport kernel
+// and the coincidence kernel, in stream order.
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream);
+// Pair-buffer capacity (records) one launch of n histories needs, and the
+// most histories a launch may take with capacity cap (0 if none).
+uint64_t transport_pairs_needed(uint64_t n);
+uint64_t transport_max_histories(uint64_t cap);
+uint64_t transport_batch_pairs_needed(uint64_t n);
+uint64_t transport_batch_max_histories(uint64_t cap);
 
 // One sub-chunk of a request: histories [h0, h0 + n) of items[item].
 struct WorkChunk {
@@ -136,8 +177,14 @@ struct BatchParams {
   const WorkChunk* chunks;       // device array
   uint32_t n_chunks;
   uint32_t* counter;             // device, reset by the launcher
+  uint64_t n_histories;          // sum of the chunks' lengths
+  uint32_t* pairs;               // the items' common pair buffer
+  uint32_t* pair_count;
+  uint64_t pair_cap;
 };
 
+// One work list (at most transport_batch_max_histories(pair_cap) histories
+// in all): pair-counter reset, transport, coincidences.
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
 
 struct PostParams {

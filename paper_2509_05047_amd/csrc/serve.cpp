@@ -72,6 +72,13 @@ struct sse_server {
   sse::WorkChunk* h_chunks[2] = {nullptr, nullptr};
   uint32_t max_chunks = 0;
   uint32_t* d_counter = nullptr;
+  // pair buffer of the transport -> coincidence hand-over, shared by the
+  // ticks (they run in stream order); a tick is launched in segments of at
+  // most pair_cap histories
+  uint32_t* d_pairs = nullptr;
+  uint32_t* d_pair_count = nullptr;
+  uint64_t pair_cap = 0;
+  uint64_t segment_histories = 0;           // most histories of one segment
   std::deque<Tick> ticks;
   int parity = 0;
   std::thread thread;
@@ -163,6 +170,10 @@ void admit(sse_server* s) {
     build_transport_params(s->ctx, ph, q.r.seed, q.r.h_offset, q.r.n_histories, p);
     p.sc_n = b.counts;
     p.sc_w = b.weights;
+    p.pairs = s->d_pairs;
+    p.pair_count = s->d_pair_count;
+    p.pair_cap = s->pair_cap;
+    p.item = static_cast<uint32_t>(slot);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->d_items + slot, &p, sizeof(p), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) note_error(s, e, "admit request");
@@ -252,8 +263,20 @@ void scheduler(sse_server* s) {
     hipError_t e = hipEventCreateWithFlags(&t.ev, hipEventDisableTiming);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->d_chunks[s->parity], list, nc * sizeof(sse::WorkChunk), hipMemcpyHostToDevice, s->stream);
-    sse::BatchParams b{s->d_items, s->d_chunks[s->parity], nc, s->d_counter};
-    if (e == hipSuccess) e = sse::launch_transport_batch(b, s->stream);
+    // segments of whole chunks of at most pair_cap histories
+    for (uint32_t c0 = 0; c0 < nc && e == hipSuccess;) {
+      uint32_t c1 = c0;
+      uint64_t hist = 0;
+      while (c1 < nc && hist + list[c1].n <= s->segment_histories) hist += list[c1++].n;
+      if (c1 == c0) {  // a chunk larger than the buffer: excluded at start-up
+        e = hipErrorInvalidValue;
+        break;
+      }
+      sse::BatchParams b{s->d_items, s->d_chunks[s->parity] + c0, c1 - c0, s->d_counter,
+                         hist, s->d_pairs, s->d_pair_count, s->pair_cap};
+      e = sse::launch_transport_batch(b, s->stream);
+      c0 = c1;
+    }
     if (e == hipSuccess) e = hipEventRecord(t.ev, s->stream);
     if (e != hipSuccess) note_error(s, e, "tick launch");
     s->ticks.push_back(t);
@@ -270,6 +293,8 @@ void free_server(sse_server* s) {
   release(s->d_chunks[0]);
   release(s->d_chunks[1]);
   release(s->d_counter);
+  release(s->d_pairs);
+  release(s->d_pair_count);
   if (s->h_items) (void)hipHostFree(s->h_items);
   if (s->h_chunks[0]) (void)hipHostFree(s->h_chunks[0]);
   if (s->h_chunks[1]) (void)hipHostFree(s->h_chunks[1]);
@@ -331,6 +356,16 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
       e = hipHostMalloc(reinterpret_cast<void**>(&s->h_chunks[i]), s->max_chunks * sizeof(sse::WorkChunk), hipHostMallocDefault);
   }
   if (e == hipSuccess) e = hipMalloc(&s->d_counter, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&s->d_pair_count, sizeof(uint32_t));
+  if (e == hipSuccess) {
+    // the records a tick needs (one pair per history at most), up to 2^25
+    // (2.7 GB; longer ticks run in segments), and room for one chunk at least
+    uint64_t cap = std::min<uint64_t>(sse::transport_batch_pairs_needed(s->cfg.tick_histories), 1ull << 25);
+    cap = std::max<uint64_t>(cap, sse::transport_batch_pairs_needed(s->cfg.chunk_histories));
+    s->pair_cap = (cap + 0xffffull) & ~0xffffull;
+    s->segment_histories = sse::transport_batch_max_histories(s->pair_cap);
+    e = hipMalloc(&s->d_pairs, static_cast<size_t>(sse::kPairWords) * s->pair_cap * sizeof(uint32_t));
+  }
   if (e != hipSuccess) {
     free_server(s);
     return hip_fail(e, "server resources");

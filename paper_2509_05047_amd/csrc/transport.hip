@@ -324,35 +324,164 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 }
 
 // ---------------------------------------------------------------------------
-// coincidence queue
+// tuning of the transport loop
 // ---------------------------------------------------------------------------
-// Pairs with both singles in the energy window are rare (about one history in
-// twenty) but their evaluation -- two crystal and LUT look-ups with binary64
-// atan2, the sinogram geometry, the TOF jitter and the atomic update -- is
-// long.  Done where photon B ends, it would run with a few lanes active in
-// almost every iteration.  Instead each wavefront appends such pairs to a
-// ring in LDS and evaluates them 64 at a time, one pair per lane.  The jitter
-// is drawn from the history's own stream at the position photon B left it,
-// so the result is the one an in-place evaluation gives.
 // Lanes left stepping when a wave moves on to its events (measured best
 // between 4 and 10 on the clinical workload).
 constexpr int kStepTail = 6;
 // Rejection rounds per iteration for the Compton sampler; a lane still
 // rejecting goes on in the next iteration with its try count.
 constexpr int kRounds = 2;
+// Waves per SIMD the transport kernels are compiled for (registers).
+constexpr int kTransportWavesPerEu = 3;
 
-constexpr uint32_t kQueueCap = 128;  // at most 63 waiting + 64 new ones
-constexpr int kSingleWords = 7;      // hx, hy, dx, dy, dz, path, ring | energy bin << 16
-// kQh: history minus the first history of the wavefront's run (a run never
-// spans 2^32 histories); kQPos: stream word where photon B ended; kQFlags:
-// words it held buffered then | scattered << 8.
-enum QueueWord {
-  kQh = 0, kQPos, kQFlags, kQA, kQB = kQA + kSingleWords, kQueueWords = kQB + kSingleWords
-};
-struct CoincQueue {
-  uint32_t e[kQueueWords][kQueueCap];  // structure of arrays; entry i at column (head + i) mod cap
-  uint32_t a[kSingleWords][64];        // photon A of each lane's current history
-};
+// ---------------------------------------------------------------------------
+// coincidences
+// ---------------------------------------------------------------------------
+// Pairs with both singles in the energy window are rare (about one history
+// in twenty) but their evaluation -- two crystal and LUT look-ups with
+// binary64 atan2, the sinogram geometry, the TOF jitter and the atomic
+// update -- is long and needs most of the detector and sinogram parameters.
+// Inside the transport loop it would run with a few lanes active and keep
+// those parameters live (and spilled) through every Woodcock step, so the
+// transport kernel appends such pairs to a buffer in device memory and the
+// coincidence kernel evaluates them, one pair per lane.  The jitter is drawn
+// from the history's own stream at the position photon B left it, so the
+// result is the one an in-place evaluation gives.
+
+// Standard normal by Marsaglia's polar method from stream q (a lane's own,
+// or a copy re-positioned in a history's stream).  Blocks below `known` were
+// generated before and are not counted again.
+template <bool kInstr, class Q>
+__device__ __forceinline__ float std_normal(Q& q, uint32_t known, const TransportParams& p,
+                                            unsigned long long* s_stats) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
+  for (int i = 0; i < kMaxTries; ++i) {
+    if (__any(q.left < 2u)) {
+      const bool g = q.room();
+      if (g) q.refill(k0, k1);
+      SSE_COUNT(kStRngBlocks, g && q.blk > known);
+    }
+    const float a = 2.0f * q.uniform() - 1.0f;
+    const float b = 2.0f * q.uniform() - 1.0f;
+    const float s = a * a + b * b;
+    if (s < 1.0f) return a * static_cast<float>(sqrt(-2.0 * log(static_cast<double>(s)) / static_cast<double>(s)));
+  }
+  return 0.0f;
+}
+
+// Pair i of the buffer: crystals, ring difference and radial acceptance,
+// TOF bin with jitter, LUT weight, sinogram update (and record and counters
+// in the instrumented form).
+template <bool kInstr>
+__device__ __forceinline__ void evaluate_pair(const TransportParams& p, const uint32_t* pairs, uint64_t i,
+                                              unsigned long long* s_stats) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
+  const uint4* rec4 = reinterpret_cast<const uint4*>(pairs + i * kPairWords);
+  const uint4 q0 = rec4[0];
+  if (q0.w == kEmptyPair) return;
+  const uint4 q1 = rec4[1], q2 = rec4[2], q3 = rec4[3], q4 = rec4[4];
+  const uint32_t words[kPairWords] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y,
+                                      q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w};
+  auto E = [&](int w) -> uint32_t { return words[w]; };
+  {
+    const uint64_t hh = static_cast<uint64_t>(E(kPhLo)) | (static_cast<uint64_t>(E(kPhHi)) << 32);
+    const uint32_t pos = E(kPPos), flags = E(kPFlags);
+    const float ax = __uint_as_float(E(kPA + 0)), ay = __uint_as_float(E(kPA + 1));
+    const float bx = __uint_as_float(E(kPB + 0)), by = __uint_as_float(E(kPB + 1));
+    const uint32_t arie = E(kPA + 6), brie = E(kPB + 6);
+    const bool scattered = (flags & 0x100u) != 0u;
+    const int cA = crystal_of(p, ax, ay), cB = crystal_of(p, bx, by);
+    const int rA = static_cast<int>(arie & 0xffffu), rB = static_cast<int>(brie & 0xffffu);
+    uint32_t outcome;
+    uint64_t bin = ~0ull;
+    float w = 0.0f, tau = 0.0f;
+    if (cA == cB) {
+      outcome = 4;
+    } else if (p.max_ring_diff >= 0 && abs(rA - rB) > p.max_ring_diff) {
+      outcome = 5;
+    } else {
+      const int nc = p.n_crystals;
+      int k = cA + cB + 1;
+      int rho = nc / 2 - abs(cA - cB);
+      if (k >= nc) { k -= nc; rho = -rho; }
+      const int view = k >> 1;
+      int m = (2 * cA + 1 - k) % (2 * nc);
+      if (m < 0) m += 2 * nc;
+      const bool a_pos = m > 0 && m < nc;
+      const int half = (p.n_rad - 1) / 2;
+      if (abs(rho) > half) {
+        outcome = 6;
+      } else {
+        const float apath = __uint_as_float(E(kPA + 5)), bpath = __uint_as_float(E(kPB + 5));
+        tau = a_pos ? (bpath - apath) * 0.5f : (apath - bpath) * 0.5f;
+        if (p.tof_sigma > 0.0f) {
+          // the history's stream where photon B left it: word `pos`, with
+          // blocks below (pos + buffered) / 4 generated then
+          RegRng q;
+          q.start(hh);
+          q.blk = pos >> 2;
+          const uint32_t known = (pos + (flags & 0xffu)) >> 2;
+          SSE_COUNT(kStRngBlocks, q.blk >= known);
+          q.refill(k0, k1);
+          for (uint32_t i = 0; i < (pos & 3u); ++i) q.take();
+          tau = tau + p.tof_sigma * std_normal<kInstr>(q, known, p, s_stats);
+        }
+        const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
+        if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
+          outcome = 7;
+        } else {
+          const uint64_t tof = static_cast<uint64_t>(floorf(xt));
+          const uint64_t plane = static_cast<uint64_t>(rA + rB);
+          bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
+                 static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
+                static_cast<uint64_t>(rho + half);
+          const uint32_t la = lut_index(p, ax, ay, __uint_as_float(E(kPA + 2)),
+                                        __uint_as_float(E(kPA + 3)), __uint_as_float(E(kPA + 4)),
+                                        static_cast<int>(arie >> 16), cA, rA);
+          const uint32_t lb = lut_index(p, bx, by, __uint_as_float(E(kPB + 2)),
+                                        __uint_as_float(E(kPB + 3)), __uint_as_float(E(kPB + 4)),
+                                        static_cast<int>(brie >> 16), cB, rB);
+          w = lut_value(p, la) * lut_value(p, lb);
+          if (scattered) {
+            outcome = 0;
+            atomicAdd(p.sc_n + bin, 1u);
+            unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
+          } else {
+            outcome = 1;
+            if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
+            if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
+          }
+        }
+      }
+    }
+    SSE_COUNT(kStScatter, outcome == 0);
+    SSE_COUNT(kStTrue, outcome == 1);
+    SSE_COUNT(kStRejSame, outcome == 4);
+    SSE_COUNT(kStRejRing, outcome == 5);
+    SSE_COUNT(kStRejRadial, outcome == 6);
+    SSE_COUNT(kStRejTof, outcome == 7);
+    if (kInstr && p.rec) {
+      const uint64_t off = hh - p.rec_h0;
+      if (off % p.rec_stride == 0) {
+        uint32_t* rc = p.rec + (off / p.rec_stride) * kRecordWords;
+        rc[0] = outcome | (scattered ? 0x100u : 0u);
+        rc[1] = static_cast<uint32_t>(bin);
+        rc[2] = static_cast<uint32_t>(bin >> 32);
+        rc[4] = __float_as_uint(w);
+        rc[5] = __float_as_uint(tau);
+      }
+    }
+  }
+}
+
+// Mark records [from, to) of the wavefront's block empty (converged call).
+__device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t from, uint64_t to) {
+  for (uint64_t k = from + (threadIdx.x & 63u); k < to; k += 64u)
+    if (k < p.pair_cap) p.pairs[k * kPairWords + kPFlags] = kEmptyPair;
+}
 
 // ---------------------------------------------------------------------------
 // the kernel
@@ -361,7 +490,8 @@ struct CoincQueue {
 // per-history records); false: the production path, with neither.
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
-// only when kInstr); cq the wavefront's coincidence queue.
+// only when kInstr); stash the wavefront's LDS area for photon A's hit data
+// (kSingleWords columns of 64 lanes).
 // The palette pointer is typed as LDS so that its reads are LDS reads even
 // where the compiler merges them with the binary32-map path.
 typedef const __attribute__((address_space(3))) float LdsFloat;
@@ -369,7 +499,8 @@ typedef const __attribute__((address_space(3))) float LdsFloat;
 template <bool kInstr>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
                                               unsigned long long* s_stats, LdsFloat* mu_tab,
-                                              CoincQueue* cq, LdsWord* rng_buf) {
+                                              LdsWord* stash, LdsWord* rng_buf, uint64_t& res_next,
+                                              uint64_t& res_end) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
@@ -379,13 +510,10 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   uint64_t h = 0;
   uint32_t* rec = nullptr;            // this history's record, if sampled
   float ex = 0.f, ey = 0.f, ez = 0.f, edx = 0.f, edy = 0.f, edz = 0.f;  // emission point, direction of A
-  // photon A summary (its in-window hit data wait in cq->a)
+  // photon A summary (its in-window hit data wait in the stash)
   uint32_t a_steps = 0;
   bool a_det = false, a_win = false, a_scat = false;
-  // coincidence queue: head and length are wave-uniform, changed only at
-  // converged points; `pushed` marks a lane that appended in this iteration
-  uint32_t q_head = 0, q_count = 0;
-  bool pushed = false;
+  bool pushed = false;                // this lane appended a pair in this iteration
   // photon state
   float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, texit = 0.f, len = 0.f;
   ECoef ec = p.e511;
@@ -393,127 +521,10 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   uint32_t steps = 0;
   int tries = 0;                      // of the rejection sampling in progress
   float ct = 1.0f;                    // cosine of the scattering angle, until the azimuth is drawn
-  const uint64_t base = next;         // queue entries hold h - base (< 2^32)
   LaneRng r;
   r.col = rng_buf + lane;
   r.start(0);
 
-  // Standard normal by Marsaglia's polar method from stream q (the lane's
-  // own, or a copy re-positioned in a history's stream).  Blocks below
-  // `known` were generated before and are not counted again.
-  auto polar_normal = [&](auto& q, uint32_t known) -> float {
-    for (int i = 0; i < kMaxTries; ++i) {
-      if (__any(q.left < 2u)) {
-        const bool g = q.room();
-        if (g) q.refill(k0, k1);
-        SSE_COUNT(kStRngBlocks, g && q.blk > known);
-      }
-      const float a = 2.0f * q.uniform() - 1.0f;
-      const float b = 2.0f * q.uniform() - 1.0f;
-      const float s = a * a + b * b;
-      if (s < 1.0f) return a * static_cast<float>(sqrt(-2.0 * log(static_cast<double>(s)) / static_cast<double>(s)));
-    }
-    return 0.0f;
-  };
-
-  // Evaluate queued pairs head .. head+n-1 (n <= 64), one per lane: crystals,
-  // ring difference and radial acceptance, TOF bin with jitter, LUT weight,
-  // sinogram update.  Called at converged points only.
-  auto drain = [&](uint32_t head, uint32_t n) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < n) {
-      const uint32_t c = (head + lane) & (kQueueCap - 1u);
-      const uint64_t hh = base + cq->e[kQh][c];
-      const uint32_t pos = cq->e[kQPos][c], flags = cq->e[kQFlags][c];
-      const float ax = __uint_as_float(cq->e[kQA + 0][c]), ay = __uint_as_float(cq->e[kQA + 1][c]);
-      const float bx = __uint_as_float(cq->e[kQB + 0][c]), by = __uint_as_float(cq->e[kQB + 1][c]);
-      const uint32_t arie = cq->e[kQA + 6][c], brie = cq->e[kQB + 6][c];
-      const bool scattered = (flags & 0x100u) != 0u;
-      const int cA = crystal_of(p, ax, ay), cB = crystal_of(p, bx, by);
-      const int rA = static_cast<int>(arie & 0xffffu), rB = static_cast<int>(brie & 0xffffu);
-      uint32_t outcome;
-      uint64_t bin = ~0ull;
-      float w = 0.0f, tau = 0.0f;
-      if (cA == cB) {
-        outcome = 4;
-      } else if (p.max_ring_diff >= 0 && abs(rA - rB) > p.max_ring_diff) {
-        outcome = 5;
-      } else {
-        const int nc = p.n_crystals;
-        int k = cA + cB + 1;
-        int rho = nc / 2 - abs(cA - cB);
-        if (k >= nc) { k -= nc; rho = -rho; }
-        const int view = k >> 1;
-        int m = (2 * cA + 1 - k) % (2 * nc);
-        if (m < 0) m += 2 * nc;
-        const bool a_pos = m > 0 && m < nc;
-        const int half = (p.n_rad - 1) / 2;
-        if (abs(rho) > half) {
-          outcome = 6;
-        } else {
-          const float apath = __uint_as_float(cq->e[kQA + 5][c]), bpath = __uint_as_float(cq->e[kQB + 5][c]);
-          tau = a_pos ? (bpath - apath) * 0.5f : (apath - bpath) * 0.5f;
-          if (p.tof_sigma > 0.0f) {
-            // the history's stream where photon B left it: word `pos`, with
-            // blocks below (pos + buffered) / 4 generated then
-            RegRng q;
-            q.start(hh);
-            q.blk = pos >> 2;
-            const uint32_t known = (pos + (flags & 0xffu)) >> 2;
-            SSE_COUNT(kStRngBlocks, q.blk >= known);
-            q.refill(k0, k1);
-            for (uint32_t i = 0; i < (pos & 3u); ++i) q.take();
-            tau = tau + p.tof_sigma * polar_normal(q, known);
-          }
-          const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
-          if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
-            outcome = 7;
-          } else {
-            const uint64_t tof = static_cast<uint64_t>(floorf(xt));
-            const uint64_t plane = static_cast<uint64_t>(rA + rB);
-            bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
-                   static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
-                  static_cast<uint64_t>(rho + half);
-            const uint32_t la = lut_index(p, ax, ay, __uint_as_float(cq->e[kQA + 2][c]),
-                                          __uint_as_float(cq->e[kQA + 3][c]), __uint_as_float(cq->e[kQA + 4][c]),
-                                          static_cast<int>(arie >> 16), cA, rA);
-            const uint32_t lb = lut_index(p, bx, by, __uint_as_float(cq->e[kQB + 2][c]),
-                                          __uint_as_float(cq->e[kQB + 3][c]), __uint_as_float(cq->e[kQB + 4][c]),
-                                          static_cast<int>(brie >> 16), cB, rB);
-            w = lut_value(p, la) * lut_value(p, lb);
-            if (scattered) {
-              outcome = 0;
-              atomicAdd(p.sc_n + bin, 1u);
-              unsafeAtomicAdd(p.sc_w + bin, static_cast<double>(w));
-            } else {
-              outcome = 1;
-              if (p.tr_n) atomicAdd(p.tr_n + bin, 1u);
-              if (p.tr_w) unsafeAtomicAdd(p.tr_w + bin, static_cast<double>(w));
-            }
-          }
-        }
-      }
-      SSE_COUNT(kStScatter, outcome == 0);
-      SSE_COUNT(kStTrue, outcome == 1);
-      SSE_COUNT(kStRejSame, outcome == 4);
-      SSE_COUNT(kStRejRing, outcome == 5);
-      SSE_COUNT(kStRejRadial, outcome == 6);
-      SSE_COUNT(kStRejTof, outcome == 7);
-      if (kInstr && p.rec) {
-        const uint64_t off = hh - p.rec_h0;
-        if (off % p.rec_stride == 0) {
-          uint32_t* rc = p.rec + (off / p.rec_stride) * kRecordWords;
-          rc[0] = outcome | (scattered ? 0x100u : 0u);
-          rc[1] = static_cast<uint32_t>(bin);
-          rc[2] = static_cast<uint32_t>(bin >> 32);
-          rc[4] = __float_as_uint(w);
-          rc[5] = __float_as_uint(tau);
-        }
-      }
-    }
-  };
 
   for (;;) {
     // ---------------- take new histories ---------------------------------
@@ -537,9 +548,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       }
       next += __popcll(needmask);
     }
-    // every lane done: leave once the queue is empty
-    const bool all_done = __all(phase == kDone);
-    if (all_done && q_count == 0u) break;
+    if (__all(phase == kDone)) break;
     // Converged top-up: every live lane ends with at least five buffered
     // words (a new history gets eight, enough for its emission).
 #pragma unroll
@@ -751,6 +760,22 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       phase = kTrack;
     }
 
+    // ---------------- pair-buffer room (converged) ------------------------
+    // Room in the wavefront's block for every lane whose photon B may end a
+    // pair below; otherwise the rest of the block is padded and the next
+    // block reserved.  res_next and res_end change only here and at the end
+    // of the iteration, so they stay wave-uniform.
+    {
+      const uint64_t need = static_cast<uint64_t>(__popcll(__ballot(phase == kFinish && side == 1 && a_win)));
+      if (res_end - res_next < need) {
+        pad_pairs(p, res_next, res_end);
+        uint32_t b0 = 0u;
+        if (lane == 0u) b0 = atomicAdd(p.pair_count, kPairBlock);
+        res_next = static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(b0))));
+        res_end = res_next + kPairBlock;
+      }
+    }
+
     // ---------------- photon finished ------------------------------------
     if (phase == kFinish) {
       float hx = 0.0f, hy = 0.0f, hz = 0.0f, path = 0.0f, edet = ec.E;
@@ -772,7 +797,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             hz = zz;
             path = len + tc;
             if (p.e_fwhm > 0.0f) {
-              const float nrm = polar_normal(r, 0u);
+              const float nrm = std_normal<kInstr>(r, 0u, p, s_stats);
               const float sig = (p.e_fwhm / 2.35482f) * sqrtf(kMec2 / ec.E);
               edet = ec.E * (1.0f + sig * nrm);
             }
@@ -809,13 +834,13 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         a_scat = (nC + nR) > 0;
         a_steps = steps;
         if (win) {
-          cq->a[0][lane] = __float_as_uint(hx);
-          cq->a[1][lane] = __float_as_uint(hy);
-          cq->a[2][lane] = __float_as_uint(dx);
-          cq->a[3][lane] = __float_as_uint(dy);
-          cq->a[4][lane] = __float_as_uint(dz);
-          cq->a[5][lane] = __float_as_uint(path);
-          cq->a[6][lane] = rie;
+          stash[0u + lane] = __float_as_uint(hx);
+          stash[64u + lane] = __float_as_uint(hy);
+          stash[128u + lane] = __float_as_uint(dx);
+          stash[192u + lane] = __float_as_uint(dy);
+          stash[256u + lane] = __float_as_uint(dz);
+          stash[320u + lane] = __float_as_uint(path);
+          stash[384u + lane] = rie;
         }
         // photon B: back to back with A
         side = 1;
@@ -836,19 +861,16 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         const bool both = a_win && win;
         const uint64_t bm = __ballot(both);
         if (both) {
-          const uint32_t c = (q_head + q_count + static_cast<uint32_t>(__popcll(bm & below))) & (kQueueCap - 1u);
-          cq->e[kQh][c] = static_cast<uint32_t>(h - base);
-          cq->e[kQPos][c] = r.blk * 4u - r.left;
-          cq->e[kQFlags][c] = r.left | (scattered ? 0x100u : 0u);
-#pragma unroll
-          for (int i = 0; i < kSingleWords; ++i) cq->e[kQA + i][c] = cq->a[i][lane];
-          cq->e[kQB + 0][c] = __float_as_uint(hx);
-          cq->e[kQB + 1][c] = __float_as_uint(hy);
-          cq->e[kQB + 2][c] = __float_as_uint(dx);
-          cq->e[kQB + 3][c] = __float_as_uint(dy);
-          cq->e[kQB + 4][c] = __float_as_uint(dz);
-          cq->e[kQB + 5][c] = __float_as_uint(path);
-          cq->e[kQB + 6][c] = rie;
+          const uint64_t slot = res_next + static_cast<uint64_t>(__popcll(bm & below));
+          if (slot < p.pair_cap) {  // always, by the launch size; a guard for the memory
+            uint4* w = reinterpret_cast<uint4*>(p.pairs + slot * kPairWords);
+            w[0] = make_uint4(static_cast<uint32_t>(h), static_cast<uint32_t>(h >> 32), r.blk * 4u - r.left,
+                              r.left | (scattered ? 0x100u : 0u) | (p.item << 16));
+            w[1] = make_uint4(stash[lane], stash[64u + lane], stash[128u + lane], stash[192u + lane]);
+            w[2] = make_uint4(stash[256u + lane], stash[320u + lane], stash[384u + lane], __float_as_uint(hx));
+            w[3] = make_uint4(__float_as_uint(hy), __float_as_uint(dx), __float_as_uint(dy), __float_as_uint(dz));
+            w[4] = make_uint4(__float_as_uint(path), rie, 0u, 0u);
+          }
         }
         pushed = both;
         SSE_COUNT(kStHist, true);
@@ -867,16 +889,8 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         phase = kEmit;
       }
     }
-
-    // ---------------- queue bookkeeping (converged) -----------------------
-    q_count += static_cast<uint32_t>(__popcll(__ballot(pushed)));
+    res_next += static_cast<uint64_t>(__popcll(__ballot(pushed)));
     pushed = false;
-    if (q_count >= 64u || all_done) {
-      const uint32_t n = q_count < 64u ? q_count : 64u;
-      drain(q_head, n);
-      q_head = (q_head + n) & (kQueueCap - 1u);
-      q_count -= n;
-    }
   }
 }
 
@@ -884,7 +898,8 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
 // per-history records); false: the production path, with neither.  Every
 // wavefront owns a contiguous share of [h0, h0 + n).
 template <bool kInstr>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_kernel(TransportParams p) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTransportWavesPerEu)))
+transport_kernel(TransportParams p) {
   const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
   const uint64_t per = p.n / nwaves, rem = p.n % nwaves;
@@ -892,13 +907,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
   const uint64_t end = begin + per + (wave < rem ? 1 : 0);
   __shared__ unsigned long long s_stats[kStatCount];
   __shared__ float s_mu_table[256];
-  __shared__ CoincQueue s_queue[4];
-  __shared__ uint32_t s_rng[4 * 8 * 64];
+  __shared__ uint32_t s_stash[4][kSingleWords * 64];
+  __shared__ uint32_t s_rng[4][8 * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
-  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), &s_queue[threadIdx.x >> 6],
-                        (LdsWord*)(s_rng + (threadIdx.x >> 6) * 512u));
+  uint64_t res_next = 0, res_end = 0;
+  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), (LdsWord*)(s_stash[threadIdx.x >> 6]),
+                        (LdsWord*)(s_rng[threadIdx.x >> 6]), res_next, res_end);
+  pad_pairs(p, res_next, res_end);
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
@@ -911,12 +928,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
 // exhausted; each sub-chunk carries its own request's parameters.  The
 // palette table is per wavefront because neighbouring wavefronts may work
 // on different requests.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) transport_batch_kernel(BatchParams b) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTransportWavesPerEu)))
+transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
-  __shared__ CoincQueue s_queue[4];
-  __shared__ uint32_t s_rng[4 * 8 * 64];
+  __shared__ uint32_t s_stash[4][kSingleWords * 64];
+  __shared__ uint32_t s_rng[4][8 * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
+  uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
+  const TransportParams* last = nullptr;
   for (;;) {
     uint32_t c = 0;
     if (lane == 0) c = atomicAdd(b.counter, 1u);
@@ -930,39 +950,140 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) t
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab), &s_queue[threadIdx.x >> 6],
-                         (LdsWord*)(s_rng + (threadIdx.x >> 6) * 512u));
+    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab), (LdsWord*)(s_stash[threadIdx.x >> 6]),
+                         (LdsWord*)(s_rng[threadIdx.x >> 6]), res_next, res_end);
+    last = &p;
     __builtin_amdgcn_wave_barrier();
   }
+  if (last) pad_pairs(*last, res_next, res_end);
+}
+
+// The records the last transport launch reserved, one per thread (padding
+// records are skipped).
+template <bool kInstr>
+__global__ void __launch_bounds__(256) coincidence_kernel(TransportParams p) {
+  __shared__ unsigned long long s_stats[kStatCount];
+  if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t count = *p.pair_count;
+  const uint64_t n = count < p.pair_cap ? count : p.pair_cap;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    evaluate_pair<kInstr>(p, p.pairs, i, s_stats);
+  if (kInstr) {
+    __syncthreads();
+    if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
+      atomicAdd(p.stats + threadIdx.x, s_stats[threadIdx.x]);
+  }
+}
+
+// Work-list form: each pair carries its request slot.
+__global__ void __launch_bounds__(256) coincidence_batch_kernel(BatchParams b) {
+  const uint64_t count = *b.pair_count;
+  const uint64_t n = count < b.pair_cap ? count : b.pair_cap;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t flags = b.pairs[i * kPairWords + kPFlags];
+    if (flags == kEmptyPair) continue;
+    evaluate_pair<false>(b.items[flags >> 16], b.pairs, i, nullptr);
+  }
+}
+
+__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+
+hipError_t device_info(int& cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return e;
+}
+
+// Blocks for a grid-stride pass over at most `items` items.
+int stride_grid(uint64_t items, int cus) {
+  const uint64_t want = (items + 255) / 256;
+  const uint64_t most = static_cast<uint64_t>(cus) * 8u;
+  return static_cast<int>(want < most ? (want > 0 ? want : 1) : most);
+}
+
+constexpr int kBlock = 256;
+
+// Resident blocks of a transport kernel on the whole device.
+template <class K>
+uint64_t resident_blocks(K kernel) {
+  int cus = 0, per_cu = 0;
+  if (device_info(cus) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess) return 0;
+  return static_cast<uint64_t>(cus) * static_cast<uint64_t>(per_cu > 0 ? per_cu : 1);
+}
+
+uint64_t transport_resident_waves() {
+  const uint64_t a = resident_blocks(transport_kernel<true>), b = resident_blocks(transport_kernel<false>);
+  return (a > b ? a : b) * (kBlock / 64);
+}
+
+// Wavefronts a launch of n histories runs with.
+uint64_t waves_for(uint64_t n, uint64_t resident_waves) {
+  const uint64_t want = ((n + kBlock - 1) / kBlock) * (kBlock / 64);
+  return want < resident_waves ? want : resident_waves;
+}
+
+// Largest n with pair_records_needed(n, waves(n)) <= cap.
+template <class W>
+uint64_t max_histories(uint64_t cap, W waves) {
+  uint64_t lo = 0, hi = cap;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (pair_records_needed(mid, waves(mid)) <= cap) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 template <bool kInstr>
 hipError_t launch(const TransportParams& p, hipStream_t stream) {
-  constexpr int kBlock = 256;
-  int dev = 0, cus = 0, per_cu = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, transport_kernel<kInstr>, kBlock, 0);
+  int cus = 0;
+  hipError_t e = device_info(cus);
   if (e != hipSuccess) return e;
-  const uint64_t resident = static_cast<uint64_t>(cus) * static_cast<uint64_t>(per_cu > 0 ? per_cu : 1);
+  const uint64_t resident = resident_blocks(transport_kernel<kInstr>);
+  if (resident == 0) return hipErrorInvalidDeviceFunction;
   // one resident wave per 64 histories at most: small runs use fewer blocks
   const uint64_t want = (p.n + kBlock - 1) / kBlock;
   const int grid = static_cast<int>(want < resident ? want : resident);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, p.pair_count);
   hipLaunchKernelGGL(transport_kernel<kInstr>, dim3(grid), dim3(kBlock), 0, stream, p);
+  hipLaunchKernelGGL(coincidence_kernel<kInstr>, dim3(stride_grid(pair_records_needed(p.n, 4ull * grid), cus)),
+                     dim3(kBlock), 0, stream, p);
   return hipGetLastError();
 }
 
 }  // namespace
 
+uint64_t transport_pairs_needed(uint64_t n) {
+  return pair_records_needed(n, waves_for(n, transport_resident_waves()));
+}
+
+uint64_t transport_max_histories(uint64_t cap) {
+  const uint64_t rw = transport_resident_waves();
+  return max_histories(cap, [rw](uint64_t n) { return waves_for(n, rw); });
+}
+
+uint64_t transport_batch_pairs_needed(uint64_t n) {
+  return pair_records_needed(n, resident_blocks(transport_batch_kernel) * (kBlock / 64));
+}
+
+uint64_t transport_batch_max_histories(uint64_t cap) {
+  const uint64_t rw = resident_blocks(transport_batch_kernel) * (kBlock / 64);
+  return max_histories(cap, [rw](uint64_t) { return rw; });  // chunks go to every resident wave
+}
+
 hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
-  // Runs of 2^32 histories at most per launch, so that a wavefront's share
-  // fits the queue's 32-bit history offsets; results do not depend on the
-  // split.
-  constexpr uint64_t kMaxPerLaunch = 1ull << 32;
+  if (!p.pairs || !p.pair_count || p.pair_cap == 0 || p.pair_cap > kMaxPairCap) return hipErrorInvalidValue;
+  const uint64_t most = transport_max_histories(p.pair_cap);
+  if (most == 0) return hipErrorInvalidValue;
   for (uint64_t done = 0; done < p.n;) {
     TransportParams q = p;
     q.h0 = p.h0 + done;
-    q.n = p.n - done < kMaxPerLaunch ? p.n - done : kMaxPerLaunch;
+    q.n = p.n - done < most ? p.n - done : most;
     const hipError_t e = (p.stats || p.rec) ? launch<true>(q, stream) : launch<false>(q, stream);
     if (e != hipSuccess) return e;
     done += q.n;
@@ -970,21 +1091,24 @@ hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
   return hipSuccess;
 }
 
-__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
-
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
   if (b.n_chunks == 0) return hipSuccess;
-  constexpr int kBlock = 256;
-  int dev = 0, cus = 0, per_cu = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, transport_batch_kernel, kBlock, 0);
+  if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap ||
+      b.n_histories > transport_batch_max_histories(b.pair_cap))
+    return hipErrorInvalidValue;
+  int cus = 0;
+  hipError_t e = device_info(cus);
   if (e != hipSuccess) return e;
-  const uint64_t resident = static_cast<uint64_t>(cus) * static_cast<uint64_t>(per_cu > 0 ? per_cu : 1);
+  const uint64_t resident = resident_blocks(transport_batch_kernel);
+  if (resident == 0) return hipErrorInvalidDeviceFunction;
   const uint64_t want = (static_cast<uint64_t>(b.n_chunks) + 3) / 4;  // one chunk per wave at least
   const int grid = static_cast<int>(want < resident ? want : resident);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.pair_count);
   hipLaunchKernelGGL(transport_batch_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
+  hipLaunchKernelGGL(coincidence_batch_kernel,
+                     dim3(stride_grid(pair_records_needed(b.n_histories, 4ull * grid), cus)), dim3(kBlock), 0,
+                     stream, b);
   return hipGetLastError();
 }
 
