@@ -477,6 +477,50 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
   }
 }
 
+// Emission of history hh into column `lane` of the queue eq: voxel from the
+// alias table (64-bit multiply-shift column, 32-bit alias decision), uniform
+// point in it, isotropic direction with cos(theta) = 1 - 2 u (exact) and
+// azimuth 2 pi u'.  It takes exactly the eight words of Philox blocks 0 and 1
+// of the history's stream, in that order.  Columns: position, direction,
+// voxel.
+__device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t hh, LdsWord* eq) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
+  const uint32_t hlo = static_cast<uint32_t>(hh), hhi = static_cast<uint32_t>(hh >> 32);
+  uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
+  philox(0u, hlo, hhi, 0u, k0, k1, a0, a1, a2, a3);
+  philox(1u, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
+  const uint64_t col = __umul64hi((static_cast<uint64_t>(a1) << 32) | a0, p.nvox);
+  const uint2 al = p.alias[col];
+  const uint32_t v = (a2 < al.x) ? static_cast<uint32_t>(col) : al.y;
+  const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
+  uint32_t ix, iy, iz;
+  if (p.nvox < (1ull << 24)) {
+    const uint32_t q = udiv24(v, nx, p.inv_nx);
+    iz = udiv24(v, nx * ny, p.inv_nxy);
+    ix = v - q * nx;
+    iy = q - iz * ny;
+  } else {
+    ix = v % nx;
+    iy = (v / nx) % ny;
+    iz = v / (nx * ny);
+  }
+  const float ex = p.lox + (static_cast<float>(ix) + to_uniform(a3)) * p.vx;
+  const float ey = p.loy + (static_cast<float>(iy) + to_uniform(b0)) * p.vy;
+  const float ez = p.loz + (static_cast<float>(iz) + to_uniform(b1)) * p.vz;
+  const float cz = 1.0f - 2.0f * to_uniform(b2);
+  const float st = sqrtf((1.0f - cz) * (1.0f + cz));
+  float sp, cp;
+  sincos_2pi(to_uniform(b3), sp, cp);
+  eq[lane] = __float_as_uint(ex);
+  eq[64u + lane] = __float_as_uint(ey);
+  eq[128u + lane] = __float_as_uint(ez);
+  eq[192u + lane] = __float_as_uint(st * cp);
+  eq[256u + lane] = __float_as_uint(st * sp);
+  eq[320u + lane] = __float_as_uint(cz);
+  eq[384u + lane] = v;
+}
+
 // Mark records [from, to) of the wavefront's block empty (converged call).
 __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t from, uint64_t to) {
   for (uint64_t k = from + (threadIdx.x & 63u); k < to; k += 64u)
@@ -491,7 +535,7 @@ __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t fro
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
 // only when kInstr); stash the wavefront's LDS area for photon A's hit data
-// (kSingleWords columns of 64 lanes).
+// (kSingleWords columns of 64 lanes); eq its emission queue (7 columns).
 // The palette pointer is typed as LDS so that its reads are LDS reads even
 // where the compiler merges them with the binary32-map path.
 typedef const __attribute__((address_space(3))) float LdsFloat;
@@ -499,8 +543,8 @@ typedef const __attribute__((address_space(3))) float LdsFloat;
 template <bool kInstr>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
                                               unsigned long long* s_stats, LdsFloat* mu_tab,
-                                              LdsWord* stash, LdsWord* rng_buf, uint64_t& res_next,
-                                              uint64_t& res_end) {
+                                              LdsWord* stash, LdsWord* rng_buf, LdsWord* eq,
+                                              uint64_t& res_next, uint64_t& res_end) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
@@ -524,33 +568,81 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   LaneRng r;
   r.col = rng_buf + lane;
   r.start(0);
+  // emission queue (wave-uniform): entries for histories qbase .. qbase +
+  // qn - 1 in eq, the next unused at qhead; qnext the next history to queue
+  uint64_t qnext = next, qbase = next;
+  uint32_t qn = 0, qhead = 0;
+
+  // Start history qbase + k from queue entry k: photon A at the emission
+  // point; its stream goes on at block 2 (the emission used blocks 0 and 1).
+  auto take_emission = [&](uint32_t k) {
+    h = qbase + k;
+    ex = __uint_as_float(eq[k]);
+    ey = __uint_as_float(eq[64u + k]);
+    ez = __uint_as_float(eq[128u + k]);
+    edx = __uint_as_float(eq[192u + k]);
+    edy = __uint_as_float(eq[256u + k]);
+    edz = __uint_as_float(eq[320u + k]);
+    r.start(h);
+    r.blk = 2u;
+    rec = nullptr;
+    if (kInstr && p.rec) {
+      const uint64_t off = h - p.rec_h0;
+      if (off % p.rec_stride == 0) {
+        rec = p.rec + (off / p.rec_stride) * kRecordWords;
+        rec[3] = eq[384u + k];
+      }
+    }
+    side = 0;
+    px = ex; py = ey; pz = ez;
+    dx = edx; dy = edy; dz = edz;
+    t = 0.0f; len = 0.0f;
+    texit = box_exit(p, px, py, pz, dx, dy, dz);
+    ec = p.e511;
+    nC = nR = nint = 0;
+    steps = 0;
+    fate = kEscaped;
+    phase = kTrack;
+  };
 
 
   for (;;) {
     // ---------------- take new histories ---------------------------------
+    // Lanes that need a history take the next emission of the wavefront's
+    // queue; when it runs out, all lanes refill it together (every history's
+    // emission is computed by one lane of a converged wave) and the remaining
+    // lanes take from the new entries.
     const uint64_t needmask = __ballot(phase == kEmit);
-    bool emitting = false;
     if (needmask) {
-      if (phase == kEmit) {
-        const uint64_t hh = next + __popcll(needmask & below);
-        if (hh < end) {
-          h = hh;
-          emitting = true;
-          r.start(h);
-          rec = nullptr;
-          if (kInstr && p.rec) {
-            const uint64_t off = h - p.rec_h0;
-            if (off % p.rec_stride == 0) rec = p.rec + (off / p.rec_stride) * kRecordWords;
-          }
-        } else {
-          phase = kDone;
+      const uint32_t want = static_cast<uint32_t>(__popcll(needmask));
+      const uint32_t rank = static_cast<uint32_t>(__popcll(needmask & below));
+      const uint32_t got = want < qn - qhead ? want : qn - qhead;
+      if (phase == kEmit && rank < got) take_emission(qhead + rank);
+      qhead += got;
+      if (want > got) {
+        if (qnext < end) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const bool valid = qnext + lane < end;
+          emit_to_queue(p, qnext + lane, eq);
+          SSE_COUNT(kStRngBlocks, valid);
+          SSE_COUNT(kStRngBlocks, valid);
+          qbase = qnext;
+          qn = end - qnext < 64u ? static_cast<uint32_t>(end - qnext) : 64u;
+          qnext += qn;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (phase == kEmit && rank >= got && rank - got < qn) take_emission(rank - got);
+          qhead = want - got < qn ? want - got : qn;
         }
+        if (phase == kEmit) phase = kDone;  // no history left for this lane
       }
-      next += __popcll(needmask);
     }
     if (__all(phase == kDone)) break;
     // Converged top-up: every live lane ends with at least five buffered
-    // words (a new history gets eight, enough for its emission).
+    // words (a new history gets eight).
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (__any(phase != kDone && r.left <= 4u)) {
@@ -558,59 +650,6 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         if (g) r.refill(k0, k1);
         SSE_COUNT(kStRngBlocks, g);
       }
-    }
-
-    // ---------------- emission --------------------------------------------
-    if (emitting) {
-      // voxel: 64-bit multiply-shift column, 32-bit alias decision
-      RNG_NEED(3u);
-      const uint64_t lo = r.take();
-      const uint64_t hi = r.take();
-      const uint64_t col = __umul64hi((hi << 32) | lo, p.nvox);
-      const uint32_t x1 = r.take();
-      const uint2 al = p.alias[col];
-      const uint32_t v = (x1 < al.x) ? static_cast<uint32_t>(col) : al.y;
-      const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
-      uint32_t ix, iy, iz;
-      if (p.nvox < (1ull << 24)) {
-        const uint32_t q = udiv24(v, nx, p.inv_nx);
-        iz = udiv24(v, nx * ny, p.inv_nxy);
-        ix = v - q * nx;
-        iy = q - iz * ny;
-      } else {
-        ix = v % nx;
-        iy = (v / nx) % ny;
-        iz = v / (nx * ny);
-      }
-      RNG_NEED(3u);
-      const float ux = r.uniform();
-      const float uy = r.uniform();
-      const float uz = r.uniform();
-      ex = p.lox + (static_cast<float>(ix) + ux) * p.vx;
-      ey = p.loy + (static_cast<float>(iy) + uy) * p.vy;
-      ez = p.loz + (static_cast<float>(iz) + uz) * p.vz;
-      // isotropic direction: cos(theta) = 1 - 2 u (exact), azimuth 2 pi u'
-      RNG_NEED(2u);
-      edz = 1.0f - 2.0f * r.uniform();
-      {
-        const float st = sqrtf((1.0f - edz) * (1.0f + edz));
-        float sp, cp;
-        sincos_2pi(r.uniform(), sp, cp);
-        edx = st * cp;
-        edy = st * sp;
-      }
-      if (kInstr && rec) rec[3] = v;
-      // photon A
-      side = 0;
-      px = ex; py = ey; pz = ez;
-      dx = edx; dy = edy; dz = edz;
-      t = 0.0f; len = 0.0f;
-      texit = box_exit(p, px, py, pz, dx, dy, dz);
-      ec = p.e511;
-      nC = nR = nint = 0;
-      steps = 0;
-      fate = kEscaped;
-      phase = kTrack;
     }
 
     // ---------------- Woodcock steps until most lanes have an event --------
@@ -909,12 +948,14 @@ transport_kernel(TransportParams p) {
   __shared__ float s_mu_table[256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][8 * 64];
+  __shared__ uint32_t s_emit[4][7 * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
   uint64_t res_next = 0, res_end = 0;
   run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), (LdsWord*)(s_stash[threadIdx.x >> 6]),
-                        (LdsWord*)(s_rng[threadIdx.x >> 6]), res_next, res_end);
+                        (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next,
+                        res_end);
   pad_pairs(p, res_next, res_end);
   if (kInstr) {
     __syncthreads();
@@ -933,6 +974,7 @@ transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][8 * 64];
+  __shared__ uint32_t s_emit[4][7 * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
@@ -951,7 +993,8 @@ transport_batch_kernel(BatchParams b) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab), (LdsWord*)(s_stash[threadIdx.x >> 6]),
-                         (LdsWord*)(s_rng[threadIdx.x >> 6]), res_next, res_end);
+                         (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next,
+                         res_end);
     last = &p;
     __builtin_amdgcn_wave_barrier();
   }
