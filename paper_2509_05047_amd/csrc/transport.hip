@@ -482,7 +482,7 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
 // point in it, isotropic direction with cos(theta) = 1 - 2 u (exact) and
 // azimuth 2 pi u'.  It takes exactly the eight words of Philox blocks 0 and 1
 // of the history's stream, in that order.  Columns: position, direction,
-// voxel.
+// voxel, distance to the exit of the voxel box.
 __device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t hh, LdsWord* eq) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
@@ -519,6 +519,7 @@ __device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t
   eq[256u + lane] = __float_as_uint(st * sp);
   eq[320u + lane] = __float_as_uint(cz);
   eq[384u + lane] = v;
+  eq[448u + lane] = __float_as_uint(box_exit(p, ex, ey, ez, st * cp, st * sp, cz));
 }
 
 // Mark records [from, to) of the wavefront's block empty (converged call).
@@ -535,7 +536,7 @@ __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t fro
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
 // only when kInstr); stash the wavefront's LDS area for photon A's hit data
-// (kSingleWords columns of 64 lanes); eq its emission queue (7 columns).
+// (kSingleWords columns of 64 lanes); eq its emission queue (8 columns).
 // The palette pointer is typed as LDS so that its reads are LDS reads even
 // where the compiler merges them with the binary32-map path.
 typedef const __attribute__((address_space(3))) float LdsFloat;
@@ -597,7 +598,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     px = ex; py = ey; pz = ez;
     dx = edx; dy = edy; dz = edz;
     t = 0.0f; len = 0.0f;
-    texit = box_exit(p, px, py, pz, dx, dy, dz);
+    texit = __uint_as_float(eq[448u + k]);
     ec = p.e511;
     nC = nR = nint = 0;
     steps = 0;
@@ -948,7 +949,7 @@ transport_kernel(TransportParams p) {
   __shared__ float s_mu_table[256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][8 * 64];
-  __shared__ uint32_t s_emit[4][7 * 64];
+  __shared__ uint32_t s_emit[4][8 * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
@@ -974,7 +975,7 @@ transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][8 * 64];
-  __shared__ uint32_t s_emit[4][7 * 64];
+  __shared__ uint32_t s_emit[4][8 * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
