@@ -85,15 +85,16 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
 // A history's random stream: the 32-bit words of Philox blocks 0, 1, 2, ...
 // with counter (block, h_lo, h_hi, 0), consumed in order.
 //
-// Lane streams keep up to eight words in LDS, in a column of eight slots per
-// lane (slot i of lane l at word 64 i + l, so a wave's accesses hit distinct
-// banks).  Block b goes to slots 4 (b mod 2) .. +3, and words are read from
-// slot rd, advancing mod 8; a lane may generate its next block whenever it
-// holds at most four words (its other half is then free), so a refill that
-// one lane needs is shared by every lane of the wave with room and Philox
-// runs mostly converged.  Reading a word is one LDS load: no register
-// shuffling and no dynamically indexed registers.
+// Lane streams keep up to kRngSlots words in LDS, in a column per lane (slot
+// i of lane l at word 64 i + l, so a wave's accesses hit distinct banks).
+// Block b goes to slots 4 (b mod kRngSlots/4) .. +3, and words are read
+// from slot rd, advancing mod kRngSlots; a lane may generate its next block
+// whenever it has room for four more words, so a refill that one lane needs
+// is shared by every lane of the wave with room and Philox runs mostly
+// converged.  Reading a word is one LDS load: no register shuffling and no
+// dynamically indexed registers.
 typedef __attribute__((address_space(3))) uint32_t LdsWord;
+constexpr uint32_t kRngSlots = 16;
 
 __device__ __forceinline__ float to_uniform(uint32_t x) {
   // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
@@ -111,11 +112,17 @@ struct LaneRng {
     left = 0;
     rd = 0;
   }
-  __device__ __forceinline__ bool room() const { return left <= 4u; }
+  // go on at block b with nothing buffered (the read slot follows the block)
+  __device__ __forceinline__ void seek_block(uint32_t b) {
+    blk = b;
+    left = 0;
+    rd = (b * 4u) & (kRngSlots - 1u);
+  }
+  __device__ __forceinline__ bool room() const { return left <= kRngSlots - 4u; }
   __device__ __forceinline__ void refill(uint32_t k0, uint32_t k1) {
     uint32_t b0, b1, b2, b3;
     philox(blk, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
-    LdsWord* d = col + ((blk & 1u) << 8);  // slots 4 (blk mod 2) .. +3
+    LdsWord* d = col + ((blk & (kRngSlots / 4u - 1u)) << 8);  // slots 4 (blk mod kRngSlots/4) .. +3
     d[0] = b0;
     d[64] = b1;
     d[128] = b2;
@@ -125,15 +132,15 @@ struct LaneRng {
   }
   __device__ __forceinline__ uint32_t take() {
     const uint32_t x = col[rd << 6];
-    rd = (rd + 1u) & 7u;
+    rd = (rd + 1u) & (kRngSlots - 1u);
     --left;
     return x;
   }
   __device__ __forceinline__ float uniform() { return to_uniform(take()); }
   // word k ahead of the next one, not consumed (k < left for a valid word)
-  __device__ __forceinline__ uint32_t peek(uint32_t k) const { return col[((rd + k) & 7u) << 6]; }
+  __device__ __forceinline__ uint32_t peek(uint32_t k) const { return col[((rd + k) & (kRngSlots - 1u)) << 6]; }
   __device__ __forceinline__ void advance(uint32_t k) {
-    rd = (rd + k) & 7u;
+    rd = (rd + k) & (kRngSlots - 1u);
     left -= k;
   }
 };
@@ -181,7 +188,7 @@ struct RegRng {
 #define RNG_NEED(k)                                  \
   do {                                               \
     if (__any(r.left < (k))) {                       \
-      const bool g_ = r.left <= 4u;                  \
+      const bool g_ = r.room();                      \
       if (g_) r.refill(k0, k1);                      \
       SSE_COUNT(kStRngBlocks, g_);                   \
     }                                                \
@@ -233,15 +240,18 @@ __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct
 // ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
+// Distance along d from p to the exit of the voxel box: the least of the
+// per-axis quotients, all three computed (no branches) and those of axes
+// the direction does not move along left out.
 __device__ __forceinline__ float box_exit(const TransportParams& p, float px, float py, float pz, float dx,
                                           float dy, float dz) {
+  const float qx = (dx > 0.0f ? p.hix - px : p.lox - px) / dx;
+  const float qy = (dy > 0.0f ? p.hiy - py : p.loy - py) / dy;
+  const float qz = (dz > 0.0f ? p.hiz - pz : p.loz - pz) / dz;
   float t = __builtin_huge_valf();
-  if (dx > 0.0f) t = fminf(t, (p.hix - px) / dx);
-  else if (dx < 0.0f) t = fminf(t, (p.lox - px) / dx);
-  if (dy > 0.0f) t = fminf(t, (p.hiy - py) / dy);
-  else if (dy < 0.0f) t = fminf(t, (p.loy - py) / dy);
-  if (dz > 0.0f) t = fminf(t, (p.hiz - pz) / dz);
-  else if (dz < 0.0f) t = fminf(t, (p.loz - pz) / dz);
+  t = dx != 0.0f ? fminf(t, qx) : t;
+  t = dy != 0.0f ? fminf(t, qy) : t;
+  t = dz != 0.0f ? fminf(t, qz) : t;
   return t;
 }
 
@@ -585,7 +595,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     edy = __uint_as_float(eq[256u + k]);
     edz = __uint_as_float(eq[320u + k]);
     r.start(h);
-    r.blk = 2u;
+    r.seek_block(2u);
     rec = nullptr;
     if (kInstr && p.rec) {
       const uint64_t off = h - p.rec_h0;
@@ -642,12 +652,12 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       }
     }
     if (__all(phase == kDone)) break;
-    // Converged top-up: every live lane ends with at least five buffered
-    // words (a new history gets eight).
+    // Converged top-up: three rounds in which every live lane with room
+    // generates a block (a new history gets twelve words).
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (__any(phase != kDone && r.left <= 4u)) {
-        const bool g = phase != kDone && r.left <= 4u;
+    for (int k = 0; k < 3; ++k) {
+      if (__any(phase != kDone && r.room())) {
+        const bool g = phase != kDone && r.room();
         if (g) r.refill(k0, k1);
         SSE_COUNT(kStRngBlocks, g);
       }
@@ -663,7 +673,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     while (__any(phase == kTrack) && (__popcll(__ballot(phase == kTrack)) > kStepTail ||
                                       !__any(phase != kTrack && phase != kDone))) {
       if (__any(phase == kTrack && r.left < 2u)) {
-        const bool g = phase != kDone && r.left <= 4u;
+        const bool g = phase != kDone && r.room();
         if (g) r.refill(k0, k1);
         SSE_COUNT(kStRngBlocks, g);
       }
@@ -948,7 +958,7 @@ transport_kernel(TransportParams p) {
   __shared__ unsigned long long s_stats[kStatCount];
   __shared__ float s_mu_table[256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
-  __shared__ uint32_t s_rng[4][8 * 64];
+  __shared__ uint32_t s_rng[4][kRngSlots * 64];
   __shared__ uint32_t s_emit[4][8 * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
@@ -974,7 +984,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTrans
 transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
-  __shared__ uint32_t s_rng[4][8 * 64];
+  __shared__ uint32_t s_rng[4][kRngSlots * 64];
   __shared__ uint32_t s_emit[4][8 * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
