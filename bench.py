@@ -23,9 +23,12 @@ import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 
-# Per-unit VALU cost model of the transport kernel (lane-instructions per
-# unit of the method's work; quarter-rate instructions count 4).  Units are
-# counted by the oracle and the kernel alike (statistics counters).
+# Per-unit VALU cost model of the transport path (lane-instructions per unit
+# of the method's work; quarter-rate instructions count 4).  Units are
+# counted by the oracle and the kernel alike (statistics counters).  The path
+# is one simulate call: its transport launches (emission, transport,
+# detection) and their coincidence launches (pair indexing, LUT weight,
+# sinogram update).
 COST = dict(rng_block=130, step=70, real=250, detected=150, history=150)
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 
@@ -41,9 +44,10 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per transport launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None when the
-    kernel has changed since the counters were taken."""
+    """HBM bytes of one simulate call (all its transport and coincidence
+    launches) from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
+    calibrated by a plain copy), or None when the kernels have changed since
+    the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", "transport_clinical_hbm_counters.md")
     try:
@@ -53,9 +57,7 @@ def measured_traffic():
     fields = dict(re.findall(r"^(\w+): (\S+)$", text, flags=re.M))
     if fields.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    fetch = float(fields["fetch_kib_per_dispatch"]) * 1024 * float(fields["fetch_factor"])
-    write = float(fields["write_kib_per_dispatch"]) * 1024 * float(fields["write_factor"])
-    return fetch + write
+    return float(fields["fetch_bytes_per_step"]) + float(fields["write_bytes_per_step"])
 
 
 def log(msg):
@@ -136,7 +138,7 @@ def large_loop(args):
                    "histories_per_step": n},
         "request_latency_ms": lat,
         "request_latency_p50_ms": float(np.percentile(lat, 50)),
-        "transport_kernel_ms": float(np.mean([t[1] for t in timing])),
+        "simulate_ms": float(np.mean([t[1] for t in timing])),
         "finalize_ms": float(np.mean([t[2] for t in timing])),
         "update_activity_ms": float(np.mean([t[0] - t[1] - t[2] for t in timing])),
     }
@@ -292,6 +294,8 @@ def main():
     final = torch.empty(ctx.n_bins, dtype=torch.float32, device="cuda")
     scale = ctx.emission_scale(pid, n)
     stream = torch.cuda.current_stream()
+    # HIP events on the stream the library launches on, around each timed
+    # simulate call (its transport, coincidence and counter-reset launches)
     tr_start = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     tr_end = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
 
@@ -343,11 +347,13 @@ def main():
                    "histories_per_step": n, "lut_dtype": args.lut, "transport": "f32",
                    "accumulation": "f64"},
         "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
-        "transport_kernel_ms": float(np.mean(kernel_ms)),
+        "simulate_ms": float(np.mean(kernel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
                                  and args.lut == "f32" else None),
+                     "kernel": "one simulate call: transport + coincidence launches",
+                     "span_ms": float(np.mean(kernel_ms)),
                      "ops_per_history": ops_per_hist},
     }
     if not args.no_cpu_baseline:

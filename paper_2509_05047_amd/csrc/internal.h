@@ -23,7 +23,7 @@ enum PairWord {
   kPhLo = 0,   // history, low and high word
   kPhHi,
   kPPos,       // word of the history's stream where photon B ended
-  kPFlags,     // words buffered then | scattered << 8 | request slot << 16, or kEmptyPair
+  kPFlags,     // scattered << 8 | request slot << 16, or kEmptyPair
   kPA,         // photon A, kSingleWords words
   kPB = kPA + kSingleWords,
   kPairWords = 20  // with two words of padding

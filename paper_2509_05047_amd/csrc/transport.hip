@@ -188,11 +188,14 @@ struct RegRng {
 #define RNG_NEED(k)                                  \
   do {                                               \
     if (__any(r.left < (k))) {                       \
-      const bool g_ = r.room();                      \
-      if (g_) r.refill(k0, k1);                      \
-      SSE_COUNT(kStRngBlocks, g_);                   \
+      if (r.room()) r.refill(k0, k1);                \
     }                                                \
   } while (0)
+
+// The statistics count the Philox blocks a history uses -- ceil(words
+// consumed / 4), the blocks an on-demand generator would make -- not the
+// ones generated ahead of need.
+__device__ __forceinline__ uint64_t blocks_used(uint32_t words) { return (words + 3u) / 4u; }
 
 // (sin 2 pi u, cos 2 pi u) for u in [0, 1), fixed operation by operation
 // (error below 1.7 * 2^-24 for the transport's uniforms):
@@ -360,18 +363,13 @@ constexpr int kTransportWavesPerEu = 3;
 // result is the one an in-place evaluation gives.
 
 // Standard normal by Marsaglia's polar method from stream q (a lane's own,
-// or a copy re-positioned in a history's stream).  Blocks below `known` were
-// generated before and are not counted again.
-template <bool kInstr, class Q>
-__device__ __forceinline__ float std_normal(Q& q, uint32_t known, const TransportParams& p,
-                                            unsigned long long* s_stats) {
-  const uint32_t lane = threadIdx.x & 63u;
+// or a copy re-positioned in a history's stream).
+template <class Q>
+__device__ __forceinline__ float std_normal(Q& q, const TransportParams& p) {
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   for (int i = 0; i < kMaxTries; ++i) {
     if (__any(q.left < 2u)) {
-      const bool g = q.room();
-      if (g) q.refill(k0, k1);
-      SSE_COUNT(kStRngBlocks, g && q.blk > known);
+      if (q.room()) q.refill(k0, k1);
     }
     const float a = 2.0f * q.uniform() - 1.0f;
     const float b = 2.0f * q.uniform() - 1.0f;
@@ -428,16 +426,16 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
         const float apath = __uint_as_float(E(kPA + 5)), bpath = __uint_as_float(E(kPB + 5));
         tau = a_pos ? (bpath - apath) * 0.5f : (apath - bpath) * 0.5f;
         if (p.tof_sigma > 0.0f) {
-          // the history's stream where photon B left it: word `pos`, with
-          // blocks below (pos + buffered) / 4 generated then
+          // the history's stream where photon B left it: word `pos`
           RegRng q;
           q.start(hh);
           q.blk = pos >> 2;
-          const uint32_t known = (pos + (flags & 0xffu)) >> 2;
-          SSE_COUNT(kStRngBlocks, q.blk >= known);
           q.refill(k0, k1);
           for (uint32_t i = 0; i < (pos & 3u); ++i) q.take();
-          tau = tau + p.tof_sigma * std_normal<kInstr>(q, known, p, s_stats);
+          tau = tau + p.tof_sigma * std_normal(q, p);
+          // blocks the jitter adds to those counted when photon B ended
+          if (kInstr && p.stats)
+            atomicAdd(&s_stats[kStRngBlocks], blocks_used(q.blk * 4u - q.left) - blocks_used(pos));
         }
         const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
         if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
@@ -635,10 +633,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          const bool valid = qnext + lane < end;
           emit_to_queue(p, qnext + lane, eq);
-          SSE_COUNT(kStRngBlocks, valid);
-          SSE_COUNT(kStRngBlocks, valid);
           qbase = qnext;
           qn = end - qnext < 64u ? static_cast<uint32_t>(end - qnext) : 64u;
           qnext += qn;
@@ -657,9 +652,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (__any(phase != kDone && r.room())) {
-        const bool g = phase != kDone && r.room();
-        if (g) r.refill(k0, k1);
-        SSE_COUNT(kStRngBlocks, g);
+        if (phase != kDone && r.room()) r.refill(k0, k1);
       }
     }
 
@@ -673,9 +666,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     while (__any(phase == kTrack) && (__popcll(__ballot(phase == kTrack)) > kStepTail ||
                                       !__any(phase != kTrack && phase != kDone))) {
       if (__any(phase == kTrack && r.left < 2u)) {
-        const bool g = phase != kDone && r.room();
-        if (g) r.refill(k0, k1);
-        SSE_COUNT(kStRngBlocks, g);
+        if (phase != kDone && r.room()) r.refill(k0, k1);
       }
       // One tentative step per tracking lane, written with selects rather
       // than branches (a masked lane costs the same issue slot): the step's
@@ -847,7 +838,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             hz = zz;
             path = len + tc;
             if (p.e_fwhm > 0.0f) {
-              const float nrm = std_normal<kInstr>(r, 0u, p, s_stats);
+              const float nrm = std_normal(r, p);
               const float sig = (p.e_fwhm / 2.35482f) * sqrtf(kMec2 / ec.E);
               edet = ec.E * (1.0f + sig * nrm);
             }
@@ -915,7 +906,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           if (slot < p.pair_cap) {  // always, by the launch size; a guard for the memory
             uint4* w = reinterpret_cast<uint4*>(p.pairs + slot * kPairWords);
             w[0] = make_uint4(static_cast<uint32_t>(h), static_cast<uint32_t>(h >> 32), r.blk * 4u - r.left,
-                              r.left | (scattered ? 0x100u : 0u) | (p.item << 16));
+                              (scattered ? 0x100u : 0u) | (p.item << 16));
             w[1] = make_uint4(stash[lane], stash[64u + lane], stash[128u + lane], stash[192u + lane]);
             w[2] = make_uint4(stash[256u + lane], stash[320u + lane], stash[384u + lane], __float_as_uint(hx));
             w[3] = make_uint4(__float_as_uint(hy), __float_as_uint(dx), __float_as_uint(dy), __float_as_uint(dz));
@@ -924,6 +915,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         }
         pushed = both;
         SSE_COUNT(kStHist, true);
+        if (kInstr && p.stats) atomicAdd(&s_stats[kStRngBlocks], blocks_used(r.blk * 4u - r.left));
         SSE_COUNT(kStRejWindow, a_det && det && !both);
         if (kInstr && rec) {
           if (!both) {
