@@ -262,11 +262,11 @@ sse_status ensure_scratch(sse_ctx* c) {
 // Separable smoothing of `in` (binary32, or binary64 weights times `scale`
 // rounded on load) into `out`, optionally multiplied by the sensitivity.
 sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, float* out, const float* sigma,
-                  float truncate, const float* sens, hipStream_t s) {
+                  float truncate, const float* sens, hipStream_t s, const float* norm = nullptr) {
   if (!sigma) return fail(SSE_EINVAL, "null sigma");
   if (!in || !out) return fail(SSE_EINVAL, "null buffer");
   if (!(truncate > 0.0f) || !std::isfinite(truncate)) return fail(SSE_EINVAL, "truncate must be positive");
-  sse::Taps taps[3];
+  sse::Taps taps[3] = {};
   int axes[3], na = 0;
   for (int a = 0; a < 3; ++a) {
     const float sg = sigma[a];
@@ -286,13 +286,9 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
     axes[na++] = a;
   }
   const sse::PostParams g = post_params(c);
-  if (na == 0) {
-    if (in_is_f64) {
-      HIP_TRY(sse::launch_scale_to_float(g, static_cast<const double*>(in), scale, out, s), "scale kernel");
-    } else if (in != out) {
-      HIP_TRY(hipMemcpyAsync(out, in, c->n_bins * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
-    }
-    if (sens) HIP_TRY(sse::launch_multiply_sens(g, out, sens, c->sens_tof, out, s), "sensitivity kernel");
+  if (na == 0) {  // elementwise (in place allowed)
+    HIP_TRY(sse::launch_smooth_axis(g, -1, in, in_is_f64, scale, norm, out, taps[0], norm, sens, c->sens_tof, s),
+            "pointwise kernel");
     return SSE_OK;
   }
   sse_status st = ensure_scratch(c);
@@ -305,8 +301,8 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
   for (int i = 0; i < na; ++i) {
     const bool last = i == na - 1;
     dst = (last && !(na == 1 && in == out)) ? out : c->d_scratch[i % 2];
-    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, src_f64, scale, dst, taps[i], last ? sens : nullptr,
-                                    c->sens_tof, s),
+    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, src_f64, scale, i == 0 ? norm : nullptr, dst, taps[i],
+                                    last ? norm : nullptr, last ? sens : nullptr, c->sens_tof, s),
             "smoothing kernel");
     src = dst;
     src_f64 = false;

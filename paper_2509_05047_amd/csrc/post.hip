@@ -5,17 +5,18 @@
 // The final scatter estimate is the LUT-weighted simulator sinogram times the
 // scatter-sensitivity sinogram (Methods, "Scatter sensitivity sinogram"); the
 // smoothing runs along the radial, angular and planar axes (Methods, "Known
-// activity distribution, very limited simulation time"), here as one pass per
-// axis over a 3D grid: x covers the radial index, y the view, z the
-// (tof, plane) pair, so no thread divides 64-bit indices.  In the fused
-// finalize the first pass reads the binary64 weights (scaled and rounded to
-// binary32 on load) and the last pass multiplies by the sensitivity.
+// activity distribution, very limited simulation time"), one pass per axis,
+// each staging its input through LDS so that HBM sees every element read
+// and written once per pass.  In the fused finalize the first pass reads the
+// binary64 weights (scaled and rounded to binary32 on load) and the last
+// pass multiplies by the sensitivity; with a smoothing normalisation
+// sinogram the first pass also multiplies by it and the last divides by it
+// (Discussion / Methods: the simulator output is normalised before smoothing
+// and the structures re-applied after).
 #include "internal.h"
 
 namespace sse {
 namespace {
-
-constexpr int kRadBlock = 128;
 
 // out[t][inner] = (float)((scale * W) * sens[t][inner] or sens[inner])
 __global__ void __launch_bounds__(256) apply_sens_kernel(const double* __restrict__ W, double scale,
@@ -36,75 +37,140 @@ __device__ __forceinline__ int reflect(int i, int n) {
   return m < n ? m : period - 1 - m;
 }
 
+// Arguments of one smoothing pass.
+struct SmoothArgs {
+  PostParams g;
+  const void* in;         // binary32, or binary64 weights times `scale` (rounded on load)
+  double scale;
+  const float* norm_in;   // multiplies the input on load (or NULL)
+  float* out;
+  const float* norm_out;  // divides the output (entries <= 0 count as 1; or NULL)
+  const float* sens;      // multiplies the output (or NULL)
+  int sens_tof;
+  Taps taps;
+};
+
 template <bool kFromF64>
-__device__ __forceinline__ float load_in(const void* in, uint64_t i, double scale) {
-  if (kFromF64) return static_cast<float>(scale * static_cast<const double*>(in)[i]);
-  return static_cast<const float*>(in)[i];
+__device__ __forceinline__ float load_in(const SmoothArgs& a, uint64_t i) {
+  float v;
+  if (kFromF64) v = static_cast<float>(a.scale * static_cast<const double*>(a.in)[i]);
+  else v = static_cast<const float*>(a.in)[i];
+  if (a.norm_in) v = v * a.norm_in[i];
+  return v;
 }
 
-// One separable pass along `axis` (0 radial, 1 view, 2 plane).
-template <int kAxis, bool kFromF64, bool kMulSens>
-__global__ void __launch_bounds__(kRadBlock) smooth_pass(PostParams g, const void* __restrict__ in,
-                                                          float* __restrict__ out, Taps taps, double scale,
-                                                          const float* __restrict__ sens, int sens_tof) {
-  const int r = blockIdx.x * kRadBlock + threadIdx.x;
-  if (r >= g.n_rad) return;
-  const int v = blockIdx.y;
-  const int t = blockIdx.z / g.n_plane;
-  const int pl = blockIdx.z - t * g.n_plane;
-  const uint64_t row = static_cast<uint64_t>(g.n_rad);
-  const uint64_t vstride = row;
-  const uint64_t pstride = row * g.n_view;
-  const uint64_t tstride = pstride * g.n_plane;
-  const uint64_t o = static_cast<uint64_t>(t) * tstride + static_cast<uint64_t>(pl) * pstride +
-                     static_cast<uint64_t>(v) * vstride + static_cast<uint64_t>(r);
-  const int radius = taps.radius;
-  float acc = 0.0f;
-  if (kAxis == 0) {
-    const uint64_t base = o - r;
-    for (int k = -radius; k <= radius; ++k) acc += taps.w[k + radius] * load_in<kFromF64>(in, base + reflect(r + k, g.n_rad), scale);
-  } else if (kAxis == 2) {
-    const uint64_t base = o - static_cast<uint64_t>(pl) * pstride;
-    for (int k = -radius; k <= radius; ++k)
-      acc += taps.w[k + radius] * load_in<kFromF64>(in, base + static_cast<uint64_t>(reflect(pl + k, g.n_plane)) * pstride, scale);
-  } else {
-    // views are periodic over 180 degrees; past the seam the same LOR is
-    // seen from the other end (radial and TOF indices reversed)
-    const int period = 2 * g.n_view;
-    const uint64_t plane_off = static_cast<uint64_t>(pl) * pstride;
-    const uint64_t direct = static_cast<uint64_t>(t) * tstride + plane_off + static_cast<uint64_t>(r);
-    const uint64_t flipped = static_cast<uint64_t>(g.n_tof - 1 - t) * tstride + plane_off +
-                             static_cast<uint64_t>(g.n_rad - 1 - r);
-    for (int k = -radius; k <= radius; ++k) {
-      int m = (v + k) % period;
-      if (m < 0) m += period;
-      const uint64_t idx = m < g.n_view ? direct + static_cast<uint64_t>(m) * vstride
-                                        : flipped + static_cast<uint64_t>(m - g.n_view) * vstride;
-      acc += taps.w[k + radius] * load_in<kFromF64>(in, idx, scale);
+__device__ __forceinline__ float finish_out(const SmoothArgs& a, float acc, uint64_t o, uint64_t inner) {
+  if (a.norm_out) {
+    const float nrm = a.norm_out[o];
+    acc = nrm > 0.0f ? acc / nrm : acc;
+  }
+  if (a.sens) acc = acc * a.sens[a.sens_tof ? o : o % inner];
+  return acc;
+}
+
+// Passes along the view (kAxis 1) or plane (kAxis 2) axis.  A block stages
+// a tile of kTL positions along the axis (plus the kernel's halo) by kTC
+// consecutive radial columns in LDS -- every input read once, in 128-byte
+// rows -- and computes the tile's outputs from LDS.  Views are periodic over
+// 180 degrees, and past the seam the same LOR is seen from the other end
+// (radial and TOF indices reversed); planes reflect at the ends.
+constexpr int kTC = 32;
+constexpr int kTL = 128;
+
+template <int kAxis, bool kFromF64>
+__global__ void __launch_bounds__(256) smooth_cols(SmoothArgs a) {
+  __shared__ float tile[(kTL + 2 * kMaxSmoothRadius) * kTC];
+  const PostParams& g = a.g;
+  const int R = a.taps.radius;
+  const int n = kAxis == 1 ? g.n_view : g.n_plane;
+  const int n_other = kAxis == 1 ? g.n_plane : g.n_view;
+  const int r0 = blockIdx.x * kTC;
+  const int p0 = blockIdx.y * kTL;
+  const int tl = n - p0 < kTL ? n - p0 : kTL;
+  const int t = blockIdx.z / n_other;
+  const int other = blockIdx.z - t * n_other;
+  const uint64_t vs = static_cast<uint64_t>(g.n_rad);
+  const uint64_t ps = vs * g.n_view;
+  const uint64_t ts = ps * g.n_plane;
+  const int col = threadIdx.x & (kTC - 1);
+  const int sub = threadIdx.x / kTC;
+  constexpr int kRowsPerSweep = 256 / kTC;
+  const int r = r0 + col;
+  const int rows = tl + 2 * R;
+  for (int i = sub; i < rows; i += kRowsPerSweep) {
+    const int pos = p0 - R + i;
+    float v = 0.0f;
+    if (r < g.n_rad) {
+      uint64_t idx;
+      if (kAxis == 2) {
+        idx = static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(reflect(pos, g.n_plane)) * ps +
+              static_cast<uint64_t>(other) * vs + static_cast<uint64_t>(r);
+      } else {
+        const int period = 2 * g.n_view;
+        int m = pos % period;
+        if (m < 0) m += period;
+        idx = m < g.n_view ? static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(other) * ps +
+                                 static_cast<uint64_t>(m) * vs + static_cast<uint64_t>(r)
+                           : static_cast<uint64_t>(g.n_tof - 1 - t) * ts + static_cast<uint64_t>(other) * ps +
+                                 static_cast<uint64_t>(m - g.n_view) * vs + static_cast<uint64_t>(g.n_rad - 1 - r);
+      }
+      v = load_in<kFromF64>(a, idx);
     }
+    tile[i * kTC + col] = v;
   }
-  if (kMulSens) {
-    const uint64_t inner = tstride;
-    acc = acc * sens[sens_tof ? o : o - static_cast<uint64_t>(t) * inner];
+  __syncthreads();
+  if (r >= g.n_rad) return;
+  for (int i = sub; i < tl; i += kRowsPerSweep) {
+    float acc = 0.0f;
+    for (int k = 0; k <= 2 * R; ++k) acc += a.taps.w[k] * tile[(i + k) * kTC + col];
+    const int pos = p0 + i;
+    const uint64_t o = kAxis == 2 ? static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(pos) * ps +
+                                        static_cast<uint64_t>(other) * vs + static_cast<uint64_t>(r)
+                                  : static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(other) * ps +
+                                        static_cast<uint64_t>(pos) * vs + static_cast<uint64_t>(r);
+    a.out[o] = finish_out(a, acc, o, ts);
   }
-  out[o] = acc;
 }
 
-// scale * W -> float (with optional sensitivity), used when no axis is smoothed
-__global__ void __launch_bounds__(256) scale_kernel(const double* __restrict__ W, double scale, uint64_t n,
-                                                     float* __restrict__ out) {
+// Pass along the radial axis (contiguous rows, reflected at both ends): each
+// wavefront stages a segment of kSeg outputs of one row plus the halo in LDS.
+constexpr int kSeg = 256;
+
+template <bool kFromF64>
+__global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows) {
+  __shared__ float seg[4][kSeg + 2 * kMaxSmoothRadius];
+  const PostParams& g = a.g;
+  const int R = a.taps.radius;
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const int segs = (g.n_rad + kSeg - 1) / kSeg;
+  const uint64_t job = static_cast<uint64_t>(blockIdx.x) * 4u + w;  // (row, segment)
+  const uint64_t row = job / static_cast<uint64_t>(segs);
+  if (row >= n_rows) return;
+  const int s0 = static_cast<int>(job - row * static_cast<uint64_t>(segs)) * kSeg;
+  const int len = g.n_rad - s0 < kSeg ? g.n_rad - s0 : kSeg;
+  const uint64_t base = row * static_cast<uint64_t>(g.n_rad);
+  float* buf = seg[w];
+  for (int i = static_cast<int>(lane); i < len + 2 * R; i += 64)
+    buf[i] = load_in<kFromF64>(a, base + static_cast<uint64_t>(reflect(s0 - R + i, g.n_rad)));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint64_t inner = static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane;
+  for (int i = static_cast<int>(lane); i < len; i += 64) {
+    float acc = 0.0f;
+    for (int k = 0; k <= 2 * R; ++k) acc += a.taps.w[k] * buf[i + k];
+    const uint64_t o = base + static_cast<uint64_t>(s0 + i);
+    a.out[o] = finish_out(a, acc, o, inner);
+  }
+}
+
+// No axis smoothed: out = ((float)(scale W) or in) * norm_in / norm_out * sens.
+template <bool kFromF64>
+__global__ void __launch_bounds__(256) pointwise_kernel(SmoothArgs a, uint64_t n) {
+  const uint64_t inner = static_cast<uint64_t>(a.g.n_rad) * a.g.n_view * a.g.n_plane;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    out[i] = static_cast<float>(scale * W[i]);
-}
-
-__global__ void __launch_bounds__(256) mul_sens_kernel(const float* __restrict__ in, const float* __restrict__ sens,
-                                                        uint64_t inner, int sens_tof, float* __restrict__ out) {
-  const uint64_t base = static_cast<uint64_t>(blockIdx.y) * inner;
-  const uint64_t sbase = sens_tof ? base : 0;
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < inner; j += stride)
-    out[base + j] = in[base + j] * sens[sbase + j];
+    a.out[i] = finish_out(a, load_in<kFromF64>(a, i), i, inner);
 }
 
 uint64_t inner_bins(const PostParams& g) { return static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane; }
@@ -112,21 +178,6 @@ uint64_t inner_bins(const PostParams& g) { return static_cast<uint64_t>(g.n_rad)
 int blocks_for(uint64_t inner) {
   const uint64_t b = (inner + 255) / 256;
   return static_cast<int>(b < 4096 ? (b ? b : 1) : 4096);
-}
-
-template <int kAxis>
-hipError_t pass(const PostParams& g, const void* in, bool from_f64, float* out, const Taps& taps, double scale,
-                const float* sens, int sens_tof, hipStream_t s) {
-  const dim3 grid((g.n_rad + kRadBlock - 1) / kRadBlock, g.n_view, g.n_plane * g.n_tof);
-  if (from_f64 && sens)
-    hipLaunchKernelGGL((smooth_pass<kAxis, true, true>), grid, dim3(kRadBlock), 0, s, g, in, out, taps, scale, sens, sens_tof);
-  else if (from_f64)
-    hipLaunchKernelGGL((smooth_pass<kAxis, true, false>), grid, dim3(kRadBlock), 0, s, g, in, out, taps, scale, sens, sens_tof);
-  else if (sens)
-    hipLaunchKernelGGL((smooth_pass<kAxis, false, true>), grid, dim3(kRadBlock), 0, s, g, in, out, taps, scale, sens, sens_tof);
-  else
-    hipLaunchKernelGGL((smooth_pass<kAxis, false, false>), grid, dim3(kRadBlock), 0, s, g, in, out, taps, scale, sens, sens_tof);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -139,26 +190,35 @@ hipError_t launch_apply_sensitivity(const PostParams& g, const double* W, double
   return hipGetLastError();
 }
 
-hipError_t launch_scale_to_float(const PostParams& g, const double* W, double scale, float* out,
-                                 hipStream_t stream) {
-  const uint64_t n = inner_bins(g) * g.n_tof;
-  hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, W, scale, n, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_multiply_sens(const PostParams& g, const float* in, const float* sens, int sens_tof,
-                                float* out, hipStream_t stream) {
-  const uint64_t inner = inner_bins(g);
-  hipLaunchKernelGGL(mul_sens_kernel, dim3(blocks_for(inner), g.n_tof), dim3(256), 0, stream, in, sens, inner,
-                     sens_tof, out);
-  return hipGetLastError();
-}
-
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
-                              float* out, const Taps& taps, const float* sens, int sens_tof, hipStream_t stream) {
-  if (axis == 0) return pass<0>(g, in, in_is_f64, out, taps, scale, sens, sens_tof, stream);
-  if (axis == 1) return pass<1>(g, in, in_is_f64, out, taps, scale, sens, sens_tof, stream);
-  return pass<2>(g, in, in_is_f64, out, taps, scale, sens, sens_tof, stream);
+                              const float* norm_in, float* out, const Taps& taps, const float* norm_out,
+                              const float* sens, int sens_tof, hipStream_t stream) {
+  SmoothArgs a{g, in, scale, norm_in, out, norm_out, sens, sens_tof, taps};
+  const uint64_t n_bins = inner_bins(g) * static_cast<uint64_t>(g.n_tof);
+  if (axis < 0) {
+    if (in_is_f64) hipLaunchKernelGGL(pointwise_kernel<true>, dim3(blocks_for(n_bins)), dim3(256), 0, stream, a, n_bins);
+    else hipLaunchKernelGGL(pointwise_kernel<false>, dim3(blocks_for(n_bins)), dim3(256), 0, stream, a, n_bins);
+    return hipGetLastError();
+  }
+  if (axis == 0) {
+    const uint64_t rows = static_cast<uint64_t>(g.n_view) * g.n_plane * g.n_tof;
+    const uint64_t jobs = rows * static_cast<uint64_t>((g.n_rad + kSeg - 1) / kSeg);
+    const dim3 grid(static_cast<unsigned>((jobs + 3) / 4));
+    if (in_is_f64) hipLaunchKernelGGL(smooth_rows<true>, grid, dim3(256), 0, stream, a, rows);
+    else hipLaunchKernelGGL(smooth_rows<false>, grid, dim3(256), 0, stream, a, rows);
+    return hipGetLastError();
+  }
+  const int n = axis == 1 ? g.n_view : g.n_plane;
+  const int n_other = axis == 1 ? g.n_plane : g.n_view;
+  const dim3 grid((g.n_rad + kTC - 1) / kTC, (n + kTL - 1) / kTL, static_cast<unsigned>(n_other * g.n_tof));
+  if (axis == 1) {
+    if (in_is_f64) hipLaunchKernelGGL((smooth_cols<1, true>), grid, dim3(256), 0, stream, a);
+    else hipLaunchKernelGGL((smooth_cols<1, false>), grid, dim3(256), 0, stream, a);
+  } else {
+    if (in_is_f64) hipLaunchKernelGGL((smooth_cols<2, true>), grid, dim3(256), 0, stream, a);
+    else hipLaunchKernelGGL((smooth_cols<2, false>), grid, dim3(256), 0, stream, a);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace sse
