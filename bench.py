@@ -60,6 +60,42 @@ def measured_traffic():
     return float(fields["fetch_bytes_per_step"]) + float(fields["write_bytes_per_step"])
 
 
+# The paper's smoothing of the scatter estimate: FWHM [9, 6, 10.5] radial,
+# view and plane bins (Results); the normalisation sinogram is smoothed more
+# heavily (three times these sigmas, a choice: the paper does not say).
+PAPER_FWHM_BINS = (9.0, 6.0, 10.5)
+
+
+def smoothing_normalisation_timing(ctx, weights, scale, out, stream, reps=3):
+    """Outside the timed steps: the smoothing-normalisation workflow on the
+    step's weights -- a normalisation sinogram (heavy smoothing of these
+    weights standing in for the reference cylinder) and the normalised
+    finalize sens * G(S N) / N with the paper's FWHM -- timed with HIP events
+    on the launch stream.  Algorithmic HBM bytes per bin: 40 for the
+    finalize (radial pass reads W and N, writes S N; view pass reads and
+    writes; plane pass reads, N and the sensitivity, writes)."""
+    import torch
+    sigma = tuple(f / 2.35482 for f in PAPER_FWHM_BINS)
+    heavy = tuple(3 * s for s in sigma)
+    norm = torch.empty_like(out)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
+    e[0].record(stream)
+    for i in range(reps):
+        ctx.smoothing_normalisation(weights, scale, norm, heavy, stream=stream)
+        e[1 + i].record(stream)
+    for i in range(reps):
+        ctx.finalize_normalised(weights, scale, norm, out, sigma, stream=stream)
+        e[1 + reps + i].record(stream)
+    torch.cuda.synchronize()
+    t_norm = [e[i].elapsed_time(e[i + 1]) for i in range(reps)]
+    t_fin = [e[reps + i].elapsed_time(e[reps + i + 1]) for i in range(reps)]
+    n_bins = out.numel()
+    fin_ms = float(np.median(t_fin))
+    return {"fwhm_bins": list(PAPER_FWHM_BINS), "normalisation_sigma_bins": list(heavy),
+            "normalisation_ms": float(np.median(t_norm)), "finalize_normalised_ms": fin_ms,
+            "finalize_bytes_per_bin": 40, "finalize_hbm_tbps": 40.0 * n_bins / (fin_ms * 1e-3) / 1e12}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -320,6 +356,7 @@ def main():
     dt = time.perf_counter() - t0
     scatter_per_step = int(out["scatter_counts"].sum(dtype=torch.int64))
     kernel_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+    next1 = smoothing_normalisation_timing(ctx, out["scatter_weights"], scale, final, stream)
     ctx.close()
 
     per_hist = {k: stats[v] / stats["histories"] for k, v in
@@ -347,6 +384,7 @@ def main():
                    "histories_per_step": n, "lut_dtype": args.lut, "transport": "f32",
                    "accumulation": "f64"},
         "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
+        "smoothing_normalisation": next1,
         "simulate_ms": float(np.mean(kernel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,

@@ -260,6 +260,30 @@ sse_status sse_gaussian_smooth(sse_ctx* ctx, const float* in, float* out, const 
 sse_status sse_finalize(sse_ctx* ctx, const double* W, double scale, const float* sigma_bins,
                         float truncate, float* out, void* stream);
 
+/* Smoothing normalisation sinogram (Methods, "Known activity distribution,
+ * very limited simulation time"): the simulated LUT scatter of a reference
+ * object (the paper: a 40 cm cylinder), heavily smoothed and divided by its
+ * unsmoothed self, N[b] = G_heavy(S)[b] / S[b] with S = float(scale * W) and
+ * G_heavy the smoothing of sse_gaussian_smooth with sigma_bins.  Bins where
+ * S or G_heavy(S) is not positive get N = 1 (a reading: the paper does not
+ * say).  W: device, n_bins binary64 weights of the reference simulation;
+ * norm_out: device, n_bins binary32, caller-owned.  Asynchronous on stream.
+ * Errors: as sse_gaussian_smooth. */
+sse_status sse_smoothing_normalisation(sse_ctx* ctx, const double* W, double scale, const float sigma_bins[3],
+                                       float truncate, float* norm_out, void* stream);
+
+/* Normalised finalize: out = sens * G(S * N) / N with S = float(scale * W),
+ * N a smoothing normalisation sinogram (entries <= 0 count as 1) and G the
+ * smoothing of sse_gaussian_smooth: the simulator output is multiplied by N
+ * to remove the LUT's high-frequency structures, smoothed, divided by N to
+ * re-apply them, and multiplied by the scatter-sensitivity sinogram (same
+ * passage).  The paper smooths with FWHM [9, 6, 10.5] radial, view and plane
+ * bins (sigma = FWHM / 2.35482).  One fused three-pass run over all planes.
+ * W, norm, out: device, n_bins each; out must not overlap W or norm.
+ * Errors: SSE_EINVAL, SSE_ESTATE (no sensitivity). */
+sse_status sse_finalize_normalised(sse_ctx* ctx, const double* W, double scale, const float* norm,
+                                   const float sigma_bins[3], float truncate, float* out, void* stream);
+
 /* Host helper: the integer alias table the library samples emission voxels
  * with.  Activity is quantised to integer masses q_i summing to n 2^32
  * (q_i = floor(a_i n 2^32 / sum a), remainder to the first largest voxel);

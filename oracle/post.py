@@ -148,3 +148,33 @@ def gaussian_smooth_at(sino: np.ndarray, sigma_bins, points, truncate: float = 4
                 acc += wr[c + rr] * x[t, p, v, r].astype(np.float64)
             out += wp[a + rp] * wv[b + rv] * acc
     return out
+
+
+def smoothing_normalisation(weights: np.ndarray, scale: float, sigma_bins, truncate: float = 4.0) -> np.ndarray:
+    """Smoothing normalisation sinogram (Methods, "Known activity
+    distribution, very limited simulation time"): the scaled LUT scatter S of
+    a reference object, heavily smoothed and divided by itself,
+    N = G_heavy(S) / S, in binary64; 1 where S or G_heavy(S) is not positive
+    (a reading: the paper does not say)."""
+    S = scale * np.asarray(weights, np.float64)
+    G = gaussian_smooth(S, sigma_bins, truncate).reshape(S.shape)
+    N = np.ones_like(S)
+    ok = (S > 0) & (G > 0)
+    N[ok] = G[ok] / S[ok]
+    return N
+
+
+def finalize_normalised(weights: np.ndarray, scale: float, norm: np.ndarray, sigma_bins, sens: np.ndarray,
+                        truncate: float = 4.0) -> np.ndarray:
+    """Normalised smoothing of the scaled LUT scatter S = scale * W (same
+    passage): multiply by the normalisation N, smooth, divide by N (entries
+    <= 0 count as 1), multiply by the scatter sensitivity; binary64."""
+    S = scale * np.asarray(weights, np.float64)
+    N = np.asarray(norm, np.float64).reshape(S.shape)
+    Nd = np.where(N > 0, N, 1.0)
+    x = S * N
+    sm = gaussian_smooth(x, sigma_bins, truncate).reshape(S.shape)
+    s = np.asarray(sens, np.float64)
+    if s.ndim == S.ndim - 1:
+        s = s[None]
+    return sm / Nd * s

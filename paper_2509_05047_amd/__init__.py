@@ -106,6 +106,8 @@ SIGNATURES = {
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
     "sse_gaussian_smooth": ([_P, _P, _P, _P, C.c_float, _P], C.c_int),
     "sse_finalize": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
+    "sse_smoothing_normalisation": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
+    "sse_finalize_normalised": ([_P, _P, C.c_double, _P, _P, C.c_float, _P, _P], C.c_int),
     "sse_build_alias_table": ([_P, C.c_uint64, _P, _P], C.c_int),
     "sse_server_start": ([_P, _P, C.POINTER(C.c_void_p)], C.c_int),
     "sse_server_submit": ([_P, _P, C.POINTER(C.c_uint64)], C.c_int),
@@ -301,6 +303,19 @@ class Context:
     def finalize(self, weights, scale: float, out, sigma_bins=None, truncate: float = 4.0, stream=None):
         s = None if sigma_bins is None else (C.c_float * 3)(*sigma_bins)
         _check(lib().sse_finalize(self._h, _ptr(weights), scale, s, truncate, _ptr(out), _stream_ptr(stream)))
+
+    def smoothing_normalisation(self, weights, scale: float, out, sigma_bins, truncate: float = 4.0, stream=None):
+        """out = G_heavy(S) / S (1 where undefined), S = float(scale * weights)."""
+        s = (C.c_float * 3)(*sigma_bins)
+        _check(lib().sse_smoothing_normalisation(self._h, _ptr(weights), scale, s, truncate, _ptr(out),
+                                                 _stream_ptr(stream)))
+
+    def finalize_normalised(self, weights, scale: float, norm, out, sigma_bins, truncate: float = 4.0,
+                            stream=None):
+        """out = sens * G(S * norm) / norm, S = float(scale * weights)."""
+        s = (C.c_float * 3)(*sigma_bins)
+        _check(lib().sse_finalize_normalised(self._h, _ptr(weights), scale, _ptr(norm), s, truncate, _ptr(out),
+                                             _stream_ptr(stream)))
 
 
 def stats_dict(t) -> dict:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "context.h"
+#include "post.h"
 
 namespace sse_detail {
 
@@ -620,6 +621,28 @@ sse_status sse_finalize(sse_ctx* c, const double* W, double scale, const float* 
   if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
   HIP_TRY(hipSetDevice(c->device), "set device");
   return smooth(c, W, true, scale, out, sigma_bins, truncate, c->d_sens, static_cast<hipStream_t>(stream));
+}
+
+sse_status sse_smoothing_normalisation(sse_ctx* c, const double* W, double scale, const float sigma_bins[3],
+                                       float truncate, float* norm_out, void* stream) {
+  if (!c || !W || !norm_out || !sigma_bins) return fail(SSE_EINVAL, "null argument");
+  if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const sse_status st = smooth(c, W, true, scale, norm_out, sigma_bins, truncate, nullptr, s);
+  if (st != SSE_OK) return st;
+  HIP_TRY(sse::launch_norm_ratio(post_params(c), W, scale, norm_out, s), "normalisation kernel");
+  return SSE_OK;
+}
+
+sse_status sse_finalize_normalised(sse_ctx* c, const double* W, double scale, const float* norm,
+                                   const float sigma_bins[3], float truncate, float* out, void* stream) {
+  if (!c || !W || !norm || !out || !sigma_bins) return fail(SSE_EINVAL, "null argument");
+  if (!c->d_sens) return fail(SSE_ESTATE, "no sensitivity sinogram loaded");
+  if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
+  if (static_cast<const void*>(out) == static_cast<const void*>(norm)) return fail(SSE_EINVAL, "out overlaps norm");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  return smooth(c, W, true, scale, out, sigma_bins, truncate, c->d_sens, static_cast<hipStream_t>(stream), norm);
 }
 
 }  // extern "C"

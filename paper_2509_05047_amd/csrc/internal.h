@@ -187,25 +187,4 @@ struct BatchParams {
 // in all): pair-counter reset, transport, coincidences.
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
 
-struct PostParams {
-  int n_rad, n_view, n_plane, n_tof;
-};
-
-hipError_t launch_apply_sensitivity(const PostParams& g, const double* W, double scale, const float* sens,
-                                    int sens_tof, float* out, hipStream_t stream);
-constexpr int kMaxSmoothRadius = 63;
-// Normalised Gaussian taps w[0 .. 2*radius], passed by value to the kernel.
-struct Taps {
-  float w[2 * kMaxSmoothRadius + 1];
-  int radius;
-};
-// One separable pass along axis (0 radial, 1 view, 2 plane; -1: no
-// smoothing, pointwise only).  The input is binary32, or binary64 weights
-// scaled by `scale` and rounded on load (in_is_f64); norm_in (if not NULL)
-// multiplies the input on load; norm_out (if not NULL) divides the output
-// (entries <= 0 count as 1) and sens (if not NULL) multiplies it.
-hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
-                              const float* norm_in, float* out, const Taps& taps, const float* norm_out,
-                              const float* sens, int sens_tof, hipStream_t stream);
-
 }  // namespace sse

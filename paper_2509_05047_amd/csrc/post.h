@@ -1,0 +1,36 @@
+// Declarations of the sinogram post-processing kernels (sensitivity
+// multiply, smoothing, smoothing normalisation) shared by the library's
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sse {
+
+struct PostParams {
+  int n_rad, n_view, n_plane, n_tof;
+};
+
+hipError_t launch_apply_sensitivity(const PostParams& g, const double* W, double scale, const float* sens,
+                                    int sens_tof, float* out, hipStream_t stream);
+constexpr int kMaxSmoothRadius = 63;
+// Normalised Gaussian taps w[0 .. 2*radius], passed by value to the kernel.
+struct Taps {
+  float w[2 * kMaxSmoothRadius + 1];
+  int radius;
+};
+// One separable pass along axis (0 radial, 1 view, 2 plane; -1: no
+// smoothing, pointwise only).  The input is binary32, or binary64 weights
+// scaled by `scale` and rounded on load (in_is_f64); norm_in (if not NULL)
+// multiplies the input on load; norm_out (if not NULL) divides the output
+// (entries <= 0 count as 1) and sens (if not NULL) multiplies it.
+hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
+                              const float* norm_in, float* out, const Taps& taps, const float* norm_out,
+                              const float* sens, int sens_tof, hipStream_t stream);
+// norm[b] = G[b] / S[b] with S = float(scale * W[b]), or 1 where S or G is
+// not positive (norm holds G on entry).
+hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale, float* norm, hipStream_t stream);
+
+}  // namespace sse

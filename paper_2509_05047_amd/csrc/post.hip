@@ -13,7 +13,7 @@
 // sinogram the first pass also multiplies by it and the last divides by it
 // (Discussion / Methods: the simulator output is normalised before smoothing
 // and the structures re-applied after).
-#include "internal.h"
+#include "post.h"
 
 namespace sse {
 namespace {
@@ -173,6 +173,17 @@ __global__ void __launch_bounds__(256) pointwise_kernel(SmoothArgs a, uint64_t n
     a.out[i] = finish_out(a, load_in<kFromF64>(a, i), i, inner);
 }
 
+// norm = G / S (S = float(scale W)), 1 where S or G is not positive.
+__global__ void __launch_bounds__(256) norm_ratio_kernel(const double* __restrict__ W, double scale,
+                                                          float* __restrict__ norm, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float s = static_cast<float>(scale * W[i]);
+    const float gs = norm[i];
+    norm[i] = (s > 0.0f && gs > 0.0f) ? gs / s : 1.0f;
+  }
+}
+
 uint64_t inner_bins(const PostParams& g) { return static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane; }
 
 int blocks_for(uint64_t inner) {
@@ -187,6 +198,12 @@ hipError_t launch_apply_sensitivity(const PostParams& g, const double* W, double
   const uint64_t inner = inner_bins(g);
   hipLaunchKernelGGL(apply_sens_kernel, dim3(blocks_for(inner), g.n_tof), dim3(256), 0, stream, W, scale, sens, inner,
                      sens_tof, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale, float* norm, hipStream_t stream) {
+  const uint64_t n = inner_bins(g) * static_cast<uint64_t>(g.n_tof);
+  hipLaunchKernelGGL(norm_ratio_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, W, scale, norm, n);
   return hipGetLastError();
 }
 

@@ -291,6 +291,87 @@ def test_clinical_finalize_matches_oracle_on_sampled_bins():
     assert np.max(np.abs(g - ref) / np.abs(ref)) < 1e-5
 
 
+PAPER_SIGMA = tuple(f / 2.35482 for f in (9.0, 6.0, 10.5))   # FWHM [9, 6, 10.5] rad/view/plane bins
+
+
+def _pattern(shape, seed):
+    """Seeded multiplicative detector-like pattern (per radial bin and view)."""
+    rng = np.random.default_rng(seed)
+    nt, npl, nv, nr = shape
+    p = (1.0 + 0.3 * rng.uniform(-1, 1, nr))[None, None, None, :] * (1.0 + 0.2 * rng.uniform(-1, 1, nv))[None, None, :, None]
+    return np.broadcast_to(p, shape).astype(np.float64)
+
+
+def test_smoothing_normalisation_workflow_matches_oracle_tiny():
+    """The smoothing normalisation of a structured reference sinogram (heavy
+    smoothing), then the normalised finalize of another sinogram with the
+    paper's FWHM, on the whole tiny sinogram."""
+    case = H.case_from("tiny")
+    sino = case.sino
+    rng = np.random.default_rng(8)
+    P = _pattern(sino.shape, 9)
+    Wref = P * rng.uniform(0.5, 1.5, sino.shape)
+    Wref[0, 0, 0, :4] = 0.0
+    Wobj = P * rng.uniform(0.0, 2.0, sino.shape)
+    sens = W.make_sensitivity(sino, seed=3, tof_axis=False)
+    heavy = tuple(3 * s for s in PAPER_SIGMA)
+    ctx, pid = H.open_context(case, sensitivity=sens, sens_tof=False)
+    try:
+        dref = torch.from_numpy(Wref.ravel()).cuda()
+        dobj = torch.from_numpy(Wobj.ravel()).cuda()
+        norm = torch.empty(sino.n_bins, dtype=torch.float32, device="cuda")
+        out = torch.empty(sino.n_bins, dtype=torch.float32, device="cuda")
+        ctx.smoothing_normalisation(dref, 0.25, norm, heavy)
+        torch.cuda.synchronize()
+        got_n = norm.cpu().numpy().reshape(sino.shape)
+        # the finalize gets the oracle's normalisation (rounded to binary32)
+        # as its input on both sides
+        ref_n = post.smoothing_normalisation(Wref, 0.25, heavy)
+        n32 = ref_n.astype(np.float32)
+        dn = torch.from_numpy(n32.ravel()).cuda()
+        ctx.finalize_normalised(dobj, 0.5, dn, out, PAPER_SIGMA)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(sino.shape)
+    finally:
+        ctx.close()
+    empty = Wref == 0
+    assert np.all(got_n[empty] == 1.0)
+    assert np.max(np.abs(got_n - ref_n) / ref_n) < 1e-5
+    ref = post.finalize_normalised(Wobj, 0.5, n32.astype(np.float64), PAPER_SIGMA, sens)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-5
+
+
+def test_clinical_normalised_finalize_matches_oracle_on_sampled_bins():
+    """Full clinical sinogram shape, paper FWHM, a seeded normalisation:
+    sens * G(S * N) / N checked on 2000 sampled bins (seam and edges
+    included)."""
+    case = H.case_from("clinical")
+    sino = case.sino
+    rng = np.random.default_rng(5)
+    Wd = torch.rand(sino.n_bins, dtype=torch.float64, device="cuda") * 10.0
+    N = (1.0 / _pattern(sino.shape, 6)).astype(np.float32)
+    sens = W.make_sensitivity(sino, seed=3, tof_axis=False)
+    ctx, pid = H.open_context(case, sensitivity=sens, sens_tof=False)
+    try:
+        dn = torch.from_numpy(N.ravel()).cuda()
+        out = torch.empty(sino.n_bins, dtype=torch.float32, device="cuda")
+        ctx.finalize_normalised(Wd, 0.5, dn, out, PAPER_SIGMA)
+        torch.cuda.synchronize()
+        scaled = (0.5 * Wd).float().cpu().numpy().reshape(sino.shape).astype(np.float64)
+        got = out.cpu().numpy().reshape(sino.shape)
+    finally:
+        ctx.close()
+    pts = np.stack([rng.integers(0, s, 2000) for s in sino.shape], 1)
+    pts[:50, 2] = 0
+    pts[50:100, 3] = 0
+    pts[100:150, 1] = sino.n_plane - 1
+    x = scaled * N.astype(np.float64)
+    ref = (post.gaussian_smooth_at(x, PAPER_SIGMA, pts) / N[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]]
+           * sens[pts[:, 1], pts[:, 2], pts[:, 3]])
+    g = got[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]]
+    assert np.max(np.abs(g - ref) / np.abs(ref)) < 1e-5
+
+
 def test_precision_forms_against_fp64_oracle():
     """Narrow-LUT precision forms (config C3) against the FP64 oracle with the
     FP32 LUT.  Bounds: with the same dequantised LUT the binary32 path equals
