@@ -100,12 +100,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, pdesc, mu, act, lut_desc, lut_f32, n):
+def cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut_f32, n):
     """The oracle as it stands, single thread, on the first n histories."""
     import oracle as O
     alias = O.build_alias(act)
     t0 = time.perf_counter()
-    r = O.simulate(w.scanner, w.sino, w.physics, pdesc, mu, alias=alias,
+    r = O.simulate(w.scanner, w.sino, physics, pdesc, mu, alias=alias,
                    lut_desc=lut_desc, lut=lut_f32, seed=w.seed, n=n, trues=False)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "histories/s", "cores": 1, "kind": "oracle",
@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs single-stream throughput")
     ap.add_argument("--histories", type=float, default=0, help="override histories per step")
     ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--lut-mode", default="lut5d", choices=list(W.LUT_MODES),
+                    help="LUT variant and energy configuration (lut5d: the workload's own)")
     ap.add_argument("--cpu-histories", type=int, default=40_000_000)
     ap.add_argument("--copy-bytes", type=float, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates HBM counters)")
@@ -306,13 +308,13 @@ def main():
         return
     w = W.WORKLOADS[args.workload]
     pdesc, mu, act = W.make_phantom(w)
-    lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    physics, lut_desc, lut = W.lut_mode(w, args.lut_mode)
     lut_dtype = {"f32": sse.F32, "f16": sse.F16, "bf16": sse.BF16}[args.lut]
     lut_store = {"f32": lut, "f16": lut.astype(np.float16).view(np.uint16), "bf16": W.to_bf16_bits(lut)}[args.lut]
     n = int(args.histories) if args.histories else w.n_histories
     sens = W.make_sensitivity(w.sino, seed=3, tof_axis=True)
     log(f"[bench] workload {w.name}: {n:.3g} histories/step, sinogram {w.sino.shape}, LUT {args.lut}")
-    ctx = sse.Context(w.scanner, w.sino, w.physics)
+    ctx = sse.Context(w.scanner, w.sino, physics)
     pid = ctx.load_phantom(pdesc, mu, act)
     ctx.load_lut(lut_desc, lut_store, dtype=lut_dtype)
     ctx.load_sensitivity(sens, has_tof_axis=True)
@@ -381,7 +383,9 @@ def main():
                                f"{w.scanner.n_crystals}x{w.scanner.n_rings} scanner, "
                                f"{'x'.join(map(str, w.sino.shape[::-1]))} TOF sinogram (rad x view x plane x tof), "
                                f"{'x'.join(map(str, lut_desc.dims))} {args.lut} LUT",
-                   "histories_per_step": n, "lut_dtype": args.lut, "transport": "f32",
+                   "histories_per_step": n, "lut_dtype": args.lut, "lut_mode": args.lut_mode,
+                   "energy_window_kev": [physics["e_lo_kev"], physics["e_hi_kev"]],
+                   "energy_fwhm": physics["e_fwhm_frac"], "transport": "f32",
                    "accumulation": "f64"},
         "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
         "smoothing_normalisation": next1,
@@ -389,14 +393,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
-                                 and args.lut == "f32" else None),
+                                 and args.lut == "f32" and args.lut_mode == "lut5d" else None),
                      "kernel": "one simulate call: transport + coincidence launches",
                      "span_ms": float(np.mean(kernel_ms)),
                      "ops_per_history": ops_per_hist},
     }
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_histories} histories")
-        result["cpu_baseline"] = cpu_baseline(w, pdesc, mu, act, lut_desc, lut, args.cpu_histories)
+        result["cpu_baseline"] = cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut, args.cpu_histories)
     print(json.dumps(result), flush=True)
 
 

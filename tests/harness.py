@@ -26,10 +26,11 @@ class Case:
     lut_dtype: int = 0
 
 
-def case_from(name, tof_sigma=None, lut_dtype=0, physics=None, phantom=None):
+def case_from(name, tof_sigma=None, lut_dtype=0, physics=None, phantom=None, lut=None):
+    """lut: (LutDesc, float32 values) replacing the workload's own LUT."""
     w = W.WORKLOADS[name]
     pd, mu, act = phantom if phantom is not None else W.make_phantom(w)
-    ld, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    ld, lut = lut if lut is not None else W.make_lut(w.lut_dims, w.lut_seed)
     sino = w.sino if tof_sigma is None else W.Sinogram(**{**w.sino.__dict__, "tof_sigma_mm": tof_sigma})
     store, seen = lut, lut
     if lut_dtype == 1:

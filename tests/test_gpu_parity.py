@@ -67,6 +67,24 @@ def test_tiny_workload_full_parity():
     assert g["scatter_counts"].sum() > 0
 
 
+@pytest.mark.parametrize("mode", ["lut5d_paper", "lut3d_angles", "lut3d_crystals", "lut1d", "nolut"])
+def test_lut_modes_full_parity(mode):
+    """The paper's LUT variants (unit dimensions of the 5D index) with its
+    LUT energy configuration (0.1 % blur, 300-650 keV), and the no-LUT mode
+    (11.2 % blur, 425-650 keV, weight 1), on the whole tiny workload."""
+    w = W.WORKLOADS["tiny"]
+    phys, ld, lut = W.lut_mode(w, mode)
+    case = H.case_from("tiny", physics=phys, lut=(ld, lut))
+    g, o, same = check_case(case, w.n_histories, w.seed)
+    assert same.all()
+    worst = H.compare_sinograms(g, o, g["records"], o["records"], same)
+    say(f"[parity] {mode}: worst relative weight difference {worst:.3e}")
+    stats_match(g["stats"], o["stats"])
+    assert g["scatter_counts"].sum() > 0
+    if mode == "nolut":
+        assert np.array_equal(g["scatter_weights"], g["scatter_counts"].astype(np.float64))
+
+
 def test_clinical_slice_parity_with_offset_and_ragged_count():
     case = H.case_from("clinical")
     g, o, same = check_case(case, 200_003, 5678, h_offset=123_456_789)

@@ -545,3 +545,60 @@ def test_binary64_transport_agrees_with_binary32():
     assert O.real_size("f32") == 4 and O.real_size("f64") == 8
     same = (a["outcome"] == b["outcome"]) & (O.record_bins(a) == O.record_bins(b))
     assert same.mean() > 0.999
+
+
+# ---------------------------------------------------------------------------
+# LUT variants and energy configurations (Methods, "Scatter simulator
+# description"; "Photon detection probability LUT")
+# ---------------------------------------------------------------------------
+
+def test_energy_blur_is_gaussian_with_the_stated_resolution():
+    """Point source in air: every photon arrives at 511 keV, so the detected
+    energies are 511 (1 + sigma n) with sigma = FWHM / 2.35482 (11.2 %, the
+    no-LUT configuration), n standard normal."""
+    w = W.WORKLOADS["tiny"]
+    ld, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    pd, mu, act = W.point_source((0.0, 0.0, 0.0))
+    phys = dict(W.PHYSICS_NO_LUT, e_lo_kev=0.0, e_hi_kev=2000.0)
+    r = run(w.scanner, w.sino, phys, pd, mu, act, ld, lut, 40_000, records=True, sinograms=False, seed=11)
+    ph = r["records"]["ph"]
+    det = (ph["inter"] >> 16) == 0
+    assert np.all(ph["e_kev"][det] == np.float32(510.99895))
+    z = (ph["e_det_kev"][det].astype(np.float64) / 510.99895 - 1.0) / (0.112 / 2.35482)
+    assert det.sum() > 20_000
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.std() - 1.0) < 0.02
+
+
+def test_no_lut_mode_counts_in_window_coincidences_with_weight_one():
+    """No-LUT mode: a one-entry LUT of 1 makes the weighted sinogram the
+    count sinogram, and every counted single lies in the 425-650 keV window
+    after the 11.2 % blur."""
+    w = W.WORKLOADS["tiny"]
+    phys, ld, lut = W.lut_mode(w, "nolut")
+    pd, mu, act = W.make_phantom(w)
+    r = run(w.scanner, w.sino, phys, pd, mu, act, ld, lut, 60_000, records=True, trues=True)
+    assert r["scatter_counts"].sum() > 0
+    assert np.array_equal(r["scatter_weights"], r["scatter_counts"].astype(np.float64))
+    rec = r["records"]
+    counted = (rec["outcome"] & 0xFF) <= 1
+    e = rec["ph"]["e_det_kev"][counted]
+    assert np.all((e >= 425.0) & (e <= 650.0))
+    blurred = rec["ph"]["e_det_kev"] != rec["ph"]["e_kev"]
+    assert blurred[counted].all()
+
+
+@pytest.mark.parametrize("mode", ["lut1d", "lut3d_angles", "lut3d_crystals"])
+def test_reduced_lut_equals_the_5d_lut_constant_along_the_other_axes(mode):
+    """A LUT with unit dimensions gives exactly the sinograms of the 5D LUT
+    that repeats its values along the missing axes (same energy axis)."""
+    w = W.WORKLOADS["tiny"]
+    phys, ld, lut = W.lut_mode(w, mode)
+    full = np.broadcast_to(lut, tuple(max(a, b) for a, b in zip(lut.shape, w.lut_dims))).copy()
+    assert full.shape == tuple(w.lut_dims)
+    ld5 = W.LutDesc(tuple(w.lut_dims), ld.e_min_kev, ld.e_max_kev)
+    pd, mu, act = W.make_phantom(w)
+    a = run(w.scanner, w.sino, phys, pd, mu, act, ld, lut, 50_000)
+    b = run(w.scanner, w.sino, phys, pd, mu, act, ld5, full, 50_000)
+    assert np.array_equal(a["scatter_counts"], b["scatter_counts"])
+    assert np.array_equal(a["scatter_weights"], b["scatter_weights"])

@@ -321,6 +321,41 @@ def make_lut(dims, seed: int, low: float = 0.2, high: float = 1.0, e_min=425.0, 
     return LutDesc(tuple(dims), float(e_min), float(e_max)), vals
 
 
+# The paper's two simulator energy configurations (Methods, "Scatter
+# simulator description"): with the LUT, a near-perfect 0.1 % energy
+# resolution and a 300-650 keV window; without it, GATE's 11.2 % and
+# 425-650 keV.  The kill energies are readings: at least six energy-resolution
+# sigmas below the window, so that no killed photon could have blurred into
+# it (11.2 % FWHM at 300 keV: sigma 18.6 keV, 125 keV below 425).
+PHYSICS_LUT_PAPER = dict(PHYSICS_DEFAULT, e_fwhm_frac=0.001, e_lo_kev=300.0, e_hi_kev=650.0, e_kill_kev=290.0)
+PHYSICS_NO_LUT = dict(PHYSICS_DEFAULT, e_fwhm_frac=0.112, e_lo_kev=425.0, e_hi_kev=650.0, e_kill_kev=300.0)
+
+# LUT variants of the paper's comparison (Methods, "Photon detection
+# probability LUT"; 1D over energy, 3D over energy and the two incidence
+# angles, 3D over energy and the two in-block crystal coordinates, and the
+# full 5D), expressed as unit dimensions of the 5D index, and the no-LUT
+# mode (a single entry of 1: every coincidence counts 1).
+LUT_MODES = ("lut5d", "lut5d_paper", "lut3d_angles", "lut3d_crystals", "lut1d", "nolut")
+
+
+def lut_mode(w: "Workload", mode: str):
+    """(physics, LutDesc, values) of a LUT mode for workload w.  'lut5d' is
+    the workload's own setting (425-650 keV, no blur, LUT energy axis
+    425-511 keV); the others use the paper's energy configurations, the LUT
+    energy axis over 300-511 keV (the 300 keV window edge to the source
+    line)."""
+    d = tuple(w.lut_dims)
+    if mode == "lut5d":
+        ld, vals = make_lut(d, w.lut_seed)
+        return dict(w.physics), ld, vals
+    if mode == "nolut":
+        return dict(PHYSICS_NO_LUT), LutDesc((1, 1, 1, 1, 1), 425.0, 511.0), np.ones((1, 1, 1, 1, 1), np.float32)
+    dims = {"lut5d_paper": d, "lut3d_angles": (d[0], d[1], d[2], 1, 1),
+            "lut3d_crystals": (d[0], 1, 1, d[3], d[4]), "lut1d": (d[0], 1, 1, 1, 1)}[mode]
+    ld, vals = make_lut(dims, w.lut_seed, e_min=300.0, e_max=511.0)
+    return dict(PHYSICS_LUT_PAPER), ld, vals
+
+
 def to_bf16_bits(x: np.ndarray) -> np.ndarray:
     """Round float32 values to bfloat16 (round to nearest even); returns uint16 bits."""
     b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
