@@ -19,11 +19,12 @@ from . import build as _build
 
 ST_NAMES = ["histories", "steps", "real", "compton", "rayleigh", "absorbed", "killed", "capped",
             "escaped", "detected", "in_window", "scatter", "true", "rej_window", "rej_same",
-            "rej_ring", "rej_radial", "rej_tof", "rng_blocks"]
+            "rej_ring", "rej_radial", "rej_tof", "rng_blocks", "rej_gap", "gap_assigned"]
 ST_COUNT = len(ST_NAMES)
 
 FATE = dict(detected=0, absorbed=1, killed=2, capped=3, axial=4)
-OUTCOME = dict(scatter=0, true=1, undetected=2, window=3, same_crystal=4, ring_diff=5, radial=6, tof=7)
+OUTCOME = dict(scatter=0, true=1, undetected=2, window=3, same_crystal=4, ring_diff=5, radial=6, tof=7, gap=8)
+GAP_POLICY = dict(discard=0, nearest=1, edge_lut=2)
 
 _PHOTON_FIELDS = [("hx", "<f4"), ("hy", "<f4"), ("hz", "<f4"), ("dx", "<f4"), ("dy", "<f4"), ("dz", "<f4"),
                   ("e_kev", "<f4"), ("e_det_kev", "<f4"), ("path_mm", "<f4"), ("crystal_ring", "<u4"),
@@ -62,6 +63,16 @@ class Lut(C.Structure):
     _fields_ = [("dims", C.c_int32 * 5), ("e_min_kev", C.c_float), ("e_max_kev", C.c_float)]
 
 
+class Gaps(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("transaxial_gap_rad", C.c_float), ("axial_gap_mm", C.c_float),
+                ("policy", C.c_int32), ("edge_n_angle", C.c_int32), ("edge_n_pos", C.c_int32)]
+
+
+class EdgeGeom(C.Structure):
+    _fields_ = [("gap_mm", C.c_float), ("depth_mm", C.c_float), ("doi_mm", C.c_float),
+                ("mu_per_mm", C.c_float), ("n_angle", C.c_int32), ("n_pos", C.c_int32)]
+
+
 _P = C.c_void_p
 _libs = {}
 
@@ -74,8 +85,8 @@ def _lib(variant: str = "f32"):
         lib = C.CDLL(path)
         lib.orc_build_alias.argtypes = [_P, C.c_uint64, _P, _P]
         lib.orc_build_alias.restype = C.c_int
-        lib.orc_simulate.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64,
-                                     _P, _P, _P, _P, _P, _P, _P]
+        lib.orc_simulate.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                     C.c_uint64, C.c_uint64, C.c_uint64, _P, _P, _P, _P, _P, _P, _P]
         lib.orc_simulate.restype = C.c_int
         lib.orc_philox.argtypes = [_P, _P, _P]
         lib.orc_u01.argtypes = [C.c_uint32]
@@ -89,6 +100,12 @@ def _lib(variant: str = "f32"):
         lib.orc_energy_model.argtypes = [_P, C.c_double, _P]
         lib.orc_lor.argtypes = [C.c_int32, C.c_int32, C.c_int32, _P, _P, _P]
         lib.orc_real_size.restype = C.c_int
+        lib.orc_edge_lut.argtypes = [_P, _P]
+        lib.orc_edge_paths.argtypes = [_P, C.c_double, C.c_double, _P, _P]
+        lib.orc_edge_prob.argtypes = [_P, C.c_double, C.c_double]
+        lib.orc_edge_prob.restype = C.c_double
+        lib.orc_locate.argtypes = [_P, _P, C.c_float, C.c_float, C.c_float, _P, _P]
+        lib.orc_locate.restype = C.c_int
         _libs[variant] = lib
     return _libs[variant]
 
@@ -121,6 +138,19 @@ def phantom_struct(d) -> Phantom:
 
 def lut_struct(d) -> Lut:
     return Lut((C.c_int32 * 5)(*d.dims), d.e_min_kev, d.e_max_kev)
+
+
+def gaps_struct(g) -> Gaps:
+    """From a mapping with transaxial_gap_rad, axial_gap_mm, policy (name or
+    number) and, for the edge-LUT policy, edge_n_angle / edge_n_pos."""
+    pol = g["policy"]
+    pol = GAP_POLICY[pol] if isinstance(pol, str) else int(pol)
+    return Gaps(1, g["transaxial_gap_rad"], g["axial_gap_mm"], pol, int(g.get("edge_n_angle", 0)),
+                int(g.get("edge_n_pos", 0)))
+
+
+def edge_geom_struct(e) -> EdgeGeom:
+    return EdgeGeom(e["gap_mm"], e["depth_mm"], e["doi_mm"], e["mu_per_mm"], int(e["n_angle"]), int(e["n_pos"]))
 
 
 # --------------------------------------------------------------------------
@@ -209,14 +239,53 @@ def lor(n_crystals, c1, c2):
     return int(v[0]), int(r[0]), int(a[0])
 
 
+def edge_lut(geom) -> np.ndarray:
+    """Edge-crystal LUT [angle][position] (float32): probability of the
+    lower-side block for a gap photon (Eq. (1)-(3))."""
+    g = edge_geom_struct(geom)
+    out = np.zeros(g.n_angle * g.n_pos, np.float32)
+    _lib().orc_edge_lut(C.byref(g), _ptr(out))
+    return out.reshape(g.n_angle, g.n_pos)
+
+
+def edge_paths(geom, theta, x0):
+    g = edge_geom_struct(geom)
+    l1, l2 = np.zeros(1), np.zeros(1)
+    _lib().orc_edge_paths(C.byref(g), float(theta), float(x0), _ptr(l1), _ptr(l2))
+    return float(l1[0]), float(l2[0])
+
+
+def edge_prob(geom, theta, x0) -> float:
+    g = edge_geom_struct(geom)
+    return float(_lib().orc_edge_prob(C.byref(g), float(theta), float(x0)))
+
+
+LOCATE_FIELDS = ("crystal", "ring", "ct", "ca", "tgap", "agap", "c_lo", "c_hi", "r_lo", "r_hi")
+
+
+def locate(scanner, gaps, hx, hy, hz):
+    """Where a hit falls with gaps: dict of LOCATE_FIELDS plus 'tfrac', 'afrac'."""
+    s_sc, s_g = scanner_struct(scanner), gaps_struct(gaps)
+    out = np.zeros(10, np.int32)
+    frac = np.zeros(2)
+    if _lib().orc_locate(C.byref(s_sc), C.byref(s_g), hx, hy, hz, _ptr(out), _ptr(frac)) != 0:
+        raise ValueError("bad scanner or gap description")
+    d = {k: int(v) for k, v in zip(LOCATE_FIELDS, out)}
+    d["tfrac"], d["afrac"] = float(frac[0]), float(frac[1])
+    return d
+
+
 def real_size(variant="f32") -> int:
     return int(_lib(variant).orc_real_size())
 
 
 def simulate(scanner, sino, physics, pdesc, mu, activity=None, alias=None, lut_desc=None, lut=None,
              seed=1, h0=0, n=0, h_list=None, sinograms=True, trues=False, records=False,
-             variant="f32"):
+             variant="f32", gaps=None, edge_t=None, edge_a=None):
     """Run the oracle.  ``alias`` is (thresh, alias) or built from ``activity``.
+    ``gaps`` (a mapping, see ``gaps_struct``) switches on the gap model, with
+    the edge LUTs ``edge_t`` / ``edge_a`` ([angle][position] float32) for the
+    edge-LUT policy.
     ``lut`` holds float32 values (dequantised if the LUT is stored narrower).
     Returns a dict with 'scatter_counts', 'scatter_weights' (flat, sinogram
     order [tof][plane][view][rad]), optional trues, 'stats' (dict) and
@@ -239,8 +308,13 @@ def simulate(scanner, sino, physics, pdesc, mu, activity=None, alias=None, lut_d
     rec = np.zeros(n, RECORD_DTYPE) if records else None
     s_sc, s_sn, s_ph = scanner_struct(scanner), sino_struct(sino), physics_struct(physics)
     s_pd, s_ld = phantom_struct(pdesc), lut_struct(lut_desc)
+    s_g = gaps_struct(gaps) if gaps is not None else None
+    et = None if edge_t is None else np.ascontiguousarray(edge_t, np.float32).ravel()
+    ea = None if edge_a is None else np.ascontiguousarray(edge_a, np.float32).ravel()
     rc = _lib(variant).orc_simulate(C.byref(s_sc), C.byref(s_sn), C.byref(s_ph), C.byref(s_pd), _ptr(mu),
-                                    _ptr(th), _ptr(al), C.byref(s_ld), _ptr(lut), seed, h0, n, _ptr(h_list),
+                                    _ptr(th), _ptr(al), C.byref(s_ld), _ptr(lut),
+                                    C.byref(s_g) if s_g is not None else None, _ptr(et), _ptr(ea),
+                                    seed, h0, n, _ptr(h_list),
                                     _ptr(sc_n), _ptr(sc_w), _ptr(tr_n), _ptr(tr_w), _ptr(st), _ptr(rec))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")

@@ -298,6 +298,10 @@ typedef struct {
   vec3 lo, hi, inv_vox, vox;
   real mu_maj;       /* Woodcock majorant at 511 keV */
   real RR, half_len, pitch, e_scale;
+  /* gap model (gp NULL: plain cylinder) */
+  const orc_gaps* gp;
+  const float* edge_t;
+  const float* edge_a;
 } ctx_t;
 
 /* Total Klein-Nishina cross section in units of 2 pi r_e^2, a = E / m_e c^2
@@ -616,17 +620,174 @@ static int bin_angle(double th, int n) {
   return (int)f;
 }
 
-static void single_index(const ctx_t* C, const photon_t* o, int* crystal, int* ring, uint32_t* lut_index) {
-  const orc_scanner* sc = C->sc;
-  /* crystal c covers azimuth [2 pi c / Nc, 2 pi (c + 1) / Nc) */
-  double phi = atan2((double)o->hy, (double)o->hx);
+/* ------------------------------------------------------------------------ */
+/* Gaps between modules and blocks, edge crystals                           */
+/* ------------------------------------------------------------------------ */
+/* Where a hit falls with gaps ("Scatter simulator description", Fig. 4): the
+ * crystal and ring it is assigned to (the nearest edge crystal / ring when it
+ * lies in a gap), the LUT crystal coordinates with their virtual gap indices,
+ * and for a gap hit the edge crystals on either side and the position across
+ * the gap.  Evaluated in binary64. */
+typedef struct {
+  int crystal, ring;    /* assigned (nearest edge for a gap hit) */
+  int ct, ca;           /* LUT coordinates: crystal in module, crystal along the axis */
+  int tgap, agap;       /* 1 if in a transaxial / axial gap */
+  int c_lo, c_hi;       /* transaxial gap: edge crystals of the lower / upper module */
+  int r_lo, r_hi;       /* axial gap: edge rings of the lower / upper block */
+  double tfrac, afrac;  /* position across the gap, 0 at the lower side, 1 at the upper */
+} hit_t;
+
+static int clamp_int(double f, int n) {
+  if (!(f >= 0.0)) return 0;
+  if (f >= (double)n) return n - 1;
+  return (int)f;
+}
+
+static void locate(const orc_scanner* sc, const orc_gaps* gp, double hx, double hy, double hz, hit_t* h) {
+  const int cm = sc->crystals_per_module, rb = sc->rings_per_block;
+  const int nm = sc->n_crystals / cm, nb = sc->n_rings / rb;
+  memset(h, 0, sizeof(*h));
+  /* transaxial: module m spans azimuth [m D, (m + 1) D); half a gap of
+   * angle g at either end, crystals of width (D - g) / cm in between */
+  const double g = (double)gp->transaxial_gap_rad;
+  const double D = TWO_PI_D / (double)nm;
+  double phi = atan2(hy, hx);
   if (phi < 0.0) phi += TWO_PI_D;
-  double fc = floor(phi * (double)sc->n_crystals / TWO_PI_D);
-  int c = (fc >= (double)sc->n_crystals) ? sc->n_crystals - 1 : (fc < 0.0 ? 0 : (int)fc);
-  /* rings tile [-L/2, L/2) */
-  int rg = clamp_index((real)floor((double)((o->hz + C->half_len) / C->pitch)), sc->n_rings);
-  *crystal = c;
-  *ring = rg;
+  const int m = clamp_int(floor(phi / D), nm);
+  const double loc = phi - (double)m * D;
+  if (g > 0.0 && loc < 0.5 * g) {
+    /* upper half of the gap between modules m - 1 and m */
+    h->tgap = 1;
+    h->ct = 0;
+    h->c_lo = ((m + nm - 1) % nm) * cm + cm - 1;
+    h->c_hi = m * cm;
+    h->crystal = h->c_hi;
+    h->tfrac = (loc + 0.5 * g) / g;
+  } else if (g > 0.0 && loc >= D - 0.5 * g) {
+    /* lower half of the gap between modules m and m + 1 */
+    h->tgap = 1;
+    h->ct = cm + 1;
+    h->c_lo = m * cm + cm - 1;
+    h->c_hi = ((m + 1) % nm) * cm;
+    h->crystal = h->c_lo;
+    h->tfrac = (loc - (D - 0.5 * g)) / g;
+  } else {
+    const int k = clamp_int(floor((loc - 0.5 * g) * (double)cm / (D - g)), cm);
+    h->ct = k + 1;
+    h->crystal = m * cm + k;
+  }
+  /* axial: blocks of rb rings of pitch pa, gaps of width w between them */
+  const double L = (double)sc->length_mm, w = (double)gp->axial_gap_mm;
+  const double pa = (L - (double)(nb - 1) * w) / (double)sc->n_rings;
+  const double span = (double)rb * pa;
+  const double period = span + w;
+  const double z = hz + 0.5 * L;
+  const int b = clamp_int(floor(z / period), nb);
+  const double zl = z - (double)b * period;
+  if (w > 0.0 && b < nb - 1 && zl >= span) {
+    /* gap between blocks b and b + 1 */
+    const double go = zl - span;
+    h->agap = 1;
+    h->r_lo = b * rb + rb - 1;
+    h->r_hi = (b + 1) * rb;
+    h->afrac = go / w;
+    if (go < 0.5 * w) {
+      h->ca = b * (rb + 2) + rb + 1;
+      h->ring = h->r_lo;
+    } else {
+      h->ca = (b + 1) * (rb + 2);
+      h->ring = h->r_hi;
+    }
+  } else {
+    const int k = clamp_int(floor(zl / pa), rb);
+    h->ca = b * (rb + 2) + 1 + k;
+    h->ring = b * rb + k;
+  }
+}
+
+/* Path lengths of a straight ray inside the two blocks either side of a gap
+ * ("Edge crystal assignment LUT", Fig. 9).  Coordinates: x across the gap
+ * (0 at its centre, block 1 at x <= -w/2, block 2 at x >= w/2), y the depth
+ * below the blocks' front faces (blocks span 0 <= y <= depth); the ray
+ * crosses the detection surface y = doi at x0 with angle theta to the y axis,
+ * moving towards +x for theta > 0.  The blocks are taken as unbounded away
+ * from the gap. */
+void orc_edge_paths(const orc_edge_geom* g, double theta, double x0, double* l1, double* l2) {
+  const double D = (double)g->depth_mm, d = (double)g->doi_mm, hw = 0.5 * (double)g->gap_mm;
+  const double t = tan(theta), c = cos(theta);
+  *l1 = 0.0;
+  *l2 = 0.0;
+  if (t == 0.0) {
+    /* parallel to the gap walls: inside a block over the whole depth, or in neither */
+    if (x0 <= -hw) *l1 = D;
+    if (x0 >= hw) *l2 = D;
+    return;
+  }
+  /* depths at which the ray crosses x = -w/2 and x = +w/2 */
+  const double y1 = d + (-hw - x0) / t, y2 = d + (hw - x0) / t;
+  double a1, b1, a2, b2;
+  if (t > 0.0) {        /* x grows with depth: block 1 above y1, block 2 below y2 */
+    a1 = 0.0; b1 = fmin(D, y1);
+    a2 = fmax(0.0, y2); b2 = D;
+  } else {              /* x falls with depth: block 2 above y2, block 1 below y1 */
+    a1 = fmax(0.0, y1); b1 = D;
+    a2 = 0.0; b2 = fmin(D, y2);
+  }
+  if (b1 > a1) *l1 = (b1 - a1) / c;
+  if (b2 > a2) *l2 = (b2 - a2) / c;
+}
+
+/* Eq. (1)-(3) in the reading that makes them probabilities of detection:
+ * the block the photon meets first absorbs it with probability
+ * 1 - exp(-mu l_first); the second with exp(-mu l_first)(1 - exp(-mu l_second))
+ * (the printed Eq. (1) reads as a transmission).  A ray through neither block
+ * goes to the nearer one (0.5 at the gap centre). */
+double orc_edge_prob(const orc_edge_geom* g, double theta, double x0) {
+  double l1, l2;
+  orc_edge_paths(g, theta, x0, &l1, &l2);
+  const double mu = (double)g->mu_per_mm;
+  double p1, p2;
+  if (theta >= 0.0) {   /* block 1 first */
+    p1 = -expm1(-mu * l1);
+    p2 = exp(-mu * l1) * -expm1(-mu * l2);
+  } else {              /* block 2 first */
+    p2 = -expm1(-mu * l2);
+    p1 = exp(-mu * l2) * -expm1(-mu * l1);
+  }
+  if (p1 + p2 > 0.0) return p1 / (p1 + p2);
+  return x0 < 0.0 ? 1.0 : (x0 > 0.0 ? 0.0 : 0.5);
+}
+
+void orc_edge_lut(const orc_edge_geom* g, float* out) {
+  const double w = (double)g->gap_mm;
+  for (int a = 0; a < g->n_angle; ++a) {
+    const double th = (-90.0 + ((double)a + 0.5) * 180.0 / (double)g->n_angle) * PI_D / 180.0;
+    for (int j = 0; j < g->n_pos; ++j) {
+      const double x0 = -0.5 * w + ((double)j + 0.5) * w / (double)g->n_pos;
+      out[a * g->n_pos + j] = (float)orc_edge_prob(g, th, x0);
+    }
+  }
+}
+
+static void single_index(const ctx_t* C, const photon_t* o, hit_t* hit, uint32_t* lut_index) {
+  const orc_scanner* sc = C->sc;
+  int c, rg;
+  if (C->gp) {
+    locate(sc, C->gp, (double)o->hx, (double)o->hy, (double)o->hz, hit);
+    c = hit->crystal;
+    rg = hit->ring;
+  } else {
+    /* crystal c covers azimuth [2 pi c / Nc, 2 pi (c + 1) / Nc) */
+    double phi = atan2((double)o->hy, (double)o->hx);
+    if (phi < 0.0) phi += TWO_PI_D;
+    double fc = floor(phi * (double)sc->n_crystals / TWO_PI_D);
+    c = (fc >= (double)sc->n_crystals) ? sc->n_crystals - 1 : (fc < 0.0 ? 0 : (int)fc);
+    /* rings tile [-L/2, L/2) */
+    rg = clamp_index((real)floor((double)((o->hz + C->half_len) / C->pitch)), sc->n_rings);
+    memset(hit, 0, sizeof(*hit));
+    hit->crystal = c;
+    hit->ring = rg;
+  }
   /* LUT axes: energy, transaxial angle, axial angle, crystal in module,
    * crystal in block.  The angles are those between the path and the hit
    * point's position vector, projected in the transaxial and axial planes,
@@ -639,9 +800,50 @@ static void single_index(const ctx_t* C, const photon_t* o, int* crystal, int* r
   double tt = (hx * (double)o->dy - hy * (double)o->dx) / rho;
   int it = bin_angle(atan2(tt, dr), dm[1]);
   int ia = bin_angle(atan2((double)o->dz, dr), dm[2]);
-  int ct = ((c % sc->crystals_per_module) * dm[3]) / sc->crystals_per_module;
-  int ca = ((rg % sc->rings_per_block) * dm[4]) / sc->rings_per_block;
+  int ct, ca;
+  if (C->gp) {
+    /* axes of size 1 ignore the coordinate; otherwise the virtual-index layout */
+    ct = dm[3] == 1 ? 0 : hit->ct;
+    ca = dm[4] == 1 ? 0 : hit->ca;
+  } else {
+    ct = ((c % sc->crystals_per_module) * dm[3]) / sc->crystals_per_module;
+    ca = ((rg % sc->rings_per_block) * dm[4]) / sc->rings_per_block;
+  }
   *lut_index = (uint32_t)((((iE * dm[1] + it) * dm[2] + ia) * dm[3] + ct) * dm[4] + ca);
+}
+
+/* Edge-crystal assignment of a gap photon of a coincidence ("Edge crystal
+ * assignment LUT"): with the edge-LUT policy a uniform draw from the
+ * history's stream below the tabulated probability picks the lower side's
+ * edge crystal, otherwise the upper side's; a photon in both kinds of gap
+ * draws for the transaxial gap first.  With the nearest policy the hit keeps
+ * its nearest edge crystal. */
+static void resolve_gap(const ctx_t* C, rng_t* r, const photon_t* o, hit_t* h, uint64_t* st) {
+  const orc_gaps* gp = C->gp;
+  if (!h->tgap && !h->agap) return;
+  double hx = (double)o->hx, hy = (double)o->hy;
+  double rho = sqrt(hx * hx + hy * hy);
+  double dr = (hx * (double)o->dx + hy * (double)o->dy) / rho;
+  double tt = (hx * (double)o->dy - hy * (double)o->dx) / rho;
+  const int na = gp->edge_n_angle, np = gp->edge_n_pos;
+  if (h->tgap) {
+    if (gp->policy == ORC_GAP_EDGE_LUT) {
+      int ia = bin_angle(atan2(tt, dr), na);
+      int ip = clamp_int(floor(h->tfrac * (double)np), np);
+      double u = (double)u01(r);
+      h->crystal = u < (double)C->edge_t[ia * np + ip] ? h->c_lo : h->c_hi;
+    }
+    st[ORC_ST_GAP_ASSIGNED] += 1;
+  }
+  if (h->agap) {
+    if (gp->policy == ORC_GAP_EDGE_LUT) {
+      int ia = bin_angle(atan2((double)o->dz, dr), na);
+      int ip = clamp_int(floor(h->afrac * (double)np), np);
+      double u = (double)u01(r);
+      h->ring = u < (double)C->edge_a[ia * np + ip] ? h->r_lo : h->r_hi;
+    }
+    st[ORC_ST_GAP_ASSIGNED] += 1;
+  }
 }
 
 /* Sinogram coordinates of the LOR between crystals c1 and c2: the view angle
@@ -695,16 +897,35 @@ static void history(const ctx_t* C, uint64_t seed, uint64_t h,
   real w = R(0), tau = R(0);
   int cA = -1, rA = -1, cB = -1, rB = -1;
   uint32_t lA = 0xffffffffu, lB = 0xffffffffu;
+  hit_t hA, hB;
   int inwinA = A.fate == ORC_FATE_DETECTED && A.Edet >= (real)C->ph->e_lo_kev && A.Edet <= (real)C->ph->e_hi_kev;
   int inwinB = B.fate == ORC_FATE_DETECTED && B.Edet >= (real)C->ph->e_lo_kev && B.Edet <= (real)C->ph->e_hi_kev;
-  if (inwinA) { single_index(C, &A, &cA, &rA, &lA); st[ORC_ST_IN_WINDOW] += 1; }
-  if (inwinB) { single_index(C, &B, &cB, &rB, &lB); st[ORC_ST_IN_WINDOW] += 1; }
+  if (inwinA) { single_index(C, &A, &hA, &lA); cA = hA.crystal; rA = hA.ring; st[ORC_ST_IN_WINDOW] += 1; }
+  if (inwinB) { single_index(C, &B, &hB, &lB); cB = hB.crystal; rB = hB.ring; st[ORC_ST_IN_WINDOW] += 1; }
+  /* the record keeps the nearest crystal and ring of each single */
+  const uint32_t crA = inwinA ? (uint32_t)cA | ((uint32_t)rA << 16) : 0xffffffffu;
+  const uint32_t crB = inwinB ? (uint32_t)cB | ((uint32_t)rB << 16) : 0xffffffffu;
   int scattered = (A.nC + A.nR + B.nC + B.nR) > 0;
+  int gap_discard = 0;
+  if (C->gp && A.fate == ORC_FATE_DETECTED && B.fate == ORC_FATE_DETECTED && inwinA && inwinB) {
+    if (C->gp->policy == ORC_GAP_DISCARD) {
+      gap_discard = hA.tgap || hA.agap || hB.tgap || hB.agap;
+    } else {
+      /* photon A's gaps draw first, then photon B's, before the TOF jitter */
+      resolve_gap(C, &r, &A, &hA, st);
+      resolve_gap(C, &r, &B, &hB, st);
+      cA = hA.crystal; rA = hA.ring;
+      cB = hB.crystal; rB = hB.ring;
+    }
+  }
   if (A.fate != ORC_FATE_DETECTED || B.fate != ORC_FATE_DETECTED) {
     outcome = ORC_OUT_UNDETECTED;
   } else if (!inwinA || !inwinB) {
     outcome = ORC_OUT_WINDOW;
     st[ORC_ST_REJ_WINDOW] += 1;
+  } else if (gap_discard) {
+    outcome = ORC_OUT_GAP;
+    st[ORC_ST_REJ_GAP] += 1;
   } else if (cA == cB) {
     outcome = ORC_OUT_SAME_CRYSTAL;
     st[ORC_ST_REJ_SAME] += 1;
@@ -759,15 +980,32 @@ static void history(const ctx_t* C, uint64_t seed, uint64_t h,
     rec->reserved = 0;
     fill_photon_rec(&rec->ph[0], &A);
     fill_photon_rec(&rec->ph[1], &B);
-    if (inwinA) { rec->ph[0].crystal_ring = (uint32_t)cA | ((uint32_t)rA << 16); rec->ph[0].lut_index = lA; }
-    if (inwinB) { rec->ph[1].crystal_ring = (uint32_t)cB | ((uint32_t)rB << 16); rec->ph[1].lut_index = lB; }
+    if (inwinA) { rec->ph[0].crystal_ring = crA; rec->ph[0].lut_index = lA; }
+    if (inwinB) { rec->ph[1].crystal_ring = crB; rec->ph[1].lut_index = lB; }
   }
 }
 
 static int setup(ctx_t* C, const orc_scanner* sc, const orc_sino* sn, const orc_physics* ph,
                  const orc_phantom* pd, const float* mu, const uint32_t* th, const uint32_t* al,
-                 const orc_lut* ld, const float* lut) {
+                 const orc_lut* ld, const float* lut,
+                 const orc_gaps* gaps, const float* edge_t, const float* edge_a) {
   if (!sc || !sn || !ph || !pd || !mu || !th || !al || !ld || !lut) return -1;
+  C->gp = NULL;
+  C->edge_t = edge_t;
+  C->edge_a = edge_a;
+  if (gaps && gaps->enabled) {
+    const int cm = sc->crystals_per_module, rb = sc->rings_per_block;
+    if (cm <= 0 || rb <= 0 || sc->n_crystals % cm || sc->n_rings % rb) return -1;
+    const int nm = sc->n_crystals / cm, nb = sc->n_rings / rb;
+    if (!(gaps->transaxial_gap_rad >= 0.0f) || !((double)gaps->transaxial_gap_rad < TWO_PI_D / (double)nm)) return -1;
+    if (!(gaps->axial_gap_mm >= 0.0f) || !((double)(nb - 1) * (double)gaps->axial_gap_mm < (double)sc->length_mm)) return -1;
+    if (ld->dims[3] != 1 && ld->dims[3] != cm + 2) return -1;
+    if (ld->dims[4] != 1 && ld->dims[4] != nb * (rb + 2)) return -1;
+    if (gaps->policy < ORC_GAP_DISCARD || gaps->policy > ORC_GAP_EDGE_LUT) return -1;
+    if (gaps->policy == ORC_GAP_EDGE_LUT &&
+        (!edge_t || !edge_a || gaps->edge_n_angle < 1 || gaps->edge_n_pos < 1)) return -1;
+    C->gp = gaps;
+  }
   if (sc->n_crystals <= 0 || sc->n_crystals % 2 || sc->n_rings <= 0) return -1;
   if (sn->n_view != sc->n_crystals / 2 || sn->n_plane != 2 * sc->n_rings - 1) return -1;
   if (sn->n_rad <= 0 || sn->n_rad % 2 == 0 || sn->n_rad > sc->n_crystals - 1 || sn->n_tof <= 0) return -1;
@@ -803,12 +1041,13 @@ int orc_simulate(const orc_scanner* sc, const orc_sino* sn, const orc_physics* p
                  const orc_phantom* pd, const float* mu511,
                  const uint32_t* alias_thresh, const uint32_t* alias_idx,
                  const orc_lut* ld, const float* lut,
+                 const orc_gaps* gaps, const float* edge_t, const float* edge_a,
                  uint64_t seed, uint64_t h0, uint64_t n, const uint64_t* h_list,
                  uint32_t* scatter_counts, double* scatter_weights,
                  uint32_t* true_counts, double* true_weights,
                  uint64_t* stats, orc_record* records) {
   ctx_t C;
-  if (setup(&C, sc, sn, ph, pd, mu511, alias_thresh, alias_idx, ld, lut)) return -1;
+  if (setup(&C, sc, sn, ph, pd, mu511, alias_thresh, alias_idx, ld, lut, gaps, edge_t, edge_a)) return -1;
   uint64_t local[ORC_ST_COUNT];
   memset(local, 0, sizeof(local));
   for (uint64_t i = 0; i < n; ++i) {
@@ -865,4 +1104,17 @@ void orc_sample_rayleigh(uint64_t seed, double e_kev, float beta, uint64_t n, do
     sample_rayleigh(&r, alpha, (real)beta, &c);
     cos_theta[i] = (double)c;
   }
+}
+
+int orc_locate(const orc_scanner* sc, const orc_gaps* gaps, float hx, float hy, float hz,
+               int32_t out[10], double frac[2]) {
+  if (!sc || !gaps || sc->crystals_per_module <= 0 || sc->rings_per_block <= 0 ||
+      sc->n_crystals % sc->crystals_per_module || sc->n_rings % sc->rings_per_block) return -1;
+  hit_t h;
+  locate(sc, gaps, (double)hx, (double)hy, (double)hz, &h);
+  out[0] = h.crystal; out[1] = h.ring; out[2] = h.ct; out[3] = h.ca; out[4] = h.tgap; out[5] = h.agap;
+  out[6] = h.c_lo; out[7] = h.c_hi; out[8] = h.r_lo; out[9] = h.r_hi;
+  frac[0] = h.tfrac;
+  frac[1] = h.afrac;
+  return 0;
 }

@@ -24,6 +24,27 @@ class Case:
     lut: np.ndarray          # float32 values as the oracle sees them
     lut_store: np.ndarray    # values as loaded into the library
     lut_dtype: int = 0
+    gaps: dict = None        # gap description (None: plain cylinder)
+    edge_t: np.ndarray = None
+    edge_a: np.ndarray = None
+
+
+def with_gaps(case: Case, gaps: dict, policy: str, edge=None, lut_seed=7):
+    """The case with the gap model on: the LUT replaced by one with the
+    virtual gap indices (values from lut_seed), and for the edge-LUT policy
+    the edge LUTs (the oracle's unless `edge` = (transaxial, axial) gives
+    them)."""
+    dims = W.gap_lut_dims(case.scanner, case.lut_desc.dims)
+    ld, vals = W.make_lut(dims, lut_seed, e_min=case.lut_desc.e_min_kev, e_max=case.lut_desc.e_max_kev)
+    g = W.gap_desc(gaps, policy)
+    et = ea = None
+    if policy == "edge_lut":
+        if edge is None:
+            gt, ga = W.edge_geometries(case.scanner, gaps)
+            edge = (O.edge_lut(gt), O.edge_lut(ga))
+        et, ea = (np.ascontiguousarray(e, np.float32) for e in edge)
+    return Case(case.scanner, case.sino, case.physics, case.pdesc, case.mu, case.act, ld, vals, vals, 0,
+                g, et, ea)
 
 
 def case_from(name, tof_sigma=None, lut_dtype=0, physics=None, phantom=None, lut=None):
@@ -78,7 +99,8 @@ def run_oracle(case: Case, n, seed, h_offset=0, h_list=None, records=True, trues
                sinograms=True):
     return O.simulate(case.scanner, case.sino, case.physics, case.pdesc, case.mu, activity=case.act,
                       lut_desc=case.lut_desc, lut=case.lut, seed=seed, h0=h_offset, n=n, h_list=h_list,
-                      records=records, trues=trues, variant=variant, sinograms=sinograms)
+                      records=records, trues=trues, variant=variant, sinograms=sinograms,
+                      gaps=case.gaps, edge_t=case.edge_t, edge_a=case.edge_a)
 
 
 def record_words(rec):

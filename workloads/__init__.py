@@ -356,6 +356,65 @@ def lut_mode(w: "Workload", mode: str):
     return dict(PHYSICS_LUT_PAPER), ld, vals
 
 
+# --------------------------------------------------------------------------
+# gaps between modules and blocks
+# --------------------------------------------------------------------------
+# Gap geometry (builder's choice; the paper gives the Signa's gaps only as
+# "the real scanner's"): on the Signa-like scanner a module spans
+# 2 pi 312 / 28 = 70.0 mm of arc, 16 crystals of about 4 mm leave a 6 mm
+# transaxial gap; 45 rings of about 5.3 mm in 5 blocks over 250.4 mm leave
+# 3 mm axial gaps.  About one in eight singles then lands in a gap, and about
+# a quarter of coincidences contain one (the paper: about 20 % on the Signa,
+# Discussion).  The tiny scanner's gaps are scaled to give a similar share.
+SIGNA_GAPS = dict(transaxial_gap_rad=6.0 / 312.0, axial_gap_mm=3.0)
+TINY_GAPS = dict(transaxial_gap_rad=0.06, axial_gap_mm=6.0)
+
+# Crystal blocks for the edge-crystal LUT: 25 mm deep LYSO (Signa), the
+# detection surface 8 mm below the front face (the mean interaction depth at
+# normal incidence), LYSO attenuation 0.087 / mm at 511 keV; 5 degree angle
+# bins as the 5D LUT, 16 position bins across a gap.
+EDGE_BLOCKS = dict(depth_mm=25.0, doi_mm=8.0, mu_per_mm=0.087)
+EDGE_N_ANGLE = 36
+EDGE_N_POS = 16
+
+# Gap policy of each LUT mode (Methods, "Photon detection probability LUT"):
+# no crystal information (or no LUT): discard; 3D with crystals: nearest edge
+# crystal; 5D: the edge-crystal LUT.
+GAP_POLICY_OF_MODE = {"lut5d": "edge_lut", "lut5d_paper": "edge_lut", "lut3d_crystals": "nearest",
+                      "lut3d_angles": "discard", "lut1d": "discard", "nolut": "discard"}
+
+
+def gap_desc(gaps: dict, policy: str) -> dict:
+    """Gap description as the oracle and the library take it."""
+    d = dict(gaps, policy=policy)
+    if policy == "edge_lut":
+        d.update(edge_n_angle=EDGE_N_ANGLE, edge_n_pos=EDGE_N_POS)
+    return d
+
+
+def edge_geometries(scanner: Scanner, gaps: dict):
+    """(transaxial, axial) edge-LUT geometries: the transaxial gap's width is
+    its angle times the detection radius (the angle between the two modules'
+    faces is neglected, as in the paper)."""
+    t = dict(EDGE_BLOCKS, gap_mm=float(np.float32(scanner.radius_mm * gaps["transaxial_gap_rad"])),
+             n_angle=EDGE_N_ANGLE, n_pos=EDGE_N_POS)
+    a = dict(EDGE_BLOCKS, gap_mm=float(gaps["axial_gap_mm"]), n_angle=EDGE_N_ANGLE, n_pos=EDGE_N_POS)
+    return t, a
+
+
+def gap_lut_dims(scanner: Scanner, dims) -> tuple:
+    """LUT dims with the virtual gap indices on the crystal axes (an axis of
+    size 1 stays 1): crystals_per_module + 2 transaxial, n_blocks
+    (rings_per_block + 2) axial."""
+    nb = scanner.n_rings // scanner.rings_per_block
+    d = list(dims)
+    if d[3] != 1:
+        d[3] = scanner.crystals_per_module + 2
+    if d[4] != 1:
+        d[4] = nb * (scanner.rings_per_block + 2)
+    return tuple(d)
+
+
 def to_bf16_bits(x: np.ndarray) -> np.ndarray:
     """Round float32 values to bfloat16 (round to nearest even); returns uint16 bits."""
     b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
