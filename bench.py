@@ -100,13 +100,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut_f32, n):
-    """The oracle as it stands, single thread, on the first n histories."""
+def cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut_f32, n, gaps=None):
+    """The oracle as it stands, single thread, on the first n histories
+    (with the gap model, its own edge LUTs)."""
     import oracle as O
     alias = O.build_alias(act)
+    et = ea = None
+    if gaps is not None and gaps["policy"] == "edge_lut":
+        gt, ga = W.edge_geometries(w.scanner, W.SIGNA_GAPS)
+        et, ea = O.edge_lut(gt), O.edge_lut(ga)
     t0 = time.perf_counter()
     r = O.simulate(w.scanner, w.sino, physics, pdesc, mu, alias=alias,
-                   lut_desc=lut_desc, lut=lut_f32, seed=w.seed, n=n, trues=False)
+                   lut_desc=lut_desc, lut=lut_f32, seed=w.seed, n=n, trues=False,
+                   gaps=gaps, edge_t=et, edge_a=ea)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "histories/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name} workload, histories 0..{n} of seed {w.seed}, one thread, {dt:.1f} s",
@@ -279,6 +285,9 @@ def main():
     ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--lut-mode", default="lut5d", choices=list(W.LUT_MODES),
                     help="LUT variant and energy configuration (lut5d: the workload's own)")
+    ap.add_argument("--gaps", default="none", choices=["none", "auto", "discard", "nearest", "edge_lut"],
+                    help="gaps between modules and blocks (Signa-like widths) with this gap policy; "
+                         "auto: the LUT mode's own policy")
     ap.add_argument("--cpu-histories", type=int, default=40_000_000)
     ap.add_argument("--copy-bytes", type=float, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates HBM counters)")
@@ -309,6 +318,13 @@ def main():
     w = W.WORKLOADS[args.workload]
     pdesc, mu, act = W.make_phantom(w)
     physics, lut_desc, lut = W.lut_mode(w, args.lut_mode)
+    gaps = None
+    if args.gaps != "none":
+        policy = W.GAP_POLICY_OF_MODE[args.lut_mode] if args.gaps == "auto" else args.gaps
+        gaps = W.gap_desc(W.SIGNA_GAPS, policy)
+        dims = W.gap_lut_dims(w.scanner, lut_desc.dims)
+        if tuple(dims) != tuple(lut_desc.dims):
+            lut_desc, lut = W.make_lut(dims, w.lut_seed, e_min=lut_desc.e_min_kev, e_max=lut_desc.e_max_kev)
     lut_dtype = {"f32": sse.F32, "f16": sse.F16, "bf16": sse.BF16}[args.lut]
     lut_store = {"f32": lut, "f16": lut.astype(np.float16).view(np.uint16), "bf16": W.to_bf16_bits(lut)}[args.lut]
     n = int(args.histories) if args.histories else w.n_histories
@@ -317,6 +333,9 @@ def main():
     ctx = sse.Context(w.scanner, w.sino, physics)
     pid = ctx.load_phantom(pdesc, mu, act)
     ctx.load_lut(lut_desc, lut_store, dtype=lut_dtype)
+    if gaps is not None:
+        gt, ga = W.edge_geometries(w.scanner, W.SIGNA_GAPS)
+        ctx.set_gaps(gaps, sse.build_edge_lut(gt), sse.build_edge_lut(ga))
     ctx.load_sensitivity(sens, has_tof_axis=True)
     del sens
     # per-history work units for the cost model, from an instrumented run on
@@ -384,6 +403,10 @@ def main():
                                f"{'x'.join(map(str, w.sino.shape[::-1]))} TOF sinogram (rad x view x plane x tof), "
                                f"{'x'.join(map(str, lut_desc.dims))} {args.lut} LUT",
                    "histories_per_step": n, "lut_dtype": args.lut, "lut_mode": args.lut_mode,
+                   "gaps": (None if gaps is None else
+                            dict(gaps, fraction_rejected=stats["rej_gap"] / max(1, stats["scatter"] + stats["true"]
+                                                                                 + stats["rej_gap"]),
+                                 assigned_per_history=stats["gap_assigned"] / stats["histories"])),
                    "energy_window_kev": [physics["e_lo_kev"], physics["e_hi_kev"]],
                    "energy_fwhm": physics["e_fwhm_frac"], "transport": "f32",
                    "accumulation": "f64"},
@@ -393,14 +416,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
-                                 and args.lut == "f32" and args.lut_mode == "lut5d" else None),
+                                 and args.lut == "f32" and args.lut_mode == "lut5d" and gaps is None else None),
                      "kernel": "one simulate call: transport + coincidence launches",
                      "span_ms": float(np.mean(kernel_ms)),
                      "ops_per_history": ops_per_hist},
     }
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_histories} histories")
-        result["cpu_baseline"] = cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut, args.cpu_histories)
+        result["cpu_baseline"] = cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut, args.cpu_histories, gaps)
     print(json.dumps(result), flush=True)
 
 

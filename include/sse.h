@@ -109,10 +109,13 @@ typedef struct {
 /* 5D detection-probability LUT, row-major [E][theta_t][theta_a][ct][ca]
  * (Methods, "Photon detection probability LUT"): energy bins of
  * (e_max - e_min) / dims[0] keV from e_min (clamped), transaxial and axial
- * incidence angle bins of 180/dims deg over [-90, 90] (Fig. 5 caption),
- * in-module crystal ct = (c mod crystals_per_module) * dims[3] /
- * crystals_per_module, in-block ring ca = (r mod rings_per_block) * dims[4] /
- * rings_per_block.  Values in [0, 1]. */
+ * incidence angle bins of 180/dims deg over [-90, 90] (Fig. 5 caption).
+ * Plain cylinder: in-module crystal ct = (c mod crystals_per_module) *
+ * dims[3] / crystals_per_module, in-block ring ca = (r mod rings_per_block) *
+ * dims[4] / rings_per_block.  With gaps (sse_set_gaps) the crystal axes
+ * carry the virtual gap indices instead: dims[3] = crystals_per_module + 2,
+ * dims[4] = n_blocks (rings_per_block + 2), or 1 to ignore the axis.  Values
+ * in [0, 1]. */
 typedef struct {
   int32_t dims[5];
   float e_min_kev, e_max_kev;
@@ -123,20 +126,26 @@ enum {
   SSE_ST_HISTORIES = 0, SSE_ST_STEPS, SSE_ST_REAL, SSE_ST_COMPTON, SSE_ST_RAYLEIGH,
   SSE_ST_ABSORBED, SSE_ST_KILLED, SSE_ST_CAPPED, SSE_ST_ESCAPED, SSE_ST_DETECTED,
   SSE_ST_IN_WINDOW, SSE_ST_SCATTER, SSE_ST_TRUE, SSE_ST_REJ_WINDOW, SSE_ST_REJ_SAME,
-  SSE_ST_REJ_RING, SSE_ST_REJ_RADIAL, SSE_ST_REJ_TOF, SSE_ST_RNG_BLOCKS, SSE_ST_COUNT
+  SSE_ST_REJ_RING, SSE_ST_REJ_RADIAL, SSE_ST_REJ_TOF, SSE_ST_RNG_BLOCKS,
+  SSE_ST_REJ_GAP,       /* coincidences discarded for a photon in a gap */
+  SSE_ST_GAP_ASSIGNED,  /* gap hits of evaluated coincidences given an edge crystal or ring */
+  SSE_ST_COUNT
 };
 
 /* Per-history record (128 bytes), for parity checks and list-mode style
  * inspection.  Word layout:
  *   0 outcome: 0 scatter, 1 true, 2 a photon undetected, 3 outside the energy
  *     window, 4 same crystal, 5 ring difference, 6 outside the radial FOV,
- *     7 outside the TOF range; bit 8 set if either photon scattered
+ *     7 outside the TOF range, 8 a photon in a gap (discard policy); bit 8
+ *     set if either photon scattered
  *   1,2 flat sinogram bin (low, high word; all ones if none)
  *   3 emission voxel   4 weight p_A p_B (float)   5 TOF offset tau (float, mm)
  *   6 Woodcock tentative steps of both photons    7 zero
  *   8..19 photon A, 20..31 photon B: hit x, y, z, direction x, y, z, energy,
- *     blurred energy, path length (floats), crystal | ring << 16, flat LUT
- *     index (all ones if the photon is not detected in the window),
+ *     blurred energy, path length (floats), crystal | ring << 16 (for a hit
+ *     in a gap the nearest edge crystal and ring, before any edge-LUT draw),
+ *     flat LUT index (both all ones if the photon is not detected in the
+ *     window),
  *     n_compton | n_rayleigh << 8 | fate << 16 (fate 0 detected, 1 absorbed,
  *     2 dropped below e_kill, 3 interaction/step cap, 4 missed the cylinder). */
 typedef struct { uint32_t w[32]; } sse_history_record;
@@ -200,6 +209,81 @@ sse_status sse_unload_phantom(sse_ctx* ctx, sse_phantom_id id);
  * Errors: SSE_EINVAL (bad dims, range or values), SSE_ENOMEM. */
 sse_status sse_load_lut(sse_ctx* ctx, const sse_lut_desc* desc, const void* values, int dtype,
                         int mem, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Gaps between modules and blocks                                           */
+/* ------------------------------------------------------------------------ */
+/* The paper's scanner has gaps between its transaxial modules (given by the
+ * angle they subtend) and its axial blocks (given by their width); a photon
+ * crossing the detection cylinder in a gap is discarded with its
+ * coincidence, assigned to the nearest edge crystal, or assigned at random
+ * to one of the two edge crystals by an edge-crystal LUT, depending on the
+ * LUT in use (Methods, "Scatter simulator description", "Photon detection
+ * probability LUT", "Edge crystal assignment LUT").
+ *
+ * Geometry.  Module m of n_modules = n_crystals / crystals_per_module covers
+ * azimuth [m D, (m + 1) D), D = 2 pi / n_modules, with half a gap at either
+ * end and its crystals sharing the rest equally.  Block b of n_blocks =
+ * n_rings / rings_per_block holds rings of pitch (L - (n_blocks - 1) w) /
+ * n_rings, blocks separated by gaps of width w, none at the scanner's ends.
+ * A hit in the half of a gap next to a module (block) takes that module's
+ * (block's) virtual LUT index and, as nearest edge crystal, its edge crystal.
+ * All of this is evaluated in binary64.
+ *
+ * Edge LUTs.  For the edge-LUT policy, one table for the transaxial gaps and
+ * one for the axial gaps, row-major [angle][position], edge_n_angle bins of
+ * the incidence angle over [-90, 90] degrees (the LUT's transaxial resp.
+ * axial angle, positive towards the upper side: larger azimuth, larger z)
+ * and edge_n_pos bins of the position across the gap (from the lower side's
+ * edge); each entry is the probability that the photon goes to the lower
+ * side's edge crystal (sse_build_edge_lut computes them).  A uniform from
+ * the history's stream (after photon B's transport: photon A's transaxial,
+ * then axial gap, then photon B's; before the TOF jitter) below the entry
+ * picks the lower side.  The LUT probability of a gap photon is the one of
+ * its virtual index, whichever crystal it goes to. */
+typedef enum { SSE_GAP_DISCARD = 0, SSE_GAP_NEAREST = 1, SSE_GAP_EDGE_LUT = 2 } sse_gap_policy;
+
+typedef struct {
+  float transaxial_gap_rad;    /* 0 <= angle < 2 pi / n_modules */
+  float axial_gap_mm;          /* >= 0, (n_blocks - 1) * width < length */
+  int32_t policy;              /* sse_gap_policy */
+  int32_t edge_n_angle;        /* edge LUT bins (EDGE_LUT policy; >= 1) */
+  int32_t edge_n_pos;
+  int32_t reserved;            /* 0 */
+} sse_gap_desc;
+
+/* Switch the gap model on (desc != NULL) or off (desc == NULL, the plain
+ * cylinder).  n_crystals must be a multiple of crystals_per_module and
+ * n_rings of rings_per_block; a loaded LUT must have the gap layout on its
+ * crystal axes (see sse_lut_desc).  edge_transaxial / edge_axial (host or
+ * device per `mem`, edge_n_angle * edge_n_pos floats in [0, 1] each) are
+ * read for the EDGE_LUT policy only and copied.  Errors: SSE_EINVAL. */
+sse_status sse_set_gaps(sse_ctx* ctx, const sse_gap_desc* desc, const float* edge_transaxial,
+                        const float* edge_axial, int mem, void* stream);
+
+/* Geometry of one kind of gap for the edge-crystal LUT: two crystal blocks
+ * depth_mm deep either side of a gap gap_mm wide (for transaxial gaps, the
+ * gap angle times the detection radius: the angle between the two modules
+ * is neglected, as in the paper), the detection cylinder doi_mm below their
+ * front faces, crystal attenuation mu_per_mm (LYSO at 511 keV: about
+ * 0.087 / mm). */
+typedef struct {
+  float gap_mm, depth_mm, doi_mm, mu_per_mm;
+  int32_t n_angle, n_pos;
+} sse_edge_geom;
+
+/* Host helper: the edge-crystal LUT of Eq. (1)-(3) ("Edge crystal assignment
+ * LUT").  For a ray through the detection surface at position x across the
+ * gap and incidence angle theta (the bin centres), l1 and l2 are its path
+ * lengths in the two blocks (taken as unbounded away from the gap); the
+ * block the ray meets first absorbs it with p_first = 1 - exp(-mu l_first),
+ * the other with p_second = exp(-mu l_first) (1 - exp(-mu l_second)) (the
+ * paper prints the first factor as a transmission; this is the reading that
+ * makes both probabilities of detection); out = p_lower / (p_lower +
+ * p_upper), or the nearer side (0.5 at the centre) for a ray through
+ * neither block.  out: host, n_angle * n_pos floats, [angle][position].
+ * Errors: SSE_EINVAL. */
+sse_status sse_build_edge_lut(const sse_edge_geom* geom, float* out);
 
 /* Load the scatter-sensitivity sinogram (float, >= 0), with the full
  * sinogram shape (has_tof_axis = 1) or without the TOF axis (shared by all

@@ -21,9 +21,11 @@ F32, F16, BF16 = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 STAT_NAMES = ["histories", "steps", "real", "compton", "rayleigh", "absorbed", "killed", "capped",
               "escaped", "detected", "in_window", "scatter", "true", "rej_window", "rej_same",
-              "rej_ring", "rej_radial", "rej_tof", "rng_blocks"]
+              "rej_ring", "rej_radial", "rej_tof", "rng_blocks", "rej_gap", "gap_assigned"]
 STAT_COUNT = len(STAT_NAMES)
 RECORD_WORDS = 32
+GAP_DISCARD, GAP_NEAREST, GAP_EDGE_LUT = 0, 1, 2
+GAP_POLICIES = {"discard": GAP_DISCARD, "nearest": GAP_NEAREST, "edge_lut": GAP_EDGE_LUT}
 
 
 class SseError(RuntimeError):
@@ -57,6 +59,16 @@ class PhantomDesc(C.Structure):
 
 class LutDesc(C.Structure):
     _fields_ = [("dims", C.c_int32 * 5), ("e_min_kev", C.c_float), ("e_max_kev", C.c_float)]
+
+
+class GapDesc(C.Structure):
+    _fields_ = [("transaxial_gap_rad", C.c_float), ("axial_gap_mm", C.c_float), ("policy", C.c_int32),
+                ("edge_n_angle", C.c_int32), ("edge_n_pos", C.c_int32), ("reserved", C.c_int32)]
+
+
+class EdgeGeom(C.Structure):
+    _fields_ = [("gap_mm", C.c_float), ("depth_mm", C.c_float), ("doi_mm", C.c_float),
+                ("mu_per_mm", C.c_float), ("n_angle", C.c_int32), ("n_pos", C.c_int32)]
 
 
 class Outputs(C.Structure):
@@ -101,6 +113,8 @@ SIGNATURES = {
     "sse_unload_phantom": ([_P, C.c_uint32], C.c_int),
     "sse_load_lut": ([_P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
     "sse_load_sensitivity": ([_P, _P, C.c_int, C.c_int, _P], C.c_int),
+    "sse_set_gaps": ([_P, _P, _P, _P, C.c_int, _P], C.c_int),
+    "sse_build_edge_lut": ([_P, _P], C.c_int),
     "sse_simulate": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
     "sse_emission_scale": ([_P, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
@@ -185,6 +199,16 @@ def build_alias_table(activity: np.ndarray):
     return th, al
 
 
+def build_edge_lut(geom) -> np.ndarray:
+    """The library's edge-crystal LUT ([angle][position] float32) for a
+    mapping with gap_mm, depth_mm, doi_mm, mu_per_mm, n_angle, n_pos."""
+    g = EdgeGeom(geom["gap_mm"], geom["depth_mm"], geom["doi_mm"], geom["mu_per_mm"], int(geom["n_angle"]),
+                 int(geom["n_pos"]))
+    out = np.zeros(max(g.n_angle, 0) * max(g.n_pos, 0), np.float32)
+    _check(lib().sse_build_edge_lut(C.byref(g), out.ctypes.data))
+    return out.reshape(g.n_angle, g.n_pos)
+
+
 class Context:
     """A scatter-estimation context on one GPU (see sse_create)."""
 
@@ -245,6 +269,21 @@ class Context:
         else:
             _check(lib().sse_load_lut(self._h, C.byref(d), _ptr(values.contiguous()), dtype, MEM_DEVICE,
                                       _stream_ptr(stream)))
+
+    def set_gaps(self, gaps=None, edge_t=None, edge_a=None):
+        """Gap model on (a mapping with transaxial_gap_rad, axial_gap_mm,
+        policy as name or number, edge_n_angle / edge_n_pos for the edge-LUT
+        policy; edge LUTs as float32 numpy arrays) or off (gaps=None)."""
+        if gaps is None:
+            _check(lib().sse_set_gaps(self._h, None, None, None, MEM_HOST, None))
+            return
+        pol = gaps["policy"]
+        pol = GAP_POLICIES[pol] if isinstance(pol, str) else int(pol)
+        d = GapDesc(gaps["transaxial_gap_rad"], gaps["axial_gap_mm"], pol, int(gaps.get("edge_n_angle", 0)),
+                    int(gaps.get("edge_n_pos", 0)), 0)
+        et = None if edge_t is None else np.ascontiguousarray(edge_t, np.float32)
+        ea = None if edge_a is None else np.ascontiguousarray(edge_a, np.float32)
+        _check(lib().sse_set_gaps(self._h, C.byref(d), _ptr(et), _ptr(ea), MEM_HOST, None))
 
     def load_sensitivity(self, sens, has_tof_axis: bool = True, stream=None):
         mem, s_ = self._as_input(sens)

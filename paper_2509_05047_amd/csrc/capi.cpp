@@ -3,6 +3,7 @@
 // kernels.  Declarations and documentation: include/sse.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,8 @@
 #include "post.h"
 
 namespace sse_detail {
+
+constexpr double kTwoPiD = 6.283185307179586;
 
 thread_local std::string g_error;
 
@@ -30,6 +33,13 @@ sse_status hip_fail(hipError_t e, const char* what) {
 
 void release(void* p) {
   if (p) (void)hipFree(p);
+}
+
+// With gaps, the LUT's crystal axes carry the virtual gap indices (or are
+// ignored with size 1).
+bool lut_fits_gaps(const sse_scanner_desc& sc, const sse_lut_desc& d) {
+  const int cm = sc.crystals_per_module, rb = sc.rings_per_block, nb = sc.n_rings / rb;
+  return (d.dims[3] == 1 || d.dims[3] == cm + 2) && (d.dims[4] == 1 || d.dims[4] == nb * (rb + 2));
 }
 
 Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
@@ -80,6 +90,25 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
   p.d0 = c->lut.dims[0]; p.d1 = c->lut.dims[1]; p.d2 = c->lut.dims[2]; p.d3 = c->lut.dims[3]; p.d4 = c->lut.dims[4];
   p.e_min = c->lut.e_min_kev;
   p.e_scale = static_cast<float>(c->lut.dims[0]) / (c->lut.e_max_kev - c->lut.e_min_kev);
+  p.gap_on = c->gaps_on;
+  if (c->gaps_on) {
+    const int rb = c->sc.rings_per_block;
+    p.n_mod = c->sc.n_crystals / c->sc.crystals_per_module;
+    p.n_blk = c->sc.n_rings / rb;
+    p.gap_policy = c->gaps.policy;
+    p.gap_t = static_cast<double>(c->gaps.transaxial_gap_rad);
+    p.mod_d = kTwoPiD / static_cast<double>(p.n_mod);
+    const double L = static_cast<double>(c->sc.length_mm), w = static_cast<double>(c->gaps.axial_gap_mm);
+    p.half_len_d = 0.5 * L;
+    p.gap_a = w;
+    p.pitch_a = (L - static_cast<double>(p.n_blk - 1) * w) / static_cast<double>(c->sc.n_rings);
+    p.block_span = static_cast<double>(rb) * p.pitch_a;
+    p.block_period = p.block_span + w;
+    p.edge_t = c->d_edge[0];
+    p.edge_a = c->d_edge[1];
+    p.edge_na = c->gaps.edge_n_angle;
+    p.edge_np = c->gaps.edge_n_pos;
+  }
   p.seed = seed;
   p.h0 = h0;
   p.rec_h0 = h0;
@@ -93,6 +122,34 @@ using namespace sse_detail;
 namespace {
 
 bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+// Path lengths of a ray in the lower (x <= -w/2) and upper (x >= w/2) block
+// of the slab 0 <= depth <= D: the ray crosses depth doi at lateral position
+// x with angle theta to the depth axis, so its lateral coordinate runs
+// linearly from xf at the front face to xb at the back face over a path of
+// D / cos(theta).
+void edge_ray_paths(const sse_edge_geom& g, double theta, double x, double& lo, double& hi, bool& lower_first) {
+  const double D = static_cast<double>(g.depth_mm), hw = 0.5 * static_cast<double>(g.gap_mm);
+  const double doi = static_cast<double>(g.doi_mm);
+  const double t = std::tan(theta);
+  const double xf = x - doi * t, xb = x + (D - doi) * t;
+  const double len = D / std::cos(theta);
+  lower_first = xb >= xf;
+  if (xf == xb) {
+    lo = xf <= -hw ? len : 0.0;
+    hi = xf >= hw ? len : 0.0;
+    return;
+  }
+  // share of the path before the lateral coordinate passes xc
+  auto share = [&](double xc) { return std::min(1.0, std::max(0.0, (xc - xf) / (xb - xf))); };
+  if (xb > xf) {
+    lo = len * share(-hw);
+    hi = len * (1.0 - share(hw));
+  } else {
+    lo = len * (1.0 - share(-hw));
+    hi = len * share(hw);
+  }
+}
 
 sse_status check_descs(const sse_scanner_desc* s, const sse_sino_desc* n, const sse_physics_desc* p) {
   if (!s || !n || !p) return fail(SSE_EINVAL, "null descriptor");
@@ -361,6 +418,7 @@ sse_status sse_destroy(sse_ctx* c) {
   }
   if (c->d_lut) release(c->d_lut);
   if (c->d_sens) release(c->d_sens);
+  for (float* e : c->d_edge) release(e);
   for (auto* s : c->d_scratch)
     if (s) release(s);
   if (c->d_pairs) release(c->d_pairs);
@@ -468,6 +526,9 @@ sse_status sse_load_lut(sse_ctx* c, const sse_lut_desc* d, const void* values, i
     if (d->dims[i] <= 0) return fail(SSE_EINVAL, "LUT dimensions must be positive");
     n *= static_cast<uint64_t>(d->dims[i]);
   }
+  if (c->gaps_on && !lut_fits_gaps(c->sc, *d))
+    return fail(SSE_EINVAL, "with gaps the LUT's crystal axes must be crystals_per_module + 2 and "
+                            "n_blocks (rings_per_block + 2) long, or 1");
   if (n >= 0xffffffffull) return fail(SSE_EINVAL, "LUT too large");
   if (!(d->e_max_kev > d->e_min_kev) || !std::isfinite(d->e_min_kev) || !std::isfinite(d->e_max_kev))
     return fail(SSE_EINVAL, "LUT energy range must be increasing");
@@ -546,12 +607,104 @@ sse_status sse_load_sensitivity(sse_ctx* c, const float* sens, int has_tof_axis,
   return SSE_OK;
 }
 
+sse_status sse_set_gaps(sse_ctx* c, const sse_gap_desc* d, const float* edge_t, const float* edge_a, int mem,
+                        void* stream) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (!d) {
+    HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
+    for (float*& e : c->d_edge) {
+      release(e);
+      e = nullptr;
+    }
+    c->gaps_on = 0;
+    c->gaps = sse_gap_desc{};
+    return SSE_OK;
+  }
+  const int cm = c->sc.crystals_per_module, rb = c->sc.rings_per_block;
+  if (c->sc.n_crystals % cm || c->sc.n_rings % rb)
+    return fail(SSE_EINVAL, "gaps need whole modules and blocks: n_crystals a multiple of crystals_per_module, "
+                            "n_rings of rings_per_block");
+  const int nm = c->sc.n_crystals / cm, nb = c->sc.n_rings / rb;
+  if (!(d->transaxial_gap_rad >= 0.0f) || !(static_cast<double>(d->transaxial_gap_rad) < kTwoPiD / nm))
+    return fail(SSE_EINVAL, "transaxial gap angle must lie in [0, 2 pi / n_modules)");
+  if (!(d->axial_gap_mm >= 0.0f) ||
+      !(static_cast<double>(nb - 1) * static_cast<double>(d->axial_gap_mm) < static_cast<double>(c->sc.length_mm)))
+    return fail(SSE_EINVAL, "axial gaps must be >= 0 and leave room for the rings");
+  if (d->policy != SSE_GAP_DISCARD && d->policy != SSE_GAP_NEAREST && d->policy != SSE_GAP_EDGE_LUT)
+    return fail(SSE_EINVAL, "unknown gap policy");
+  if (c->d_lut && !lut_fits_gaps(c->sc, c->lut))
+    return fail(SSE_EINVAL, "the loaded LUT lacks the gap layout on its crystal axes");
+  float* fresh[2] = {nullptr, nullptr};
+  if (d->policy == SSE_GAP_EDGE_LUT) {
+    if (d->edge_n_angle < 1 || d->edge_n_pos < 1 || d->edge_n_angle > 65536 || d->edge_n_pos > 65536)
+      return fail(SSE_EINVAL, "edge LUT sizes must lie in [1, 65536]");
+    if (!edge_t || !edge_a) return fail(SSE_EINVAL, "the edge-LUT policy needs both edge LUTs");
+    const uint64_t n = static_cast<uint64_t>(d->edge_n_angle) * static_cast<uint64_t>(d->edge_n_pos);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const float* src[2] = {edge_t, edge_a};
+    for (int k = 0; k < 2; ++k) {
+      std::vector<float> h;
+      sse_status st = fetch_floats(src[k], n, mem, s, h);
+      for (uint64_t i = 0; st == SSE_OK && i < n; ++i)
+        if (!(h[i] >= 0.0f && h[i] <= 1.0f)) st = fail(SSE_EINVAL, "edge LUT values must lie in [0, 1]");
+      hipError_t e = hipSuccess;
+      if (st == SSE_OK) e = hipMalloc(&fresh[k], n * sizeof(float));
+      if (st == SSE_OK && e == hipSuccess) e = hipMemcpy(fresh[k], h.data(), n * sizeof(float), hipMemcpyHostToDevice);
+      if (st == SSE_OK && e != hipSuccess) st = hip_fail(e, "upload edge LUT");
+      if (st != SSE_OK) {
+        release(fresh[0]);
+        release(fresh[1]);
+        return st;
+      }
+    }
+  }
+  HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
+  for (int k = 0; k < 2; ++k) {
+    release(c->d_edge[k]);
+    c->d_edge[k] = fresh[k];
+  }
+  c->gaps = *d;
+  c->gaps_on = 1;
+  return SSE_OK;
+}
+
+sse_status sse_build_edge_lut(const sse_edge_geom* g, float* out) {
+  if (!g || !out) return fail(SSE_EINVAL, "null argument");
+  if (g->n_angle < 1 || g->n_pos < 1 || g->n_angle > 65536 || g->n_pos > 65536)
+    return fail(SSE_EINVAL, "bin counts must lie in [1, 65536]");
+  if (!finite_pos(g->gap_mm) || !finite_pos(g->depth_mm) || !(g->doi_mm >= 0.0f) || !(g->doi_mm <= g->depth_mm) ||
+      !finite_pos(g->mu_per_mm))
+    return fail(SSE_EINVAL, "gap, depth and attenuation must be positive, 0 <= doi <= depth");
+  const double mu = static_cast<double>(g->mu_per_mm), w = static_cast<double>(g->gap_mm);
+  for (int a = 0; a < g->n_angle; ++a) {
+    const double deg = -90.0 + (static_cast<double>(a) + 0.5) * 180.0 / static_cast<double>(g->n_angle);
+    const double theta = deg * (kTwoPiD / 360.0);
+    for (int j = 0; j < g->n_pos; ++j) {
+      const double x = -0.5 * w + (static_cast<double>(j) + 0.5) * w / static_cast<double>(g->n_pos);
+      double lo, hi;
+      bool lower_first;
+      edge_ray_paths(*g, theta, x, lo, hi, lower_first);
+      // absorption in the block met first, then in the other one
+      const double a_lo = -std::expm1(-mu * lo), a_hi = -std::expm1(-mu * hi);
+      const double p_lo = lower_first ? a_lo : std::exp(-mu * hi) * a_lo;
+      const double p_hi = lower_first ? std::exp(-mu * lo) * a_hi : a_hi;
+      double v;
+      if (p_lo + p_hi > 0.0) v = p_lo / (p_lo + p_hi);
+      else v = x < 0.0 ? 1.0 : (x > 0.0 ? 0.0 : 0.5);
+      out[a * g->n_pos + j] = static_cast<float>(v);
+    }
+  }
+  return SSE_OK;
+}
+
 sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uint64_t seed, uint64_t h_offset,
                         const sse_outputs* out, void* stream) {
   if (!c) return fail(SSE_EINVAL, "null context");
   Phantom* ph = get_phantom(c, id);
   if (!ph) return fail(SSE_EINVAL, "unknown phantom id");
   if (!c->d_lut) return fail(SSE_ESTATE, "no LUT loaded");
+  if (c->gaps_on && !lut_fits_gaps(c->sc, c->lut)) return fail(SSE_ESTATE, "the loaded LUT lacks the gap layout");
   if (!out || !out->scatter_counts || !out->scatter_weights) return fail(SSE_EINVAL, "scatter outputs are required");
   if (reinterpret_cast<uintptr_t>(out->scatter_counts) % 4 || reinterpret_cast<uintptr_t>(out->scatter_weights) % 8 ||
       reinterpret_cast<uintptr_t>(out->true_counts) % 4 || reinterpret_cast<uintptr_t>(out->true_weights) % 8 ||

@@ -32,6 +32,10 @@ struct sse_ctx {
   int lut_type = -1;
   sse_lut_desc lut{};
   float* d_sens = nullptr;
+  // gap model (gaps_on = 0: plain cylinder) and the device copies of the edge LUTs
+  int gaps_on = 0;
+  sse_gap_desc gaps{};
+  float* d_edge[2] = {nullptr, nullptr};
   int sens_tof = 0;
   float* d_scratch[2] = {nullptr, nullptr};
   // pair buffer of the transport -> coincidence hand-over (kPairWords words
@@ -50,6 +54,8 @@ sse_status fail(sse_status st, const std::string& msg);
 sse_status hip_fail(hipError_t e, const char* what);
 void release(void* p);
 Phantom* get_phantom(sse_ctx* c, sse_phantom_id id);
+// With gaps on, whether a LUT's crystal axes have the gap layout.
+bool lut_fits_gaps(const sse_scanner_desc& sc, const sse_lut_desc& d);
 // Kernel parameters of histories [h0, h0 + n) of a phantom (outputs unset).
 void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, uint64_t h0, uint64_t n,
                             sse::TransportParams& p);

@@ -11,14 +11,21 @@ constexpr float kMec2 = 510.99895f;          // electron rest energy, keV (CODAT
 constexpr int kMaxSteps = 100000;            // tentative Woodcock steps per photon
 constexpr int kMaxTries = 1000;              // rejection-loop guard (never reached)
 constexpr int kRecordWords = 32;
-constexpr int kStatCount = 19;
+constexpr int kStatCount = 21;
 
 enum LutType { kLutF32 = 0, kLutF16 = 1, kLutBF16 = 2 };
+// What happens to a single that hits a gap between modules or blocks (the
+// values of sse_gap_policy).
+enum GapPolicy { kGapDiscard = 0, kGapNearest = 1, kGapEdgeLut = 2 };
 
 // A coincidence with both singles in the energy window, as the transport
 // kernel hands it to the coincidence kernel: one 80-byte record per pair
 // (written as five 16-byte stores).
-constexpr int kSingleWords = 7;  // per single: hx, hy, dx, dy, dz, path, ring | energy bin << 16
+// Per single: hit x, y, z, direction x, y, z, path length (floats) and the
+// LUT energy bin; where the hit lies on the detector (crystal, ring, gap) is
+// the coincidence kernel's work.
+constexpr int kSingleWords = 8;
+enum SingleWord { kSX = 0, kSY, kSZ, kSDx, kSDy, kSDz, kSPath, kSEbin };
 enum PairWord {
   kPhLo = 0,   // history, low and high word
   kPhHi,
@@ -26,8 +33,9 @@ enum PairWord {
   kPFlags,     // scattered << 8 | request slot << 16, or kEmptyPair
   kPA,         // photon A, kSingleWords words
   kPB = kPA + kSingleWords,
-  kPairWords = 20  // with two words of padding
+  kPairWords = kPB + kSingleWords
 };
+static_assert(kPairWords % 4 == 0, "pair records are written as 16-byte stores");
 constexpr uint32_t kEmptyPair = 0xffffffffu;  // flags of a padding record
 // Wavefronts reserve the buffer in blocks of kPairBlock records (one atomic
 // per block); the part of a block a wavefront cannot use is padded with
@@ -74,6 +82,16 @@ struct TransportParams {
   int lut_type;
   int d0, d1, d2, d3, d4;
   float e_min, e_scale;
+  // gaps between modules and blocks (gap_on = 0: plain cylinder): gap
+  // policy, module and block counts, transaxial gap angle and module angle,
+  // axial geometry in binary64 (half length, gap width, ring pitch, the rings
+  // of a block, block period), and the edge-crystal LUTs
+  int gap_on, gap_policy, n_mod, n_blk;
+  double gap_t, mod_d;
+  double half_len_d, gap_a, pitch_a, block_span, block_period;
+  const float* edge_t;
+  const float* edge_a;
+  int edge_na, edge_np;
   // run
   uint64_t seed, h0, n;
   // outputs

@@ -311,6 +311,7 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
   *out = nullptr;
   if (cfg->max_active < 1 || cfg->max_active > 256) return fail(SSE_EINVAL, "max_active must be 1..256");
   if (!c->d_lut) return fail(SSE_ESTATE, "no LUT loaded");
+  if (c->gaps_on && !lut_fits_gaps(c->sc, c->lut)) return fail(SSE_ESTATE, "the loaded LUT lacks the gap layout");
   HIP_TRY(hipSetDevice(c->device), "set device");
   sse_server* s = new (std::nothrow) sse_server();
   if (!s) return fail(SSE_ENOMEM, "host allocation");

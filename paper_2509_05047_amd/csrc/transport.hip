@@ -43,7 +43,7 @@ enum Fate { kDetected = 0, kAbsorbed = 1, kKilled = 2, kCapped = 3, kAxial = 4, 
 enum Stat {
   kStHist = 0, kStSteps, kStReal, kStCompton, kStRayleigh, kStAbsorbed, kStKilled, kStCapped, kStEscaped,
   kStDetected, kStInWindow, kStScatter, kStTrue, kStRejWindow, kStRejSame, kStRejRing, kStRejRadial,
-  kStRejTof, kStRngBlocks
+  kStRejTof, kStRngBlocks, kStRejGap, kStGapAssigned
 };
 
 // ---------------------------------------------------------------------------
@@ -285,7 +285,14 @@ __device__ __forceinline__ float lut_value(const TransportParams& p, uint32_t i)
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-// Crystal of a single detected at (hx, hy): azimuth in [0, 2 pi) in binary64.
+__device__ __forceinline__ int clamp_index_d(double f, int n) {
+  if (!(f >= 0.0)) return 0;
+  if (f >= static_cast<double>(n)) return n - 1;
+  return static_cast<int>(f);
+}
+
+// Crystal of a single detected at (hx, hy) on the plain cylinder: azimuth in
+// [0, 2 pi) in binary64.
 __device__ __forceinline__ int crystal_of(const TransportParams& p, float hx, float hy) {
   double phi = atan2(static_cast<double>(hy), static_cast<double>(hx));
   if (phi < 0.0) phi += kTwoPi;
@@ -301,29 +308,119 @@ __device__ __forceinline__ int energy_bin(const TransportParams& p, float E) {
   return clamp_floor((E - p.e_min) * p.e_scale, p.d0);
 }
 
-// Flat LUT index of a single: energy bin, transaxial and axial incidence
-// angles relative to the radial direction at the hit, crystal-in-module and
-// ring-in-block positions.
-__device__ __forceinline__ uint32_t lut_index(const TransportParams& p, float hx_, float hy_, float dx, float dy,
-                                              float dz, int ie, int c, int rg) {
+// Where a single falls on the detector (Methods, "Scatter simulator
+// description", Fig. 4): the crystal and ring it is assigned to (for a hit in
+// a gap, the nearest edge crystal and ring), its coordinates on the LUT's
+// crystal axes, and for a gap hit the edge crystals / rings of the lower and
+// upper side and the position across the gap (0 at the lower side).
+struct Hit {
+  int crystal, ring, ct, ca;
+  int c_lo, c_hi, r_lo, r_hi;
+  double tfrac, afrac;
+  bool tgap, agap;
+};
+
+__device__ void locate(const TransportParams& p, float hx, float hy, float hz, Hit& h) {
+  h.tgap = false;
+  h.agap = false;
+  h.c_lo = h.c_hi = h.r_lo = h.r_hi = 0;
+  h.tfrac = h.afrac = 0.0;
+  if (!p.gap_on) {
+    // plain cylinder: the LUT's crystal axes bin the crystal in its module
+    // and the ring in its block
+    h.crystal = crystal_of(p, hx, hy);
+    h.ring = ring_of(p, hz);
+    h.ct = ((h.crystal % p.cmod) * p.d3) / p.cmod;
+    h.ca = ((h.ring % p.rblk) * p.d4) / p.rblk;
+    return;
+  }
+  const int cm = p.cmod, rb = p.rblk, nm = p.n_mod, nb = p.n_blk;
+  // Transaxial: module m spans azimuth [m D, (m + 1) D) with half a gap of
+  // angle g at either end and cm crystals of width (D - g) / cm between.
+  // LUT index 0 is the gap half before the module, cm + 1 the one after it.
+  const double g = p.gap_t, D = p.mod_d;
+  double phi = atan2(static_cast<double>(hy), static_cast<double>(hx));
+  if (phi < 0.0) phi += kTwoPi;
+  const int m = clamp_index_d(floor(phi / D), nm);
+  const double loc = phi - static_cast<double>(m) * D;
+  if (g > 0.0 && loc < 0.5 * g) {
+    h.tgap = true;
+    h.c_lo = ((m + nm - 1) % nm) * cm + cm - 1;
+    h.c_hi = m * cm;
+    h.crystal = h.c_hi;
+    h.ct = 0;
+    h.tfrac = (loc + 0.5 * g) / g;
+  } else if (g > 0.0 && loc >= D - 0.5 * g) {
+    h.tgap = true;
+    h.c_lo = m * cm + cm - 1;
+    h.c_hi = ((m + 1) % nm) * cm;
+    h.crystal = h.c_lo;
+    h.ct = cm + 1;
+    h.tfrac = (loc - (D - 0.5 * g)) / g;
+  } else {
+    const int k = clamp_index_d(floor((loc - 0.5 * g) * static_cast<double>(cm) / (D - g)), cm);
+    h.crystal = m * cm + k;
+    h.ct = k + 1;
+  }
+  // Axial: blocks of rb rings of pitch pitch_a separated by gaps of width w
+  // (none at the scanner's ends).  Block b's rings have LUT indices
+  // b (rb + 2) + 1 + k, the gap halves either side of it b (rb + 2) and
+  // b (rb + 2) + rb + 1.
+  const double w = p.gap_a;
+  const double z = static_cast<double>(hz) + p.half_len_d;
+  const int b = clamp_index_d(floor(z / p.block_period), nb);
+  const double zl = z - static_cast<double>(b) * p.block_period;
+  if (w > 0.0 && b < nb - 1 && zl >= p.block_span) {
+    const double go = zl - p.block_span;
+    h.agap = true;
+    h.r_lo = b * rb + rb - 1;
+    h.r_hi = (b + 1) * rb;
+    h.afrac = go / w;
+    const bool lower = go < 0.5 * w;
+    h.ring = lower ? h.r_lo : h.r_hi;
+    h.ca = lower ? b * (rb + 2) + rb + 1 : (b + 1) * (rb + 2);
+  } else {
+    const int k = clamp_index_d(floor(zl / p.pitch_a), rb);
+    h.ring = b * rb + k;
+    h.ca = b * (rb + 2) + 1 + k;
+  }
+  // a LUT axis of size 1 ignores the coordinate
+  if (p.d3 == 1) h.ct = 0;
+  if (p.d4 == 1) h.ca = 0;
+}
+
+// Transaxial and axial incidence angles of a single: the angles between its
+// path and the hit point's position vector, projected in the transaxial and
+// axial planes, in [-90, 90] degrees (Fig. 5 caption), binary64.
+__device__ __forceinline__ void incidence(float hx_, float hy_, float dx, float dy, float dz, double& th_t,
+                                          double& th_a) {
   const double hx = static_cast<double>(hx_), hy = static_cast<double>(hy_);
   const double rho = sqrt(hx * hx + hy * hy);
   const double dr = (hx * static_cast<double>(dx) + hy * static_cast<double>(dy)) / rho;
   const double tt = (hx * static_cast<double>(dy) - hy * static_cast<double>(dx)) / rho;
-  const int it = angle_bin(atan2(tt, dr), p.d1);
-  const int ia = angle_bin(atan2(static_cast<double>(dz), dr), p.d2);
-  const int ct = ((c % p.cmod) * p.d3) / p.cmod;
-  const int ca = ((rg % p.rblk) * p.d4) / p.rblk;
+  th_t = atan2(tt, dr);
+  th_a = atan2(static_cast<double>(dz), dr);
+}
+
+// Flat LUT index of a single: energy bin, incidence angles, crystal axes.
+__device__ __forceinline__ uint32_t lut_index(const TransportParams& p, int ie, double th_t, double th_a, int ct,
+                                              int ca) {
+  const int it = angle_bin(th_t, p.d1);
+  const int ia = angle_bin(th_a, p.d2);
   return static_cast<uint32_t>((((ie * p.d1 + it) * p.d2 + ia) * p.d3 + ct) * p.d4 + ca);
 }
 
-// Crystal, ring and flat LUT index of a single detected at (hx, hy, hz) with
-// direction (dx, dy, dz) and energy E.
+// crystal | ring << 16 (the nearest edge ones for a gap hit) and the flat LUT
+// index of a single detected at (hx, hy, hz) with direction (dx, dy, dz) and
+// energy E.
 __device__ void index_single(const TransportParams& p, float hx, float hy, float hz, float dx, float dy, float dz,
-                             float E, int& crystal, int& ring, uint32_t& lut) {
-  crystal = crystal_of(p, hx, hy);
-  ring = ring_of(p, hz);
-  lut = lut_index(p, hx, hy, dx, dy, dz, energy_bin(p, E), crystal, ring);
+                             float E, uint32_t& crystal_ring, uint32_t& lut) {
+  Hit h;
+  locate(p, hx, hy, hz, h);
+  double th_t, th_a;
+  incidence(hx, hy, dx, dy, dz, th_t, th_a);
+  crystal_ring = static_cast<uint32_t>(h.crystal) | (static_cast<uint32_t>(h.ring) << 16);
+  lut = lut_index(p, energy_bin(p, E), th_t, th_a, h.ct, h.ca);
 }
 
 // q = v / d for v < 2^24 and d >= 1: binary32 reciprocal estimate (off by at
@@ -379,9 +476,43 @@ __device__ __forceinline__ float std_normal(Q& q, const TransportParams& p) {
   return 0.0f;
 }
 
-// Pair i of the buffer: crystals, ring difference and radial acceptance,
-// TOF bin with jitter, LUT weight, sinogram update (and record and counters
-// in the instrumented form).
+// Edge-crystal assignment of a gap hit of a coincidence (Methods, "Edge
+// crystal assignment LUT"): with the edge-LUT policy a uniform from the
+// history's stream below the table's probability (at the incidence-angle and
+// position bin) picks the lower side's edge crystal or ring, otherwise the
+// upper side's; a hit in both kinds of gap draws for the transaxial gap
+// first.  The nearest policy keeps the nearest edge crystal.  Returns the
+// number of gap assignments.
+__device__ int resolve_gap(const TransportParams& p, RegRng& q, Hit& h, double th_t, double th_a) {
+  const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
+  const bool draw = p.gap_policy == kGapEdgeLut;
+  const int np = p.edge_np;
+  int n = 0;
+  if (h.tgap) {
+    if (draw) {
+      const int ia = angle_bin(th_t, p.edge_na);
+      const int ip = clamp_index_d(floor(h.tfrac * static_cast<double>(np)), np);
+      if (q.left == 0u) q.refill(k0, k1);
+      h.crystal = q.uniform() < p.edge_t[ia * np + ip] ? h.c_lo : h.c_hi;
+    }
+    ++n;
+  }
+  if (h.agap) {
+    if (draw) {
+      const int ia = angle_bin(th_a, p.edge_na);
+      const int ip = clamp_index_d(floor(h.afrac * static_cast<double>(np)), np);
+      if (q.left == 0u) q.refill(k0, k1);
+      h.ring = q.uniform() < p.edge_a[ia * np + ip] ? h.r_lo : h.r_hi;
+    }
+    ++n;
+  }
+  return n;
+}
+
+// Pair i of the buffer: where both singles fall (crystals, rings, gaps), the
+// gap policy, ring difference and radial acceptance, TOF bin with jitter, LUT
+// weight, sinogram update (and record and counters in the instrumented
+// form).
 template <bool kInstr>
 __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const uint32_t* pairs, uint64_t i,
                                               unsigned long long* s_stats) {
@@ -393,20 +524,46 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
   const uint4 q1 = rec4[1], q2 = rec4[2], q3 = rec4[3], q4 = rec4[4];
   const uint32_t words[kPairWords] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y,
                                       q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w};
-  auto E = [&](int w) -> uint32_t { return words[w]; };
+  auto F = [&](int w) -> float { return __uint_as_float(words[w]); };
   {
-    const uint64_t hh = static_cast<uint64_t>(E(kPhLo)) | (static_cast<uint64_t>(E(kPhHi)) << 32);
-    const uint32_t pos = E(kPPos), flags = E(kPFlags);
-    const float ax = __uint_as_float(E(kPA + 0)), ay = __uint_as_float(E(kPA + 1));
-    const float bx = __uint_as_float(E(kPB + 0)), by = __uint_as_float(E(kPB + 1));
-    const uint32_t arie = E(kPA + 6), brie = E(kPB + 6);
+    const uint64_t hh = static_cast<uint64_t>(words[kPhLo]) | (static_cast<uint64_t>(words[kPhHi]) << 32);
+    const uint32_t pos = words[kPPos], flags = words[kPFlags];
     const bool scattered = (flags & 0x100u) != 0u;
-    const int cA = crystal_of(p, ax, ay), cB = crystal_of(p, bx, by);
-    const int rA = static_cast<int>(arie & 0xffffu), rB = static_cast<int>(brie & 0xffffu);
+    Hit ha, hb;
+    locate(p, F(kPA + kSX), F(kPA + kSY), F(kPA + kSZ), ha);
+    locate(p, F(kPB + kSX), F(kPB + kSY), F(kPB + kSZ), hb);
+    double ta_t, ta_a, tb_t, tb_a;
+    incidence(F(kPA + kSX), F(kPA + kSY), F(kPA + kSDx), F(kPA + kSDy), F(kPA + kSDz), ta_t, ta_a);
+    incidence(F(kPB + kSX), F(kPB + kSY), F(kPB + kSDx), F(kPB + kSDy), F(kPB + kSDz), tb_t, tb_a);
+    const bool any_gap = ha.tgap || ha.agap || hb.tgap || hb.agap;
+    // the history's stream where photon B left it (word pos), for the edge
+    // draws and the TOF jitter
+    RegRng q;
+    const bool qon = p.tof_sigma > 0.0f || (p.gap_on && p.gap_policy == kGapEdgeLut && any_gap);
+    if (qon) {
+      q.start(hh);
+      q.blk = pos >> 2;
+      q.refill(k0, k1);
+      for (uint32_t j = 0; j < (pos & 3u); ++j) q.take();
+    }
+    bool gap_drop = false;
+    int assigned = 0;
+    if (p.gap_on) {
+      if (p.gap_policy == kGapDiscard) {
+        gap_drop = any_gap;
+      } else {
+        // photon A's gaps first, then photon B's, before the jitter
+        assigned = resolve_gap(p, q, ha, ta_t, ta_a);
+        assigned += resolve_gap(p, q, hb, tb_t, tb_a);
+      }
+    }
+    const int cA = ha.crystal, cB = hb.crystal, rA = ha.ring, rB = hb.ring;
     uint32_t outcome;
     uint64_t bin = ~0ull;
     float w = 0.0f, tau = 0.0f;
-    if (cA == cB) {
+    if (gap_drop) {
+      outcome = 8;
+    } else if (cA == cB) {
       outcome = 4;
     } else if (p.max_ring_diff >= 0 && abs(rA - rB) > p.max_ring_diff) {
       outcome = 5;
@@ -423,20 +580,9 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
       if (abs(rho) > half) {
         outcome = 6;
       } else {
-        const float apath = __uint_as_float(E(kPA + 5)), bpath = __uint_as_float(E(kPB + 5));
+        const float apath = F(kPA + kSPath), bpath = F(kPB + kSPath);
         tau = a_pos ? (bpath - apath) * 0.5f : (apath - bpath) * 0.5f;
-        if (p.tof_sigma > 0.0f) {
-          // the history's stream where photon B left it: word `pos`
-          RegRng q;
-          q.start(hh);
-          q.blk = pos >> 2;
-          q.refill(k0, k1);
-          for (uint32_t i = 0; i < (pos & 3u); ++i) q.take();
-          tau = tau + p.tof_sigma * std_normal(q, p);
-          // blocks the jitter adds to those counted when photon B ended
-          if (kInstr && p.stats)
-            atomicAdd(&s_stats[kStRngBlocks], blocks_used(q.blk * 4u - q.left) - blocks_used(pos));
-        }
+        if (p.tof_sigma > 0.0f) tau = tau + p.tof_sigma * std_normal(q, p);
         const float xt = tau / p.tof_bin + static_cast<float>(p.n_tof) * 0.5f;
         if (!(xt >= 0.0f) || !(xt < static_cast<float>(p.n_tof))) {
           outcome = 7;
@@ -446,12 +592,10 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
           bin = ((tof * static_cast<uint64_t>(p.n_plane) + plane) * static_cast<uint64_t>(p.n_view) +
                  static_cast<uint64_t>(view)) * static_cast<uint64_t>(p.n_rad) +
                 static_cast<uint64_t>(rho + half);
-          const uint32_t la = lut_index(p, ax, ay, __uint_as_float(E(kPA + 2)),
-                                        __uint_as_float(E(kPA + 3)), __uint_as_float(E(kPA + 4)),
-                                        static_cast<int>(arie >> 16), cA, rA);
-          const uint32_t lb = lut_index(p, bx, by, __uint_as_float(E(kPB + 2)),
-                                        __uint_as_float(E(kPB + 3)), __uint_as_float(E(kPB + 4)),
-                                        static_cast<int>(brie >> 16), cB, rB);
+          // detection probabilities at the hit positions (a gap hit keeps its
+          // virtual LUT index whatever edge crystal it went to)
+          const uint32_t la = lut_index(p, static_cast<int>(words[kPA + kSEbin]), ta_t, ta_a, ha.ct, ha.ca);
+          const uint32_t lb = lut_index(p, static_cast<int>(words[kPB + kSEbin]), tb_t, tb_a, hb.ct, hb.ca);
           w = lut_value(p, la) * lut_value(p, lb);
           if (scattered) {
             outcome = 0;
@@ -465,12 +609,18 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
         }
       }
     }
+    // blocks the edge draws and the jitter add to those counted when photon B ended
+    if (kInstr && p.stats && qon)
+      atomicAdd(&s_stats[kStRngBlocks], blocks_used(q.blk * 4u - q.left) - blocks_used(pos));
+    if (kInstr && p.stats && assigned)
+      atomicAdd(&s_stats[kStGapAssigned], static_cast<unsigned long long>(assigned));
     SSE_COUNT(kStScatter, outcome == 0);
     SSE_COUNT(kStTrue, outcome == 1);
     SSE_COUNT(kStRejSame, outcome == 4);
     SSE_COUNT(kStRejRing, outcome == 5);
     SSE_COUNT(kStRejRadial, outcome == 6);
     SSE_COUNT(kStRejTof, outcome == 7);
+    SSE_COUNT(kStRejGap, outcome == 8);
     if (kInstr && p.rec) {
       const uint64_t off = hh - p.rec_h0;
       if (off % p.rec_stride == 0) {
@@ -855,33 +1005,32 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       const bool win = det && edet >= p.e_lo && edet <= p.e_hi;
       SSE_COUNT(kStInWindow, win);
       if (kInstr && rec) {
-        int cry = 0, rng = 0;
-        uint32_t lidx = 0xffffffffu;
-        if (win) index_single(p, hx, hy, hz, dx, dy, dz, ec.E, cry, rng, lidx);
+        uint32_t cr = 0xffffffffu, lidx = 0xffffffffu;
+        if (win) index_single(p, hx, hy, hz, dx, dy, dz, ec.E, cr, lidx);
         uint32_t* w = rec + 8 + 12 * side;
         w[0] = __float_as_uint(hx); w[1] = __float_as_uint(hy); w[2] = __float_as_uint(hz);
         w[3] = __float_as_uint(dx); w[4] = __float_as_uint(dy); w[5] = __float_as_uint(dz);
         w[6] = __float_as_uint(ec.E); w[7] = __float_as_uint(edet); w[8] = __float_as_uint(path);
-        w[9] = win ? (static_cast<uint32_t>(cry) | (static_cast<uint32_t>(rng) << 16)) : 0xffffffffu;
-        w[10] = win ? lidx : 0xffffffffu;
+        w[9] = cr;
+        w[10] = lidx;
         w[11] = static_cast<uint32_t>(nC) | (static_cast<uint32_t>(nR) << 8) | (static_cast<uint32_t>(fate) << 16);
       }
-      // what the coincidence evaluation needs of an in-window single
-      const uint32_t rie = win ? (static_cast<uint32_t>(ring_of(p, hz)) |
-                                  (static_cast<uint32_t>(energy_bin(p, ec.E)) << 16)) : 0u;
+      // the LUT energy bin of an in-window single
+      const uint32_t ebin = win ? static_cast<uint32_t>(energy_bin(p, ec.E)) : 0u;
       if (side == 0) {
         a_det = det;
         a_win = win;
         a_scat = (nC + nR) > 0;
         a_steps = steps;
         if (win) {
-          stash[0u + lane] = __float_as_uint(hx);
-          stash[64u + lane] = __float_as_uint(hy);
-          stash[128u + lane] = __float_as_uint(dx);
-          stash[192u + lane] = __float_as_uint(dy);
-          stash[256u + lane] = __float_as_uint(dz);
-          stash[320u + lane] = __float_as_uint(path);
-          stash[384u + lane] = rie;
+          stash[64u * kSX + lane] = __float_as_uint(hx);
+          stash[64u * kSY + lane] = __float_as_uint(hy);
+          stash[64u * kSZ + lane] = __float_as_uint(hz);
+          stash[64u * kSDx + lane] = __float_as_uint(dx);
+          stash[64u * kSDy + lane] = __float_as_uint(dy);
+          stash[64u * kSDz + lane] = __float_as_uint(dz);
+          stash[64u * kSPath + lane] = __float_as_uint(path);
+          stash[64u * kSEbin + lane] = ebin;
         }
         // photon B: back to back with A
         side = 1;
@@ -908,9 +1057,9 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             w[0] = make_uint4(static_cast<uint32_t>(h), static_cast<uint32_t>(h >> 32), r.blk * 4u - r.left,
                               (scattered ? 0x100u : 0u) | (p.item << 16));
             w[1] = make_uint4(stash[lane], stash[64u + lane], stash[128u + lane], stash[192u + lane]);
-            w[2] = make_uint4(stash[256u + lane], stash[320u + lane], stash[384u + lane], __float_as_uint(hx));
-            w[3] = make_uint4(__float_as_uint(hy), __float_as_uint(dx), __float_as_uint(dy), __float_as_uint(dz));
-            w[4] = make_uint4(__float_as_uint(path), rie, 0u, 0u);
+            w[2] = make_uint4(stash[256u + lane], stash[320u + lane], stash[384u + lane], stash[448u + lane]);
+            w[3] = make_uint4(__float_as_uint(hx), __float_as_uint(hy), __float_as_uint(hz), __float_as_uint(dx));
+            w[4] = make_uint4(__float_as_uint(dy), __float_as_uint(dz), __float_as_uint(path), ebin);
           }
         }
         pushed = both;

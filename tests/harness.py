@@ -90,6 +90,8 @@ def open_context(case: Case, sensitivity=None, sens_tof=True):
     ctx = sse.Context(case.scanner, case.sino, case.physics)
     pid = ctx.load_phantom(case.pdesc, case.mu, case.act)
     ctx.load_lut(case.lut_desc, case.lut_store, dtype=case.lut_dtype)
+    if case.gaps is not None:
+        ctx.set_gaps(case.gaps, case.edge_t, case.edge_a)
     if sensitivity is not None:
         ctx.load_sensitivity(sensitivity, has_tof_axis=sens_tof)
     return ctx, pid

@@ -45,6 +45,8 @@ def test_structure_sizes_match_header_layout():
     assert C.sizeof(sse.Request) == 48
     assert C.sizeof(sse.Completion) == 64
     assert C.sizeof(sse.ServerStats) == 64
+    assert C.sizeof(sse.GapDesc) == 24
+    assert C.sizeof(sse.EdgeGeom) == 24
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
@@ -101,3 +103,32 @@ def test_create_rejects_bad_descriptors(mutate):
     mutate(s, n, p)
     assert _create(s, n, p) == sse.EINVAL
     assert sse.lib().sse_last_error() != b""
+
+
+# --------------------------------------------------------------------------
+# edge-crystal LUT (host helper): the library's own Eq. (1)-(3) against the
+# oracle's (two independent implementations of the same reading)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["transaxial", "axial"])
+def test_edge_lut_equals_oracle(which):
+    gt, ga = W.edge_geometries(W.signa_scanner(), W.SIGNA_GAPS)
+    g = gt if which == "transaxial" else ga
+    lib_lut = sse.build_edge_lut(g)
+    orc_lut = O.edge_lut(g)
+    assert lib_lut.shape == orc_lut.shape == (W.EDGE_N_ANGLE, W.EDGE_N_POS)
+    assert np.abs(lib_lut.astype(np.float64) - orc_lut).max() < 2e-7
+
+
+def test_edge_lut_equals_oracle_on_odd_bins():
+    g = dict(gap_mm=3.5, depth_mm=20.0, doi_mm=6.0, mu_per_mm=0.12, n_angle=37, n_pos=5)
+    assert np.abs(sse.build_edge_lut(g).astype(np.float64) - O.edge_lut(g)).max() < 2e-7
+
+
+@pytest.mark.parametrize("bad", [dict(n_angle=0), dict(n_pos=-1), dict(gap_mm=0.0), dict(depth_mm=-1.0),
+                                 dict(doi_mm=30.0), dict(mu_per_mm=0.0), dict(gap_mm=float("nan"))])
+def test_edge_lut_rejects_bad_geometry(bad):
+    g = dict(gap_mm=3.0, depth_mm=25.0, doi_mm=8.0, mu_per_mm=0.087, n_angle=36, n_pos=16)
+    g.update(bad)
+    with pytest.raises(sse.SseError) as e:
+        sse.build_edge_lut(g)
+    assert e.value.status == sse.EINVAL

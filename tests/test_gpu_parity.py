@@ -85,6 +85,44 @@ def test_lut_modes_full_parity(mode):
         assert np.array_equal(g["scatter_weights"], g["scatter_counts"].astype(np.float64))
 
 
+@pytest.mark.parametrize("policy", ["discard", "nearest", "edge_lut"])
+def test_gap_policies_full_parity(policy):
+    """Gaps between modules and blocks with each gap policy (the LUT with
+    its virtual gap indices; the oracle's edge LUTs), TOF jitter on so that
+    the jitter continues the stream after the edge draws: the whole tiny
+    workload history by history."""
+    w = W.WORKLOADS["tiny"]
+    case = H.with_gaps(H.case_from("tiny", tof_sigma=15.0), W.TINY_GAPS, policy)
+    g, o, same = check_case(case, w.n_histories, w.seed)
+    assert same.all()
+    worst = H.compare_sinograms(g, o, g["records"], o["records"], same)
+    say(f"[parity] gaps {policy}: worst relative weight difference {worst:.3e}, "
+        f"rej_gap {g['stats']['rej_gap']}, gap_assigned {g['stats']['gap_assigned']}")
+    stats_match(g["stats"], o["stats"])
+    assert (g["stats"]["rej_gap"] > 0) == (policy == "discard")
+    assert (g["stats"]["gap_assigned"] > 0) == (policy != "discard")
+
+
+def test_gap_edge_lut_clinical_slice_parity():
+    """The Signa-like scanner with its gaps, the paper's LUT shape on the
+    crystal axes (18 transaxial, 55 axial indices) and the edge-crystal LUT
+    policy, with the edge LUTs the library builds itself."""
+    import paper_2509_05047_amd as lib_sse
+    base = H.case_from("clinical")
+    gt, ga = W.edge_geometries(base.scanner, W.SIGNA_GAPS)
+    orc_edge = (O.edge_lut(gt), O.edge_lut(ga))
+    # the two builders agree to float rounding; both sides then use the oracle's tables
+    assert max(np.abs(lib_sse.build_edge_lut(gt) - orc_edge[0]).max(),
+               np.abs(lib_sse.build_edge_lut(ga) - orc_edge[1]).max()) < 2e-7
+    case = H.with_gaps(base, W.SIGNA_GAPS, "edge_lut", edge=orc_edge)
+    assert case.lut_desc.dims[3:] == (18, 55)
+    g, o, same = check_case(case, 200_003, 5678, h_offset=987_654_321)
+    H.compare_sinograms(g, o, g["records"], o["records"], same)
+    if same.all():
+        stats_match(g["stats"], o["stats"])
+    say(f"[parity] clinical gaps: {same.mean():.6f} identical, gap_assigned {g['stats']['gap_assigned']}")
+
+
 def test_clinical_slice_parity_with_offset_and_ragged_count():
     case = H.case_from("clinical")
     g, o, same = check_case(case, 200_003, 5678, h_offset=123_456_789)
@@ -214,6 +252,48 @@ def test_edge_cases():
             ctx.load_phantom(big, np.zeros(big.shape, np.float32), np.ones(big.shape, np.float32))
         with pytest.raises(sse.SseError):
             ctx.load_lut(case.lut_desc, case.lut * 2.0)
+    finally:
+        ctx.close()
+
+
+def test_gap_argument_checks():
+    """sse_set_gaps and the LUT-layout checks reject what the gap model
+    cannot take, and switching gaps off restores the plain cylinder."""
+    case = H.case_from("tiny")
+    gcase = H.with_gaps(case, W.TINY_GAPS, "edge_lut")
+    tab = gcase.edge_t
+    ctx, pid = H.open_context(case)
+    try:
+        bad = [dict(W.TINY_GAPS, policy=3), dict(W.TINY_GAPS, policy="nearest", transaxial_gap_rad=1.0),
+               dict(W.TINY_GAPS, policy="nearest", axial_gap_mm=-1.0),
+               dict(W.TINY_GAPS, policy="nearest", axial_gap_mm=500.0)]
+        for g in bad:
+            with pytest.raises(sse.SseError) as e:
+                ctx.set_gaps(g)
+            assert e.value.status == sse.EINVAL
+        # the plain LUT (4 x 2 crystal axes) lacks the gap layout
+        with pytest.raises(sse.SseError) as e:
+            ctx.set_gaps(W.gap_desc(W.TINY_GAPS, "nearest"))
+        assert e.value.status == sse.EINVAL
+        # load the gap-layout LUT, then the edge policy needs both tables in [0, 1]
+        ctx.load_lut(gcase.lut_desc, gcase.lut_store)
+        with pytest.raises(sse.SseError):
+            ctx.set_gaps(gcase.gaps, tab, None)
+        with pytest.raises(sse.SseError):
+            ctx.set_gaps(gcase.gaps, tab, tab * 2.0)
+        ctx.set_gaps(gcase.gaps, gcase.edge_t, gcase.edge_a)
+        # with gaps on, a LUT without the layout is refused
+        with pytest.raises(sse.SseError):
+            ctx.load_lut(case.lut_desc, case.lut_store)
+        g = H.run_gpu(ctx, pid, 20_000, 5, record_stride=1)
+        o = H.run_oracle(gcase, 20_000, 5)
+        assert H.identical_mask(g["records"], o["records"]).all()
+        # gaps off again, the original LUT: the plain run
+        ctx.set_gaps(None)
+        ctx.load_lut(case.lut_desc, case.lut_store)
+        g = H.run_gpu(ctx, pid, 20_000, 5, record_stride=1)
+        o = H.run_oracle(case, 20_000, 5)
+        assert H.identical_mask(g["records"], o["records"]).all()
     finally:
         ctx.close()
 
