@@ -10,6 +10,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "context.h"
@@ -194,53 +195,107 @@ sse_status fetch_floats(const float* src, uint64_t n, int mem, hipStream_t s, st
   return SSE_OK;
 }
 
-// Integer alias table (see sse_build_alias_table); returns false on bad input.
-bool build_alias(const float* act, uint64_t n, uint32_t* thresh, uint32_t* alias, double* sum_out) {
+// Integer alias table (see sse_build_alias_table), packed as (threshold,
+// alias) pairs into out; returns false on bad input.  The sum runs in index
+// order (its rounding is part of the definition); each voxel's mass depends
+// only on its activity and the sum, so the masses are computed in parallel,
+// the remainder going to the first largest; Vose's pairing is sequential by
+// definition and runs on the two stacks of the workspace.
+bool build_alias(const float* act, uint64_t n, AliasWork& w, uint2* out, double* sum_out) {
   if (n == 0 || n > 0xffffffffull) return false;
   double sum = 0.0;
+  bool bad = false;
   for (uint64_t i = 0; i < n; ++i) {
     const double a = static_cast<double>(act[i]);
-    if (!(a >= 0.0) || std::isinf(a)) return false;
+    bad |= !(a >= 0.0) || std::isinf(a);
     sum += a;
   }
-  if (!(sum > 0.0) || std::isinf(sum)) return false;
-  const uint64_t T = static_cast<uint64_t>(1) << 32;
-  std::vector<uint64_t> mass(n), small, large;
-  small.reserve(n);
-  large.reserve(n);
+  if (bad || !(sum > 0.0) || std::isinf(sum)) return false;
+  constexpr uint64_t T = static_cast<uint64_t>(1) << 32;
+  if (w.mass.size() < n) {
+    w.mass.resize(n);
+    w.small.resize(n);
+    w.large.resize(n);
+  }
+  uint64_t* mass = w.mass.data();
   const double scale = static_cast<double>(n) * 4294967296.0 / sum;
-  uint64_t total = 0, imax = 0;
-  for (uint64_t i = 0; i < n; ++i) {
-    mass[i] = static_cast<uint64_t>(std::floor(static_cast<double>(act[i]) * scale));
-    total += mass[i];
-    if (mass[i] > mass[imax]) imax = i;
+  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const unsigned nt = n >= (1u << 20) ? hw : 1u;
+  std::vector<uint64_t> part_total(nt, 0), part_max(nt, 0);
+  auto quantise = [&](unsigned t) {
+    const uint64_t a = n * t / nt, b = n * (t + 1) / nt;
+    uint64_t tot = 0, m = a;
+    for (uint64_t i = a; i < b; ++i) {
+      const uint64_t v = static_cast<uint64_t>(std::floor(static_cast<double>(act[i]) * scale));
+      mass[i] = v;
+      tot += v;
+      if (v > mass[m]) m = i;
+    }
+    part_total[t] = tot;
+    part_max[t] = m;
+  };
+  if (nt == 1) {
+    quantise(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nt; ++t) pool.emplace_back(quantise, t);
+    for (auto& th : pool) th.join();
+  }
+  uint64_t total = 0, imax = part_max[0];
+  for (unsigned t = 0; t < nt; ++t) {
+    total += part_total[t];
+    if (mass[part_max[t]] > mass[imax]) imax = part_max[t];
   }
   mass[imax] += n * T - total;
-  for (uint64_t i = 0; i < n; ++i) (mass[i] < T ? small : large).push_back(i);
-  while (!small.empty() && !large.empty()) {
-    const uint64_t l = small.back();
-    small.pop_back();
-    const uint64_t g = large.back();
-    large.pop_back();
-    thresh[l] = static_cast<uint32_t>(mass[l]);
-    alias[l] = static_cast<uint32_t>(g);
-    mass[g] -= T - mass[l];
-    (mass[g] < T ? small : large).push_back(g);
+  uint32_t* small = w.small.data();
+  uint32_t* large = w.large.data();
+  uint64_t ns = 0, nl = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (mass[i] < T) small[ns++] = static_cast<uint32_t>(i);
+    else large[nl++] = static_cast<uint32_t>(i);
   }
-  for (uint64_t g : large) { thresh[g] = 0xffffffffu; alias[g] = static_cast<uint32_t>(g); }
-  for (uint64_t l : small) { thresh[l] = 0xffffffffu; alias[l] = static_cast<uint32_t>(l); }
+  while (ns && nl) {
+    const uint32_t l = small[--ns], g = large[--nl];
+    const uint64_t ml = mass[l];
+    out[l] = make_uint2(static_cast<uint32_t>(ml), g);
+    const uint64_t mg = mass[g] - (T - ml);
+    mass[g] = mg;
+    if (mg < T) small[ns++] = g;
+    else large[nl++] = g;
+  }
+  while (nl) {
+    const uint32_t g = large[--nl];
+    out[g] = make_uint2(0xffffffffu, g);
+  }
+  while (ns) {
+    const uint32_t l = small[--ns];
+    out[l] = make_uint2(0xffffffffu, l);
+  }
   if (sum_out) *sum_out = sum;
   return true;
 }
 
-sse_status upload_alias(const float* act_host, uint64_t n, hipStream_t s, uint2* d_alias, double* sum) {
-  std::vector<uint32_t> th(n), al(n);
-  if (!build_alias(act_host, n, th.data(), al.data(), sum))
+// Build a phantom's alias table from host activity into its pinned staging
+// buffer and upload it on stream s (synchronous: the table is in place for
+// work on any stream when this returns).
+sse_status upload_alias(const float* act_host, hipStream_t s, Phantom& p) {
+  if (!p.alias_work) p.alias_work = std::make_shared<AliasWork>();
+  AliasWork& w = *p.alias_work;
+  const uint64_t n = p.nvox;
+  if (w.staging_cap < n) {
+    if (w.staging) (void)hipHostFree(w.staging);
+    w.staging = nullptr;
+    w.staging_cap = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.staging), n * sizeof(uint2), hipHostMallocDefault),
+            "allocate alias staging buffer");
+    w.staging_cap = n;
+  }
+  double sum = 0.0;
+  if (!build_alias(act_host, n, w, w.staging, &sum))
     return fail(SSE_EINVAL, "activity must be finite, non-negative and not all zero");
-  std::vector<uint2> packed(n);
-  for (uint64_t i = 0; i < n; ++i) packed[i] = make_uint2(th[i], al[i]);
-  HIP_TRY(hipMemcpyAsync(d_alias, packed.data(), n * sizeof(uint2), hipMemcpyHostToDevice, s), "upload alias table");
+  HIP_TRY(hipMemcpyAsync(p.d_alias, w.staging, n * sizeof(uint2), hipMemcpyHostToDevice, s), "upload alias table");
   HIP_TRY(hipStreamSynchronize(s), "synchronise alias upload");
+  p.activity_sum = sum;
   return SSE_OK;
 }
 
@@ -380,8 +435,15 @@ const char* sse_last_error(void) { return g_error.c_str(); }
 
 sse_status sse_build_alias_table(const float* activity, uint64_t n, uint32_t* thresh, uint32_t* alias) {
   if (!activity || !thresh || !alias) return fail(SSE_EINVAL, "null pointer");
-  if (!build_alias(activity, n, thresh, alias, nullptr))
+  if (n == 0 || n > 0xffffffffull) return fail(SSE_EINVAL, "activity must have 1 .. 2^32 - 1 entries");
+  AliasWork w;
+  std::vector<uint2> packed(n);
+  if (!build_alias(activity, n, w, packed.data(), nullptr))
     return fail(SSE_EINVAL, "activity must be finite, non-negative and not all zero");
+  for (uint64_t i = 0; i < n; ++i) {
+    thresh[i] = packed[i].x;
+    alias[i] = packed[i].y;
+  }
   return SSE_OK;
 }
 
@@ -469,7 +531,7 @@ sse_status sse_load_phantom(sse_ctx* c, const sse_phantom_desc* d, const float* 
     release(p.d_mu);
     return hip_fail(e, "allocate alias table");
   }
-  st = upload_alias(hact.data(), n, s, p.d_alias, &p.activity_sum);
+  st = upload_alias(hact.data(), s, p);
   if (st == SSE_OK) {
     e = hipMemcpyAsync(p.d_mu, hmu.data(), n * sizeof(float), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -500,10 +562,14 @@ sse_status sse_update_activity(sse_ctx* c, sse_phantom_id id, const float* activ
   if (!activity) return fail(SSE_EINVAL, "null activity");
   HIP_TRY(hipSetDevice(c->device), "set device");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<float> hact;
-  sse_status st = fetch_floats(activity, p->nvox, mem, s, hact);
-  if (st != SSE_OK) return st;
-  return upload_alias(hact.data(), p->nvox, s, p->d_alias, &p->activity_sum);
+  if (!p->alias_work) p->alias_work = std::make_shared<AliasWork>();
+  const float* host_act = activity;
+  if (mem != SSE_MEM_HOST) {
+    sse_status st = fetch_floats(activity, p->nvox, mem, s, p->alias_work->act);
+    if (st != SSE_OK) return st;
+    host_act = p->alias_work->act.data();
+  }
+  return upload_alias(host_act, s, *p);
 }
 
 sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {

@@ -3,11 +3,30 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "internal.h"
 #include "sse.h"
+
+// Host workspace of a phantom's alias-table builds, kept between activity
+// updates so that a rebuild touches no fresh pages: the integer masses, the
+// two index stacks of the pairing, a host copy of device-resident activity,
+// and a pinned staging copy of the packed table for the upload.
+struct AliasWork {
+  std::vector<uint64_t> mass;
+  std::vector<uint32_t> small, large;
+  std::vector<float> act;
+  uint2* staging = nullptr;
+  uint64_t staging_cap = 0;
+  AliasWork() = default;
+  AliasWork(const AliasWork&) = delete;
+  AliasWork& operator=(const AliasWork&) = delete;
+  ~AliasWork() {
+    if (staging) (void)hipHostFree(staging);
+  }
+};
 
 struct Phantom {
   bool used = false;
@@ -19,6 +38,7 @@ struct Phantom {
   uint2* d_alias = nullptr;
   uint8_t* d_mu8 = nullptr;      // palette indices when the map has <= 256 distinct values
   float* d_mu_table = nullptr;   // the 256-entry palette (exact values)
+  std::shared_ptr<AliasWork> alias_work;
 };
 
 struct sse_ctx {
