@@ -66,6 +66,11 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
   p.hiy = p.loy + static_cast<float>(d.ny) * p.vy;
   p.hiz = p.loz + static_cast<float>(d.nz) * p.vz;
   p.ivx = 1.0f / p.vx; p.ivy = 1.0f / p.vy; p.ivz = 1.0f / p.vz;
+  p.fx_max = static_cast<float>(d.nx - 1);
+  p.fy_max = static_cast<float>(d.ny - 1);
+  p.fz_max = static_cast<float>(d.nz - 1);
+  // (iz ny + iy) < ny nz and each factor below 2^24: exact 24-bit products
+  p.vox24 = static_cast<uint64_t>(d.ny) * static_cast<uint64_t>(d.nz) <= (1ull << 24) && d.nx < (1 << 24);
   p.mu_maj = c->ph.mu_majorant > 0.0f ? c->ph.mu_majorant : ph->mu_max;
   p.n_crystals = c->sc.n_crystals;
   p.n_rings = c->sc.n_rings;

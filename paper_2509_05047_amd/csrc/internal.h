@@ -66,6 +66,8 @@ struct TransportParams {
   float inv_nx, inv_nxy;   // binary32 reciprocals of nx and nx * ny
   float lox, loy, loz, hix, hiy, hiz;
   float ivx, ivy, ivz, vx, vy, vz;
+  float fx_max, fy_max, fz_max;   // nx - 1, ny - 1, nz - 1
+  int vox24;                      // ny nz <= 2^24: voxel indices by 24-bit multiplies
   float mu_maj;             // Woodcock majorant at 511 keV
   // scanner and sinogram
   int n_crystals, n_rings, cmod, rblk, max_ring_diff;

@@ -101,6 +101,17 @@ __device__ __forceinline__ float to_uniform(uint32_t x) {
   return static_cast<float>((x >> 8) | 1u) * 5.9604644775390625e-08f;
 }
 
+// The key is the same for every lane of a transport wavefront.  Passed to
+// Philox as an opaque scalar, its ten round keys are formed by scalar adds at
+// each use: otherwise the compiler keeps all twenty of them live across the
+// whole transport loop, spills them into vector-register lanes and reads
+// them back with two extra vector instructions per round.
+__device__ __forceinline__ void wave_uniform_key(uint32_t& k0, uint32_t& k1) {
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
+  asm volatile("" : "+s"(k0), "+s"(k1));
+}
+
 struct LaneRng {
   LdsWord* col;  // this lane's column
   uint32_t hlo, hhi, blk, left, rd;
@@ -121,6 +132,7 @@ struct LaneRng {
   __device__ __forceinline__ bool room() const { return left <= kRngSlots - 4u; }
   __device__ __forceinline__ void refill(uint32_t k0, uint32_t k1) {
     uint32_t b0, b1, b2, b3;
+    wave_uniform_key(k0, k1);
     philox(blk, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
     LdsWord* d = col + ((blk & (kRngSlots / 4u - 1u)) << 8);  // slots 4 (blk mod kRngSlots/4) .. +3
     d[0] = b0;
@@ -263,12 +275,17 @@ __device__ __forceinline__ int clamp_floor(float f, int n) {
   return static_cast<int>(fminf(fmaxf(floorf(f), 0.0f), static_cast<float>(n - 1)));
 }
 
+// Voxel of a point, clamped to the grid (a valid index for any finite
+// point): the clamp is one median-of-three before the floor, which equals
+// flooring first and clamping to [0, n - 1] after; the index takes 24-bit
+// multiplies when the grid's sizes allow them (vox24).
 __device__ __forceinline__ uint32_t voxel_at(const TransportParams& p, float x, float y, float z) {
-  const int ix = clamp_floor((x - p.lox) * p.ivx, p.nx);
-  const int iy = clamp_floor((y - p.loy) * p.ivy, p.ny);
-  const int iz = clamp_floor((z - p.loz) * p.ivz, p.nz);
-  return (static_cast<uint32_t>(iz) * static_cast<uint32_t>(p.ny) + static_cast<uint32_t>(iy)) *
-             static_cast<uint32_t>(p.nx) + static_cast<uint32_t>(ix);
+  const uint32_t ix = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((x - p.lox) * p.ivx, 0.0f, p.fx_max)));
+  const uint32_t iy = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((y - p.loy) * p.ivy, 0.0f, p.fy_max)));
+  const uint32_t iz = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((z - p.loz) * p.ivz, 0.0f, p.fz_max)));
+  const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
+  if (p.vox24) return __umul24(__umul24(iz, ny) + iy, nx) + ix;
+  return (iz * ny + iy) * nx + ix;
 }
 
 __device__ __forceinline__ int angle_bin(double th, int n) {
@@ -646,8 +663,10 @@ __device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint32_t hlo = static_cast<uint32_t>(hh), hhi = static_cast<uint32_t>(hh >> 32);
   uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
-  philox(0u, hlo, hhi, 0u, k0, k1, a0, a1, a2, a3);
-  philox(1u, hlo, hhi, 0u, k0, k1, b0, b1, b2, b3);
+  uint32_t q0 = k0, q1 = k1;
+  wave_uniform_key(q0, q1);
+  philox(0u, hlo, hhi, 0u, q0, q1, a0, a1, a2, a3);
+  philox(1u, hlo, hhi, 0u, q0, q1, b0, b1, b2, b3);
   const uint64_t col = __umul64hi((static_cast<uint64_t>(a1) << 32) | a0, p.nvox);
   const uint2 al = p.alias[col];
   const uint32_t v = (a2 < al.x) ? static_cast<uint32_t>(col) : al.y;

@@ -298,6 +298,21 @@ def test_gap_argument_checks():
         ctx.close()
 
 
+def test_large_grid_index_paths():
+    """A 1 x 4100 x 4100 grid: ny nz > 2^24 takes the 32-bit voxel index
+    (not the 24-bit multiplies) and nvox >= 2^24 the integer-division voxel
+    decomposition of the emission; histories match the oracle."""
+    desc = W.centred_desc((1, 4100, 4100), (100.0, 0.05, 0.05))
+    z, y, x = W.voxel_centres(desc)
+    mu = np.broadcast_to(np.where((y * y + z * z) <= 60.0 ** 2, W.MU_WATER, 0.0), desc.shape).astype(np.float32)
+    act = np.broadcast_to(np.where((y * y + z * z) <= 50.0 ** 2, 1.0, 0.0), desc.shape).astype(np.float32)
+    case = H.case_from("tiny", phantom=(desc, mu, act))
+    assert desc.ny * desc.nz > (1 << 24)
+    g, o, same = check_case(case, 20_000, 17)
+    assert same.all()
+    H.compare_sinograms(g, o, g["records"], o["records"], same)
+
+
 def test_point_source_and_all_ones_lut():
     w = W.WORKLOADS["tiny"]
     ones_case = H.case_from("tiny")
