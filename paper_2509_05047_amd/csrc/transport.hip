@@ -453,9 +453,9 @@ __device__ __forceinline__ uint32_t udiv24(uint32_t v, uint32_t d, float inv_d) 
 // ---------------------------------------------------------------------------
 // tuning of the transport loop
 // ---------------------------------------------------------------------------
-// Lanes left stepping when a wave moves on to its events (measured best
-// between 4 and 10 on the clinical workload).
-constexpr int kStepTail = 6;
+// Lanes left stepping when a wave moves on to its events (measured on the
+// clinical workload: flat between 8 and 12, slower at 4 and 16).
+constexpr int kStepTail = 10;
 // Rejection rounds per iteration for the Compton sampler; a lane still
 // rejecting goes on in the next iteration with its try count.
 constexpr int kRounds = 2;
@@ -657,7 +657,9 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
 // point in it, isotropic direction with cos(theta) = 1 - 2 u (exact) and
 // azimuth 2 pi u'.  It takes exactly the eight words of Philox blocks 0 and 1
 // of the history's stream, in that order.  Columns: position, direction,
-// voxel, distance to the exit of the voxel box.
+// voxel, distances to the exit of the voxel box along +d (photon A) and -d
+// (photon B: computed here, with all lanes active, rather than when photon A
+// ends).
 __device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t hh, LdsWord* eq) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
@@ -697,7 +699,11 @@ __device__ __forceinline__ void emit_to_queue(const TransportParams& p, uint64_t
   eq[320u + lane] = __float_as_uint(cz);
   eq[384u + lane] = v;
   eq[448u + lane] = __float_as_uint(box_exit(p, ex, ey, ez, st * cp, st * sp, cz));
+  eq[512u + lane] = __float_as_uint(box_exit(p, ex, ey, ez, -(st * cp), -(st * sp), -cz));
 }
+
+// Columns of the emission queue.
+constexpr int kEmitWords = 9;
 
 // Mark records [from, to) of the wavefront's block empty (converged call).
 __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t from, uint64_t to) {
@@ -713,7 +719,8 @@ __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t fro
 // Simulate histories [next, end) of one wavefront.  mu_tab is the palette
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
 // only when kInstr); stash the wavefront's LDS area for photon A's hit data
-// (kSingleWords columns of 64 lanes); eq its emission queue (8 columns).
+// (kSingleWords columns of 64 lanes); eq its emission queue (kEmitWords
+// columns).
 // The palette pointer is typed as LDS so that its reads are LDS reads even
 // where the compiler merges them with the binary32-map path.
 typedef const __attribute__((address_space(3))) float LdsFloat;
@@ -732,6 +739,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
   uint64_t h = 0;
   uint32_t* rec = nullptr;            // this history's record, if sampled
   float ex = 0.f, ey = 0.f, ez = 0.f, edx = 0.f, edy = 0.f, edz = 0.f;  // emission point, direction of A
+  float texit_b = 0.f;                // distance to the voxel box's exit along -d
   // photon A summary (its in-window hit data wait in the stash)
   uint32_t a_steps = 0;
   bool a_det = false, a_win = false, a_scat = false;
@@ -776,6 +784,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     dx = edx; dy = edy; dz = edz;
     t = 0.0f; len = 0.0f;
     texit = __uint_as_float(eq[448u + k]);
+    texit_b = __uint_as_float(eq[512u + k]);
     ec = p.e511;
     nC = nR = nint = 0;
     steps = 0;
@@ -1056,7 +1065,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         px = ex; py = ey; pz = ez;
         dx = -edx; dy = -edy; dz = -edz;
         t = 0.0f; len = 0.0f;
-        texit = box_exit(p, px, py, pz, dx, dy, dz);
+        texit = texit_b;
         ec = p.e511;
         nC = nR = nint = 0;
         steps = 0;
@@ -1119,7 +1128,7 @@ transport_kernel(TransportParams p) {
   __shared__ float s_mu_table[256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][kRngSlots * 64];
-  __shared__ uint32_t s_emit[4][8 * 64];
+  __shared__ uint32_t s_emit[4][kEmitWords * 64];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
@@ -1145,7 +1154,7 @@ transport_batch_kernel(BatchParams b) {
   __shared__ float s_tab[4][256];
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][kRngSlots * 64];
-  __shared__ uint32_t s_emit[4][8 * 64];
+  __shared__ uint32_t s_emit[4][kEmitWords * 64];
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
