@@ -201,6 +201,7 @@ struct BatchParams {
   uint32_t* pairs;               // the items' common pair buffer
   uint32_t* pair_count;
   uint64_t pair_cap;
+  int gap_on;                    // the items' gap model is on (they share one context)
 };
 
 // One work list (at most transport_batch_max_histories(pair_cap) histories

@@ -273,7 +273,7 @@ void scheduler(sse_server* s) {
         break;
       }
       sse::BatchParams b{s->d_items, s->d_chunks[s->parity] + c0, c1 - c0, s->d_counter,
-                         hist, s->d_pairs, s->d_pair_count, s->pair_cap};
+                         hist, s->d_pairs, s->d_pair_count, s->pair_cap, s->ctx->gaps_on};
       e = sse::launch_transport_batch(b, s->stream);
       c0 = c1;
     }

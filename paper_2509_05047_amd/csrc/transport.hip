@@ -337,20 +337,28 @@ struct Hit {
   bool tgap, agap;
 };
 
-__device__ void locate(const TransportParams& p, float hx, float hy, float hz, Hit& h) {
+// The plain cylinder: the LUT's crystal axes bin the crystal in its module
+// and the ring in its block.
+__device__ __forceinline__ void locate_plain(const TransportParams& p, float hx, float hy, float hz, Hit& h) {
   h.tgap = false;
   h.agap = false;
   h.c_lo = h.c_hi = h.r_lo = h.r_hi = 0;
   h.tfrac = h.afrac = 0.0;
+  h.crystal = crystal_of(p, hx, hy);
+  h.ring = ring_of(p, hz);
+  h.ct = ((h.crystal % p.cmod) * p.d3) / p.cmod;
+  h.ca = ((h.ring % p.rblk) * p.d4) / p.rblk;
+}
+
+__device__ void locate(const TransportParams& p, float hx, float hy, float hz, Hit& h) {
   if (!p.gap_on) {
-    // plain cylinder: the LUT's crystal axes bin the crystal in its module
-    // and the ring in its block
-    h.crystal = crystal_of(p, hx, hy);
-    h.ring = ring_of(p, hz);
-    h.ct = ((h.crystal % p.cmod) * p.d3) / p.cmod;
-    h.ca = ((h.ring % p.rblk) * p.d4) / p.rblk;
+    locate_plain(p, hx, hy, hz, h);
     return;
   }
+  h.tgap = false;
+  h.agap = false;
+  h.c_lo = h.c_hi = h.r_lo = h.r_hi = 0;
+  h.tfrac = h.afrac = 0.0;
   const int cm = p.cmod, rb = p.rblk, nm = p.n_mod, nb = p.n_blk;
   // Transaxial: module m spans azimuth [m D, (m + 1) D) with half a gap of
   // angle g at either end and cm crystals of width (D - g) / cm between.
@@ -529,8 +537,9 @@ __device__ int resolve_gap(const TransportParams& p, RegRng& q, Hit& h, double t
 // Pair i of the buffer: where both singles fall (crystals, rings, gaps), the
 // gap policy, ring difference and radial acceptance, TOF bin with jitter, LUT
 // weight, sinogram update (and record and counters in the instrumented
-// form).
-template <bool kInstr>
+// form).  kGaps: the gap model is compiled in (it is used when p.gap_on);
+// without it the plain cylinder's evaluation keeps fewer registers.
+template <bool kInstr, bool kGaps>
 __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const uint32_t* pairs, uint64_t i,
                                               unsigned long long* s_stats) {
   const uint32_t lane = threadIdx.x & 63u;
@@ -547,16 +556,21 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
     const uint32_t pos = words[kPPos], flags = words[kPFlags];
     const bool scattered = (flags & 0x100u) != 0u;
     Hit ha, hb;
-    locate(p, F(kPA + kSX), F(kPA + kSY), F(kPA + kSZ), ha);
-    locate(p, F(kPB + kSX), F(kPB + kSY), F(kPB + kSZ), hb);
+    if (kGaps) {
+      locate(p, F(kPA + kSX), F(kPA + kSY), F(kPA + kSZ), ha);
+      locate(p, F(kPB + kSX), F(kPB + kSY), F(kPB + kSZ), hb);
+    } else {
+      locate_plain(p, F(kPA + kSX), F(kPA + kSY), F(kPA + kSZ), ha);
+      locate_plain(p, F(kPB + kSX), F(kPB + kSY), F(kPB + kSZ), hb);
+    }
     double ta_t, ta_a, tb_t, tb_a;
     incidence(F(kPA + kSX), F(kPA + kSY), F(kPA + kSDx), F(kPA + kSDy), F(kPA + kSDz), ta_t, ta_a);
     incidence(F(kPB + kSX), F(kPB + kSY), F(kPB + kSDx), F(kPB + kSDy), F(kPB + kSDz), tb_t, tb_a);
-    const bool any_gap = ha.tgap || ha.agap || hb.tgap || hb.agap;
+    const bool any_gap = kGaps && (ha.tgap || ha.agap || hb.tgap || hb.agap);
     // the history's stream where photon B left it (word pos), for the edge
     // draws and the TOF jitter
     RegRng q;
-    const bool qon = p.tof_sigma > 0.0f || (p.gap_on && p.gap_policy == kGapEdgeLut && any_gap);
+    const bool qon = p.tof_sigma > 0.0f || (kGaps && p.gap_on && p.gap_policy == kGapEdgeLut && any_gap);
     if (qon) {
       q.start(hh);
       q.blk = pos >> 2;
@@ -565,7 +579,7 @@ __device__ __forceinline__ void evaluate_pair(const TransportParams& p, const ui
     }
     bool gap_drop = false;
     int assigned = 0;
-    if (p.gap_on) {
+    if (kGaps && p.gap_on) {
       if (p.gap_policy == kGapDiscard) {
         gap_drop = any_gap;
       } else {
@@ -1183,7 +1197,7 @@ transport_batch_kernel(BatchParams b) {
 
 // The records the last transport launch reserved, one per thread (padding
 // records are skipped).
-template <bool kInstr>
+template <bool kInstr, bool kGaps>
 __global__ void __launch_bounds__(256) coincidence_kernel(TransportParams p) {
   __shared__ unsigned long long s_stats[kStatCount];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
@@ -1192,7 +1206,7 @@ __global__ void __launch_bounds__(256) coincidence_kernel(TransportParams p) {
   const uint64_t n = count < p.pair_cap ? count : p.pair_cap;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    evaluate_pair<kInstr>(p, p.pairs, i, s_stats);
+    evaluate_pair<kInstr, kGaps>(p, p.pairs, i, s_stats);
   if (kInstr) {
     __syncthreads();
     if (p.stats && threadIdx.x < kStatCount && s_stats[threadIdx.x])
@@ -1201,6 +1215,7 @@ __global__ void __launch_bounds__(256) coincidence_kernel(TransportParams p) {
 }
 
 // Work-list form: each pair carries its request slot.
+template <bool kGaps>
 __global__ void __launch_bounds__(256) coincidence_batch_kernel(BatchParams b) {
   const uint64_t count = *b.pair_count;
   const uint64_t n = count < b.pair_cap ? count : b.pair_cap;
@@ -1208,7 +1223,7 @@ __global__ void __launch_bounds__(256) coincidence_batch_kernel(BatchParams b) {
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint32_t flags = b.pairs[i * kPairWords + kPFlags];
     if (flags == kEmptyPair) continue;
-    evaluate_pair<false>(b.items[flags >> 16], b.pairs, i, nullptr);
+    evaluate_pair<false, kGaps>(b.items[flags >> 16], b.pairs, i, nullptr);
   }
 }
 
@@ -1274,8 +1289,11 @@ hipError_t launch(const TransportParams& p, hipStream_t stream) {
   const int grid = static_cast<int>(want < resident ? want : resident);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, p.pair_count);
   hipLaunchKernelGGL(transport_kernel<kInstr>, dim3(grid), dim3(kBlock), 0, stream, p);
-  hipLaunchKernelGGL(coincidence_kernel<kInstr>, dim3(stride_grid(pair_records_needed(p.n, 4ull * grid), cus)),
-                     dim3(kBlock), 0, stream, p);
+  const dim3 cgrid(stride_grid(pair_records_needed(p.n, 4ull * grid), cus));
+  if (p.gap_on)
+    hipLaunchKernelGGL((coincidence_kernel<kInstr, true>), cgrid, dim3(kBlock), 0, stream, p);
+  else
+    hipLaunchKernelGGL((coincidence_kernel<kInstr, false>), cgrid, dim3(kBlock), 0, stream, p);
   return hipGetLastError();
 }
 
@@ -1329,9 +1347,11 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.pair_count);
   hipLaunchKernelGGL(transport_batch_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
-  hipLaunchKernelGGL(coincidence_batch_kernel,
-                     dim3(stride_grid(pair_records_needed(b.n_histories, 4ull * grid), cus)), dim3(kBlock), 0,
-                     stream, b);
+  const dim3 cgrid(stride_grid(pair_records_needed(b.n_histories, 4ull * grid), cus));
+  if (b.gap_on)
+    hipLaunchKernelGGL(coincidence_batch_kernel<true>, cgrid, dim3(kBlock), 0, stream, b);
+  else
+    hipLaunchKernelGGL(coincidence_batch_kernel<false>, cgrid, dim3(kBlock), 0, stream, b);
   return hipGetLastError();
 }
 
