@@ -110,6 +110,37 @@ def test_requests_are_the_same_alone_and_in_the_mix():
     ctx.close()
 
 
+def test_gap_model_requests_alone_and_in_the_mix():
+    """With the gap model on (edge-LUT policy), the server's work-list
+    kernels (the coincidence evaluation compiled with gaps) give every
+    request the sinograms sse_simulate gives it alone."""
+    import oracle as O
+    ctx, pids = tiny_ctx()
+    w = W.WORKLOADS["tiny"]
+    dims = W.gap_lut_dims(w.scanner, w.lut_dims)
+    ld, lut = W.make_lut(dims, 5)
+    ctx.load_lut(ld, lut)
+    gt, ga = W.edge_geometries(w.scanner, W.TINY_GAPS)
+    ctx.set_gaps(W.gap_desc(W.TINY_GAPS, "edge_lut"), O.edge_lut(gt), O.edge_lut(ga))
+    reqs = [(pids[0], 3_000_000, 21, 0), (pids[1], 170_000, 22, 0), (pids[0], 60_000, 23, 5_000)]
+    ref = [alone(ctx, *r) for r in reqs]
+    assert int(ref[0][0].sum()) > 0
+    srv = sse.Server(ctx, max_active=4, tick_histories=1_000_000, chunk_histories=4096)
+    ids = [srv.submit(pid, n, seed, h_offset=h0) for pid, n, seed, h0 in reqs]
+    results = {}
+
+    def on_done(c):
+        assert c["status"] == sse.REQ_DONE
+        results[c["id"]] = fetch(ctx, c)
+        srv.release(c["id"])
+
+    drain(srv, len(reqs), on_done)
+    srv.stop()
+    for rid, r in zip(ids, ref):
+        same(results[rid], r)
+    ctx.close()
+
+
 def test_admission_by_hbm_budget():
     ctx, pids = tiny_ctx()
     footprint = ctx.n_bins * 12
