@@ -181,7 +181,8 @@ const char* sse_last_error(void);
 sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner,
                       const sse_sino_desc* sino, const sse_physics_desc* physics);
 
-/* Wait for the context's pending work and free everything it owns. */
+/* Wait for the context's pending work and free everything it owns.
+ * Errors: SSE_EBUSY while a server runs on the context (stop it first). */
 sse_status sse_destroy(sse_ctx* ctx);
 
 /* Load a phantom: mu511_per_mm (attenuation at 511 keV, 1/mm) and activity
@@ -197,16 +198,20 @@ sse_status sse_load_phantom(sse_ctx* ctx, const sse_phantom_desc* desc, const fl
 
 /* Replace a loaded phantom's activity (rebuilds its emission sampler); the
  * iterative estimation loop re-simulates with updated activity (Methods,
- * "Unknown activity distribution, very limited simulation time"). */
+ * "Unknown activity distribution, very limited simulation time").
+ * Errors: SSE_EINVAL, SSE_EBUSY while a server runs on the context (its
+ * requests read the sampler). */
 sse_status sse_update_activity(sse_ctx* ctx, sse_phantom_id id, const float* activity, int mem,
                                void* stream);
 
-/* Free a phantom.  Errors: SSE_EINVAL (unknown id). */
+/* Free a phantom.  Errors: SSE_EINVAL (unknown id), SSE_EBUSY while a
+ * server runs on the context. */
 sse_status sse_unload_phantom(sse_ctx* ctx, sse_phantom_id id);
 
 /* Load the 5D LUT (see sse_lut_desc) in F32, F16 or BF16 (`dtype`), host or
  * device.  Values are checked to lie in [0, 1].  Replaces any previous LUT.
- * Errors: SSE_EINVAL (bad dims, range or values), SSE_ENOMEM. */
+ * Errors: SSE_EINVAL (bad dims, range or values), SSE_ENOMEM, SSE_EBUSY
+ * while a server runs on the context (its requests hold the LUT). */
 sse_status sse_load_lut(sse_ctx* ctx, const sse_lut_desc* desc, const void* values, int dtype,
                         int mem, void* stream);
 
@@ -257,7 +262,8 @@ typedef struct {
  * n_rings of rings_per_block; a loaded LUT must have the gap layout on its
  * crystal axes (see sse_lut_desc).  edge_transaxial / edge_axial (host or
  * device per `mem`, edge_n_angle * edge_n_pos floats in [0, 1] each) are
- * read for the EDGE_LUT policy only and copied.  Errors: SSE_EINVAL. */
+ * read for the EDGE_LUT policy only and copied.  Errors: SSE_EINVAL,
+ * SSE_EBUSY while a server runs on the context. */
 sse_status sse_set_gaps(sse_ctx* ctx, const sse_gap_desc* desc, const float* edge_transaxial,
                         const float* edge_axial, int mem, void* stream);
 

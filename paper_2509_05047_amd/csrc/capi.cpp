@@ -36,6 +36,12 @@ void release(void* p) {
   if (p) (void)hipFree(p);
 }
 
+sse_status refuse_while_serving(const sse_ctx* c, const char* what) {
+  if (c->servers.load() > 0)
+    return fail(SSE_EBUSY, std::string(what) + " while a server runs on the context (stop it first)");
+  return SSE_OK;
+}
+
 // With gaps, the LUT's crystal axes carry the virtual gap indices (or are
 // ignored with size 1).
 bool lut_fits_gaps(const sse_scanner_desc& sc, const sse_lut_desc& d) {
@@ -475,6 +481,7 @@ sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner
 
 sse_status sse_destroy(sse_ctx* c) {
   if (!c) return SSE_OK;
+  if (sse_status st = refuse_while_serving(c, "cannot destroy the context"); st != SSE_OK) return st;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (auto& p : c->phantoms) {
@@ -564,6 +571,7 @@ sse_status sse_load_phantom(sse_ctx* c, const sse_phantom_desc* d, const float* 
 sse_status sse_update_activity(sse_ctx* c, sse_phantom_id id, const float* activity, int mem, void* stream) {
   Phantom* p = get_phantom(c, id);
   if (!p) return fail(SSE_EINVAL, "unknown phantom id");
+  if (sse_status st = refuse_while_serving(c, "cannot update an activity"); st != SSE_OK) return st;
   if (!activity) return fail(SSE_EINVAL, "null activity");
   HIP_TRY(hipSetDevice(c->device), "set device");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -580,6 +588,7 @@ sse_status sse_update_activity(sse_ctx* c, sse_phantom_id id, const float* activ
 sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {
   Phantom* p = get_phantom(c, id);
   if (!p) return fail(SSE_EINVAL, "unknown phantom id");
+  if (sse_status st = refuse_while_serving(c, "cannot unload a phantom"); st != SSE_OK) return st;
   HIP_TRY(hipSetDevice(c->device), "set device");
   HIP_TRY(hipDeviceSynchronize(), "wait for pending work");
   release(p->d_mu);
@@ -592,6 +601,7 @@ sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {
 
 sse_status sse_load_lut(sse_ctx* c, const sse_lut_desc* d, const void* values, int dtype, int mem, void* stream) {
   if (!c || !d || !values) return fail(SSE_EINVAL, "null argument");
+  if (sse_status st = refuse_while_serving(c, "cannot replace the LUT"); st != SSE_OK) return st;
   uint64_t n = 1;
   for (int i = 0; i < 5; ++i) {
     if (d->dims[i] <= 0) return fail(SSE_EINVAL, "LUT dimensions must be positive");
@@ -681,6 +691,7 @@ sse_status sse_load_sensitivity(sse_ctx* c, const float* sens, int has_tof_axis,
 sse_status sse_set_gaps(sse_ctx* c, const sse_gap_desc* d, const float* edge_t, const float* edge_a, int mem,
                         void* stream) {
   if (!c) return fail(SSE_EINVAL, "null context");
+  if (sse_status st = refuse_while_serving(c, "cannot change the gap model"); st != SSE_OK) return st;
   HIP_TRY(hipSetDevice(c->device), "set device");
   if (!d) {
     HIP_TRY(hipDeviceSynchronize(), "wait for pending work");

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <memory>
 #include <string>
 #include <vector>
@@ -65,6 +66,9 @@ struct sse_ctx {
   uint32_t* d_pair_count = nullptr;
   uint64_t pair_cap = 0;
   hipEvent_t pair_done = nullptr;
+  // servers running on this context: their requests hold its device tables,
+  // so calls that replace or free them are refused meanwhile
+  std::atomic<int> servers{0};
 };
 
 namespace sse_detail {
@@ -74,6 +78,8 @@ sse_status fail(sse_status st, const std::string& msg);
 sse_status hip_fail(hipError_t e, const char* what);
 void release(void* p);
 Phantom* get_phantom(sse_ctx* c, sse_phantom_id id);
+// SSE_EBUSY if a server runs on the context.
+sse_status refuse_while_serving(const sse_ctx* c, const char* what);
 // With gaps on, whether a LUT's crystal axes have the gap layout.
 bool lut_fits_gaps(const sse_scanner_desc& sc, const sse_lut_desc& d);
 // Kernel parameters of histories [h0, h0 + n) of a phantom (outputs unset).

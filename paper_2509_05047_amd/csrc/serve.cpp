@@ -378,6 +378,7 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
     free_server(s);
     return fail(SSE_ENOMEM, "scheduler thread");
   }
+  c->servers.fetch_add(1);
   *out = s;
   return SSE_OK;
 }
@@ -460,7 +461,9 @@ sse_status sse_server_stop(sse_server* s) {
   if (s->thread.joinable()) s->thread.join();
   (void)hipStreamSynchronize(s->stream);
   const std::string err = s->async_error;
+  sse_ctx* c = s->ctx;
   free_server(s);
+  c->servers.fetch_sub(1);
   if (!err.empty()) return fail(SSE_EDEVICE, err);
   return SSE_OK;
 }

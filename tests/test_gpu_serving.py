@@ -141,6 +141,28 @@ def test_gap_model_requests_alone_and_in_the_mix():
     ctx.close()
 
 
+def test_context_tables_are_locked_while_serving():
+    """Calls that would replace or free device tables a running server's
+    requests read are refused with SSE_EBUSY until the server stops."""
+    ctx, pids = tiny_ctx()
+    w = W.WORKLOADS["tiny"]
+    ld, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    srv = sse.Server(ctx, max_active=2)
+    try:
+        for call in (lambda: ctx.load_lut(ld, lut), lambda: ctx.set_gaps(None),
+                     lambda: ctx.update_activity(pids[0], W.tiny_cylinder()[2]),
+                     lambda: ctx.unload_phantom(pids[2])):
+            with pytest.raises(sse.SseError) as e:
+                call()
+            assert e.value.status == sse.EBUSY
+        assert sse.lib().sse_destroy(ctx._h) == sse.EBUSY
+    finally:
+        srv.stop()
+    ctx.load_lut(ld, lut)
+    ctx.unload_phantom(pids[2])
+    ctx.close()
+
+
 def test_admission_by_hbm_budget():
     ctx, pids = tiny_ctx()
     footprint = ctx.n_bins * 12
