@@ -29,6 +29,10 @@
  * sinogram conventions to its simulator; the readings used here are listed in
  * the design notes and are followed step for step below.
  *
+ * Parity unpinned: the Rayleigh angular model (Thomson factor times an
+ * analytic squared form factor) is this builder's choice, not the paper's;
+ * its sampler is pinned to its own pdf, but nothing fixes the model itself.
+ *
  * Precision.  The file is compiled twice.  With ORACLE_REAL=float every step
  * of the transport that decides an integer (a voxel, an interaction, a
  * crystal, a bin) is taken in binary32, the kernel's precision, with correctly
