@@ -226,19 +226,22 @@ void scheduler(sse_server* s) {
     }
     // Shortest remaining work first: the tick goes to the requests closest to
     // completion (small requests finish within one tick), the rest of the
-    // tick to the next ones; ties keep admission order.
+    // tick to the next ones; ties keep admission order.  The request that
+    // was submitted first gets the first quarter of every tick, so a large
+    // request cannot be starved by a stream of smaller arrivals.
     std::stable_sort(act.begin(), act.end(), [s](int a, int b) {
       return s->slots[a].r.n_histories - s->slots[a].next < s->slots[b].r.n_histories - s->slots[b].next;
     });
+    int oldest = act[0];
+    for (int slot : act)
+      if (s->slots[slot].t_submit < s->slots[oldest].t_submit) oldest = slot;
     sse::WorkChunk* list = s->h_chunks[s->parity];
     uint32_t nc = 0;
     uint64_t room = s->cfg.tick_histories;
     std::vector<int> in_tick;
-    for (int slot : act) {
-      if (room == 0 || nc >= s->max_chunks) break;
+    auto give = [&](int slot, uint64_t want) {
       Req& q = s->slots[slot];
-      uint64_t take = std::min<uint64_t>(room, q.r.n_histories - q.next);
-      room -= take;
+      uint64_t take = std::min<uint64_t>(want, q.r.n_histories - q.next);
       bool added = false;
       while (take > 0 && nc < s->max_chunks) {
         const uint64_t len = std::min<uint64_t>(take, chunk);
@@ -248,13 +251,19 @@ void scheduler(sse_server* s) {
         ++nc;
         q.next += len;
         take -= len;
+        room -= len;
         s->st.histories += len;
         added = true;
       }
-      if (added) {
+      if (added && std::find(in_tick.begin(), in_tick.end(), slot) == in_tick.end()) {
         ++q.inflight;
         in_tick.push_back(slot);
       }
+    };
+    give(oldest, room / 4);
+    for (int slot : act) {
+      if (room == 0 || nc >= s->max_chunks) break;
+      give(slot, room);
     }
     s->st.max_active_seen = std::max<uint64_t>(s->st.max_active_seen, in_tick.size());
     ++s->st.ticks;
