@@ -392,7 +392,8 @@ sse_status sse_build_alias_table(const float* activity, uint64_t n, uint32_t* th
  * server admits requests first-in first-out while their output footprint
  * fits an HBM budget and a slot is free, and every scheduling tick launches
  * one kernel over a work list of history sub-chunks drawn from the active
- * requests, shortest remaining work first, so requests that arrive while
+ * requests (the request submitted first takes a quarter of the tick, the
+ * rest goes by shortest remaining work first), so requests that arrive while
  * others run join the next tick and their work overlaps on the device.  Every random
  * number is keyed by the history index, so a request's sinograms are the
  * same alone or in any mix (counts exactly; weights up to the order of
