@@ -5,9 +5,11 @@
 // the activity alias table, two photons tracked with Woodcock steps through
 // the attenuation map (Compton by Kahn's method, Rayleigh with an analytic
 // form factor, photoabsorption), crossing of the detection cylinder, crystal /
-// ring / 5D-LUT indexing of each single, and one atomic update of the TOF
-// sinogram bin with count 1 and weight p_A p_B (Methods, "Scatter simulator
-// description" and "Photon detection probability LUT").
+// ring / 5D-LUT indexing of each single (with the gaps between modules and
+// blocks and the edge-crystal assignment when they are modelled), and one
+// atomic update of the TOF sinogram bin with count 1 and weight p_A p_B
+// (Methods, "Scatter simulator description", "Photon detection probability
+// LUT" and "Edge crystal assignment LUT").
 //
 // Execution model: a persistent grid; every wavefront owns a contiguous range
 // of histories and every lane runs a small state machine
@@ -24,8 +26,9 @@
 // detector-side atan2 and the TOF jitter's logarithm in binary64, rounded
 // once where they feed binary32 values.  Random numbers: one Philox4x32-10
 // stream per history, keyed by the seed and countered by (block, history),
-// consumed in order by the emission, photon A, photon B and the TOF jitter,
-// so a history's result does not depend on the launch geometry.
+// consumed in order by the emission, photon A, photon B, the edge-crystal
+// draws and the TOF jitter, so a history's result does not depend on the
+// launch geometry.
 #include "internal.h"
 
 namespace sse {

@@ -123,6 +123,30 @@ def test_gap_edge_lut_clinical_slice_parity():
     say(f"[parity] clinical gaps: {same.mean():.6f} identical, gap_assigned {g['stats']['gap_assigned']}")
 
 
+def test_paper_size_lut_with_gaps():
+    """The LUT at the paper's shape on the Signa-like scanner with gaps: 5 keV
+    energy bins over 300-650 keV, 5 degree angle bins, 18 transaxial and 55
+    axial crystal indices (70 x 36 x 36 x 18 x 55 = 90 M entries, FP16), the
+    paper's LUT energy setting and the edge-LUT policy."""
+    w = W.WORKLOADS["clinical"]
+    dims = (70, 36, 36, 18, 55)
+    assert dims == W.gap_lut_dims(w.scanner, (70, 36, 36, 16, 45))
+    ld, vals = W.make_lut(dims, 11, e_min=300.0, e_max=650.0)
+    store = vals.astype(np.float16).view(np.uint16)
+    seen = vals.astype(np.float16).astype(np.float32)
+    base = H.case_from("clinical", physics=dict(W.PHYSICS_LUT_PAPER))
+    case = H.with_gaps(base, W.SIGNA_GAPS, "edge_lut")
+    case.lut_desc, case.lut, case.lut_store, case.lut_dtype = ld, seen, store, sse.F16
+    g, o, same = check_case(case, 100_003, 31, h_offset=4_000_000_000)
+    H.compare_sinograms(g, o, g["records"], o["records"], same)
+    if same.all():
+        stats_match(g["stats"], o["stats"])
+    lidx = g["records"]["ph"]["lut_index"]
+    used = lidx[lidx != 0xFFFFFFFF]
+    say(f"[parity] paper-size LUT: max index {int(used.max())} of {vals.size}")
+    assert int(used.max()) > vals.size // 2
+
+
 def test_clinical_slice_parity_with_offset_and_ragged_count():
     case = H.case_from("clinical")
     g, o, same = check_case(case, 200_003, 5678, h_offset=123_456_789)
