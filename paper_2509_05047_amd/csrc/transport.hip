@@ -858,8 +858,16 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     // kStepTail lanes are still stepping (they go on in the next iteration)
     // rather than waiting for the longest run of steps in the wave -- unless
     // no lane has anything else to do.
-    while (__any(phase == kTrack) && (__popcll(__ballot(phase == kTrack)) > kStepTail ||
-                                      !__any(phase != kTrack && phase != kDone))) {
+    // The test is one wave-uniform flag, computed before the loop and at the
+    // end of each step: with the condition at the loop's head the compiler
+    // kept two copies of the photon state and moved eleven registers per step.
+    auto keep_stepping = [&]() -> bool {
+      const uint64_t trk_m = __ballot(phase == kTrack);
+      if (!trk_m) return false;
+      return __popcll(trk_m) > kStepTail || !__any(phase != kTrack && phase != kDone);
+    };
+    bool stepping = keep_stepping();
+    while (stepping) {
       if (__any(phase == kTrack && r.left < 2u)) {
         if (phase != kDone && r.room()) r.refill(k0, k1);
       }
@@ -895,6 +903,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       px = real ? qx : px;
       py = real ? qy : py;
       pz = real ? qz : pz;
+      stepping = keep_stepping();
     }
 
     // ---------------- real interactions ----------------------------------
