@@ -285,6 +285,9 @@ def main():
     ap.add_argument("--lut", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--lut-mode", default="lut5d", choices=list(W.LUT_MODES),
                     help="LUT variant and energy configuration (lut5d: the workload's own)")
+    ap.add_argument("--lut-shape", default="workload", choices=["workload", "paper"],
+                    help="paper: the paper's LUT shape, 5 keV bins over 0-515 keV, 5 degree angle bins, "
+                         "18 x 55 crystal indices (103 x 36 x 36 x 18 x 55; needs the gap model)")
     ap.add_argument("--gaps", default="none", choices=["none", "auto", "discard", "nearest", "edge_lut"],
                     help="gaps between modules and blocks (Signa-like widths) with this gap policy; "
                          "auto: the LUT mode's own policy")
@@ -319,12 +322,19 @@ def main():
     pdesc, mu, act = W.make_phantom(w)
     physics, lut_desc, lut = W.lut_mode(w, args.lut_mode)
     gaps = None
+    if args.lut_shape == "paper" and args.gaps == "none":
+        args.gaps = "auto"   # the 18 x 55 crystal axes are the gap layout
     if args.gaps != "none":
         policy = W.GAP_POLICY_OF_MODE[args.lut_mode] if args.gaps == "auto" else args.gaps
         gaps = W.gap_desc(W.SIGNA_GAPS, policy)
         dims = W.gap_lut_dims(w.scanner, lut_desc.dims)
+        e_min, e_max = lut_desc.e_min_kev, lut_desc.e_max_kev
+        if args.lut_shape == "paper":
+            # unit axes of the LUT variant stay unit
+            dims = tuple(1 if d == 1 else pd for d, pd in zip(dims, W.PAPER_LUT_DIMS))
+            e_min, e_max = W.PAPER_LUT_E_RANGE
         if tuple(dims) != tuple(lut_desc.dims):
-            lut_desc, lut = W.make_lut(dims, w.lut_seed, e_min=lut_desc.e_min_kev, e_max=lut_desc.e_max_kev)
+            lut_desc, lut = W.make_lut(dims, w.lut_seed, e_min=e_min, e_max=e_max)
     lut_dtype = {"f32": sse.F32, "f16": sse.F16, "bf16": sse.BF16}[args.lut]
     lut_store = {"f32": lut, "f16": lut.astype(np.float16).view(np.uint16), "bf16": W.to_bf16_bits(lut)}[args.lut]
     n = int(args.histories) if args.histories else w.n_histories
@@ -403,6 +413,7 @@ def main():
                                f"{'x'.join(map(str, w.sino.shape[::-1]))} TOF sinogram (rad x view x plane x tof), "
                                f"{'x'.join(map(str, lut_desc.dims))} {args.lut} LUT",
                    "histories_per_step": n, "lut_dtype": args.lut, "lut_mode": args.lut_mode,
+                   "lut_shape": args.lut_shape, "lut_mib": round(lut_store.nbytes / 2 ** 20, 1),
                    "gaps": (None if gaps is None else
                             dict(gaps, fraction_rejected=stats["rej_gap"] / max(1, stats["scatter"] + stats["true"]
                                                                                  + stats["rej_gap"]),
@@ -416,7 +427,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
-                                 and args.lut == "f32" and args.lut_mode == "lut5d" and gaps is None else None),
+                                 and args.lut == "f32" and args.lut_mode == "lut5d" and gaps is None
+                                 and args.lut_shape == "workload" else None),
                      "kernel": "one simulate call: transport + coincidence launches",
                      "span_ms": float(np.mean(kernel_ms)),
                      "ops_per_history": ops_per_hist},

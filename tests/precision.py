@@ -9,8 +9,8 @@ LUT stored in F32, F16 and BF16, against
     the only difference left is the order of the binary64 sums).
 
 Errors are per-bin relative errors over bins nonzero in the reference and
-the relative error of the total scatter.  Used by tests and by
-``bench.py --precision``.
+the relative error of the total scatter.  Test infrastructure (it runs the
+oracle).
 """
 from __future__ import annotations
 

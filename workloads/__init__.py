@@ -377,6 +377,14 @@ EDGE_BLOCKS = dict(depth_mm=25.0, doi_mm=8.0, mu_per_mm=0.087)
 EDGE_N_ANGLE = 36
 EDGE_N_POS = 16
 
+# The paper's LUT shape (Methods, "Photon detection probability LUT"): 5 keV
+# energy bins over the 0-511 keV source spectrum (103 bins, to 515 keV),
+# 5 degree bins of both incidence angles, 18 transaxial (16 crystals and two
+# gap halves) and 55 axial (5 blocks of 9 rings and two gap halves each)
+# crystal indices: 132 M entries.
+PAPER_LUT_DIMS = (103, 36, 36, 18, 55)
+PAPER_LUT_E_RANGE = (0.0, 515.0)
+
 # Gap policy of each LUT mode (Methods, "Photon detection probability LUT"):
 # no crystal information (or no LUT): discard; 3D with crystals: nearest edge
 # crystal; 5D: the edge-crystal LUT.
