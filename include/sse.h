@@ -291,6 +291,17 @@ typedef struct {
  * Errors: SSE_EINVAL. */
 sse_status sse_build_edge_lut(const sse_edge_geom* geom, float* out);
 
+/* Self-check of the device division: the transport forms its binary32
+ * quotients as the hardware reciprocal refined by one Newton step, then one
+ * remainder correction (Markstein 1990), which is the correctly rounded
+ * quotient when the refined reciprocal is the correctly rounded 1/b.  This
+ * call checks that premise for all 2^23 significands and compares n_random
+ * quotients of hashed operands (exponents -20..20; `seed` varies them) with
+ * the IEEE operator on the context's GPU.  Both counts are 0 on a conforming
+ * device.  Synchronous.  Errors: SSE_EINVAL, SSE_EDEVICE. */
+sse_status sse_check_division(sse_ctx* ctx, uint64_t n_random, uint32_t seed, uint64_t* reciprocal_mismatches,
+                              uint64_t* quotient_mismatches);
+
 /* Load the scatter-sensitivity sinogram (float, >= 0), with the full
  * sinogram shape (has_tof_axis = 1) or without the TOF axis (shared by all
  * TOF bins).  Methods, "Scatter sensitivity sinogram". */

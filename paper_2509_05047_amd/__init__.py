@@ -115,6 +115,7 @@ SIGNATURES = {
     "sse_load_sensitivity": ([_P, _P, C.c_int, C.c_int, _P], C.c_int),
     "sse_set_gaps": ([_P, _P, _P, _P, C.c_int, _P], C.c_int),
     "sse_build_edge_lut": ([_P, _P], C.c_int),
+    "sse_check_division": ([_P, C.c_uint64, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], C.c_int),
     "sse_simulate": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
     "sse_emission_scale": ([_P, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
@@ -284,6 +285,13 @@ class Context:
         et = None if edge_t is None else np.ascontiguousarray(edge_t, np.float32)
         ea = None if edge_a is None else np.ascontiguousarray(edge_a, np.float32)
         _check(lib().sse_set_gaps(self._h, C.byref(d), _ptr(et), _ptr(ea), MEM_HOST, None))
+
+    def check_division(self, n_random: int = 1 << 30, seed: int = 1):
+        """(reciprocal mismatches, quotient mismatches) of the device division
+        against the IEEE operator (see sse_check_division); both 0 expected."""
+        r, q = C.c_uint64(), C.c_uint64()
+        _check(lib().sse_check_division(self._h, n_random, seed, C.byref(r), C.byref(q)))
+        return r.value, q.value
 
     def load_sensitivity(self, sens, has_tof_axis: bool = True, stream=None):
         mem, s_ = self._as_input(sens)

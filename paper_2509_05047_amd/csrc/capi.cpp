@@ -751,6 +751,23 @@ sse_status sse_set_gaps(sse_ctx* c, const sse_gap_desc* d, const float* edge_t, 
   return SSE_OK;
 }
 
+sse_status sse_check_division(sse_ctx* c, uint64_t n_random, uint32_t seed, uint64_t* reciprocal_mismatches,
+                              uint64_t* quotient_mismatches) {
+  if (!c || !reciprocal_mismatches || !quotient_mismatches) return fail(SSE_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  unsigned long long* d = nullptr;
+  HIP_TRY(hipMalloc(&d, 2 * sizeof(unsigned long long)), "allocate counters");
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sse::launch_check_division(n_random, seed, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost);
+  release(d);
+  if (e != hipSuccess) return hip_fail(e, "division check");
+  *reciprocal_mismatches = h[0];
+  *quotient_mismatches = h[1];
+  return SSE_OK;
+}
+
 sse_status sse_build_edge_lut(const sse_edge_geom* g, float* out) {
   if (!g || !out) return fail(SSE_EINVAL, "null argument");
   if (g->n_angle < 1 || g->n_pos < 1 || g->n_angle > 65536 || g->n_pos > 65536)

@@ -122,6 +122,16 @@ struct TransportParams {
 // is arranged as s - (s^2/2 - r (s^2/2 + R)) so the exact s is not rounded
 // (the split of the fdlibm logarithm); -ln u = n ln 2 - ln f, n = -e, with
 // ln 2 split so that n times its leading part is exact.
+//
+// Div is how the correctly rounded quotients of the binary32 model are
+// formed: the IEEE operator on the host (IeeeDiv), an equivalent faster
+// sequence on the device (the transport's DevDiv); both give the correctly
+// rounded quotient for the operands these functions see.
+struct IeeeDiv {
+  __host__ __device__ static float div(float a, float b) { return a / b; }
+};
+
+template <class Div = IeeeDiv>
 __host__ __device__ inline float neg_log32(float u) {
   int e;
   float f = frexpf(u, &e);
@@ -130,7 +140,7 @@ __host__ __device__ inline float neg_log32(float u) {
     e -= 1;
   }
   const float s = f - 1.0f;
-  const float r = s / (2.0f + s);
+  const float r = Div::div(s, 2.0f + s);
   const float z = r * r;
   const float R = z * (2.0f / 3.0f + z * (2.0f / 5.0f + z * (2.0f / 7.0f + z * (2.0f / 9.0f))));
   const float hfsq = 0.5f * s * s;
@@ -144,11 +154,12 @@ __host__ __device__ inline float neg_log32(float u) {
 // the quotients through 1/a and 1/(1 + 2a).  Relative error below 2e-5 for
 // E >= 100 keV, the lowest kill energy accepted (cancellation grows as
 // a -> 0).
+template <class Div = IeeeDiv>
 __host__ __device__ inline float kn_total32(float a) {
-  const float ia = 1.0f / a;
+  const float ia = Div::div(1.0f, a);
   const float b = 1.0f + 2.0f * a;
-  const float i12 = 1.0f / b;
-  const float L = -neg_log32(b);
+  const float i12 = Div::div(1.0f, b);
+  const float L = -neg_log32<Div>(b);
   const float t1 = (((1.0f + a) * ia) * ia) * ((2.0f * (1.0f + a)) * i12 - L * ia);
   const float t2 = (0.5f * L) * ia;
   const float t3 = ((1.0f + 3.0f * a) * i12) * i12;
@@ -157,14 +168,17 @@ __host__ __device__ inline float kn_total32(float a) {
 
 // Coefficients of the separable attenuation model mu(x, E) = mu511(x) g(E),
 // g = fC + fR + fP with fC = kc KN(a) (kc = f_C / KN(1)), fR = f_R / a^2 and
-// fP = f_P / a^3, in binary32 (host and device evaluate it alike).
+// fP = f_P / a^3, in binary32 (host and device evaluate it alike).  The
+// majorant's reciprocal uses the IEEE operator: its divisor is 0 for a
+// phantom of air.
+template <class Div = IeeeDiv>
 __host__ __device__ inline void energy_coefficients(ECoef& c, float E, float kc, float f_r, float f_p,
                                                     float mu_maj) {
   c.E = E;
-  c.alpha = E / kMec2;
+  c.alpha = Div::div(E, kMec2);
   const float a = c.alpha;
-  const float ia = 1.0f / a;
-  const float fc = kc * kn_total32(a);
+  const float ia = Div::div(1.0f, a);
+  const float fc = kc * kn_total32<Div>(a);
   const float fr = f_r * ia * ia;
   const float fp = f_p * ia * ia * ia;
   c.g = (fc + fr) + fp;
@@ -183,6 +197,9 @@ uint64_t transport_pairs_needed(uint64_t n);
 uint64_t transport_max_histories(uint64_t cap);
 uint64_t transport_batch_pairs_needed(uint64_t n);
 uint64_t transport_batch_max_histories(uint64_t cap);
+
+// The device division check (counts: two zeroed device words).
+hipError_t launch_check_division(uint64_t n, uint32_t seed, unsigned long long* counts, hipStream_t stream);
 
 // One sub-chunk of a request: histories [h0, h0 + n) of items[item].
 struct WorkChunk {

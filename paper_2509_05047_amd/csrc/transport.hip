@@ -104,6 +104,28 @@ __device__ __forceinline__ float to_uniform(uint32_t x) {
   return static_cast<float>((x >> 8) | 1u) * 5.9604644775390625e-08f;
 }
 
+// ---------------------------------------------------------------------------
+// division
+// ---------------------------------------------------------------------------
+// The correctly rounded binary32 quotient a / b without the general divide
+// sequence (scaling, special cases): the hardware reciprocal (within one ulp)
+// refined by one Newton step is the correctly rounded reciprocal RN(1/b) for
+// every significand (sse_check_division verifies all 2^23 of them on the
+// device), and with RN(1/b) one remainder correction of q = RN(a y) gives
+// RN(a / b) (Markstein 1990).  Valid while b, 1/b and a/b are normal numbers,
+// which holds for every quotient the transport forms (see the call sites);
+// six instructions instead of about twelve.
+struct DevDiv {
+  __device__ static float div(float a, float b) {
+    const float y0 = __builtin_amdgcn_rcpf(b);
+    const float y = __builtin_fmaf(__builtin_fmaf(-b, y0, 1.0f), y0, y0);
+    const float q = a * y;
+    const float r = __builtin_fmaf(-b, q, a);
+    return __builtin_fmaf(r, y, q);
+  }
+};
+__device__ __forceinline__ float fdiv(float a, float b) { return DevDiv::div(a, b); }
+
 // The key is the same for every lane of a transport wavefront.  Passed to
 // Philox as an opaque scalar, its ten round keys are formed by scalar adds at
 // each use: otherwise the compiler keeps all twenty of them live across the
@@ -249,8 +271,9 @@ __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct
     dz = sg * ct;
   } else {
     const float tmp = sqrtf((1.0f - uz) * (1.0f + uz));
-    dx = ux * ct + st * (ux * uz * cp - uy * sp) / tmp;
-    dy = uy * ct + st * (uy * uz * cp + ux * sp) / tmp;
+    // tmp = sin of the polar angle, above 0.0045 on this branch
+    dx = ux * ct + fdiv(st * (ux * uz * cp - uy * sp), tmp);
+    dy = uy * ct + fdiv(st * (uy * uz * cp + ux * sp), tmp);
     dz = uz * ct - tmp * st * cp;
   }
 }
@@ -263,9 +286,10 @@ __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct
 // the direction does not move along left out.
 __device__ __forceinline__ float box_exit(const TransportParams& p, float px, float py, float pz, float dx,
                                           float dy, float dz) {
-  const float qx = (dx > 0.0f ? p.hix - px : p.lox - px) / dx;
-  const float qy = (dy > 0.0f ? p.hiy - py : p.loy - py) / dy;
-  const float qz = (dz > 0.0f ? p.hiz - pz : p.loz - pz) / dz;
+  // a quotient by a zero component is not used (its value does not matter)
+  const float qx = fdiv(dx > 0.0f ? p.hix - px : p.lox - px, dx);
+  const float qy = fdiv(dy > 0.0f ? p.hiy - py : p.loy - py, dy);
+  const float qz = fdiv(dz > 0.0f ? p.hiz - pz : p.loz - pz, dz);
   float t = __builtin_huge_valf();
   t = dx != 0.0f ? fminf(t, qx) : t;
   t = dy != 0.0f ? fminf(t, qy) : t;
@@ -879,7 +903,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       const bool trk = phase == kTrack;
       const bool go = trk && steps < static_cast<uint32_t>(kMaxSteps);
       const uint32_t x0 = r.peek(0u), x1 = r.peek(1u);
-      const float tn = t + neg_log32(to_uniform(x0)) * ec.inv_maj;
+      const float tn = t + neg_log32<DevDiv>(to_uniform(x0)) * ec.inv_maj;
       const bool inside = go && tn < texit;
       const float qx = px + tn * dx;
       const float qy = py + tn * dy;
@@ -971,24 +995,24 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
               const float xx = 1.0f + twoa * r2;
               if (r3 * (xx * xx) <= 4.0f * (xx - 1.0f)) { x = xx; acc = true; }
             } else {
-              const float xx = b1 / (1.0f + twoa * r2);
-              const float c = 1.0f + (1.0f - xx) / ec.alpha;
-              if (2.0f * r3 <= c * c + 1.0f / xx) { x = xx; acc = true; }
+              const float xx = fdiv(b1, 1.0f + twoa * r2);
+              const float c = 1.0f + fdiv(1.0f - xx, ec.alpha);
+              if (2.0f * r3 <= c * c + fdiv(1.0f, xx)) { x = xx; acc = true; }
             }
           }
         }
       }
       if (acc) {
         SSE_COUNT(kStCompton, true);
-        const float e2 = ec.E / x;
-        ct = 1.0f - (x - 1.0f) / ec.alpha;
+        const float e2 = fdiv(ec.E, x);
+        ct = 1.0f - fdiv(x - 1.0f, ec.alpha);
         ct = fminf(fmaxf(ct, -1.0f), 1.0f);
         ++nC;
         if (e2 < p.e_kill) {
           fate = kKilled;
           phase = kFinish;
         } else {
-          energy_coefficients(ec, e2, p.kc, p.f_r, p.f_p, p.mu_maj);
+          energy_coefficients<DevDiv>(ec, e2, p.kc, p.f_r, p.f_p, p.mu_maj);
           tries = 0;
           phase = kAzimuth;
         }
@@ -1033,7 +1057,8 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           const float c = px * px + py * py - p.rr;
           const float disc = b * b - a * c;
           const float sq = sqrtf(disc);
-          const float tc = (b > 0.0f) ? (-c) / (b + sq) : (sq - b) / a;
+          // c < 0 (the voxel box lies inside the cylinder), a > 0: a positive quotient
+          const float tc = (b > 0.0f) ? fdiv(-c, b + sq) : fdiv(sq - b, a);
           const float zz = pz + tc * dz;
           if (zz >= -p.half_len && zz < p.half_len) {
             fate = kDetected;
@@ -1241,6 +1266,44 @@ __global__ void __launch_bounds__(256) coincidence_batch_kernel(BatchParams b) {
 
 __global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
 
+// Check of DevDiv against the IEEE operator: the refined reciprocal of every
+// significand in [1, 2) (counts[0]: differences from 1 / b), then n quotients
+// of operands with hashed significands and exponents in [-20, 20]
+// (counts[1]: differences from a / b).
+__device__ __forceinline__ uint32_t check_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) check_division_kernel(uint64_t n, uint32_t seed,
+                                                             unsigned long long* counts) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long bad_r = 0, bad_q = 0;
+  for (uint64_t m = t0; m < (1ull << 23); m += stride) {
+    const float b = __uint_as_float(0x3f800000u | static_cast<uint32_t>(m));
+    const float y0 = __builtin_amdgcn_rcpf(b);
+    const float y = __builtin_fmaf(__builtin_fmaf(-b, y0, 1.0f), y0, y0);
+    bad_r += __float_as_uint(y) != __float_as_uint(1.0f / b) ? 1u : 0u;
+  }
+  for (uint64_t i = t0; i < n; i += stride) {
+    const uint32_t h1 = check_hash(static_cast<uint32_t>(i) ^ check_hash(static_cast<uint32_t>(i >> 32) + seed));
+    const uint32_t h2 = check_hash(h1 ^ 0x85ebca6bu);
+    const uint32_t h3 = check_hash(h2 ^ 0xc2b2ae35u);
+    const int ea = static_cast<int>(h3 % 41u) - 20;
+    const int eb = static_cast<int>((h3 >> 16) % 41u) - 20;
+    const float a = ldexpf(__uint_as_float(0x3f800000u | (h1 >> 9)), ea);
+    const float b = ldexpf(__uint_as_float(0x3f800000u | (h2 >> 9)), eb);
+    bad_q += __float_as_uint(DevDiv::div(a, b)) != __float_as_uint(a / b) ? 1u : 0u;
+  }
+  if (bad_r) atomicAdd(counts, bad_r);
+  if (bad_q) atomicAdd(counts + 1, bad_q);
+}
+
 hipError_t device_info(int& cus) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1342,6 +1405,15 @@ hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
     done += q.n;
   }
   return hipSuccess;
+}
+
+hipError_t launch_check_division(uint64_t n, uint32_t seed, unsigned long long* counts, hipStream_t stream) {
+  int cus = 0;
+  hipError_t e = device_info(cus);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(check_division_kernel, dim3(static_cast<unsigned>(cus) * 16u), dim3(kBlock), 0, stream, n,
+                     seed, counts);
+  return hipGetLastError();
 }
 
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {

@@ -337,6 +337,21 @@ def test_large_grid_index_paths():
     H.compare_sinograms(g, o, g["records"], o["records"], same)
 
 
+def test_device_division_is_correctly_rounded():
+    """The transport's device division (refined reciprocal, one remainder
+    correction) equals the IEEE quotient: its reciprocal is the correctly
+    rounded 1/b for every significand, and 2^31 hashed quotients match."""
+    case = H.case_from("tiny")
+    ctx = sse.Context(case.scanner, case.sino, case.physics)
+    try:
+        for seed in (1, 2):
+            r, q = ctx.check_division(1 << 30, seed)
+            say(f"[division] seed {seed}: reciprocal mismatches {r} of 2^23, quotient mismatches {q} of 2^30")
+            assert r == 0 and q == 0
+    finally:
+        ctx.close()
+
+
 def test_point_source_and_all_ones_lut():
     w = W.WORKLOADS["tiny"]
     ones_case = H.case_from("tiny")
