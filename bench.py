@@ -295,6 +295,9 @@ def main():
     ap.add_argument("--copy-bytes", type=float, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the second timing with pair pruning (photon B not tracked once photon A "
+                         "missed the energy window; identical sinograms)")
 
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -387,6 +390,26 @@ def main():
     dt = time.perf_counter() - t0
     scatter_per_step = int(out["scatter_counts"].sum(dtype=torch.int64))
     kernel_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+    pruned = None
+    if not args.no_pruned:
+        # The same steps with pair pruning, reported beside the headline (which
+        # tracks both photons of every history): same histories, same sinograms.
+        ctx.set_pair_pruning(True)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i)
+            log(f"[bench] pruned step {i + 1}/{args.steps} queued")
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        pruned_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+        ctx.set_pair_pruning(False)
+        pruned = {"value": n * args.steps / dtp, "ms_per_step": dtp / args.steps * 1e3,
+                  "simulate_ms": float(np.mean(pruned_ms)),
+                  "same_scatter_counts": int(out["scatter_counts"].sum(dtype=torch.int64)) == scatter_per_step,
+                  "note": "photon B not tracked when photon A ended outside the energy window"}
     next1 = smoothing_normalisation_timing(ctx, out["scatter_weights"], scale, final, stream)
     ctx.close()
 
@@ -423,6 +446,7 @@ def main():
                    "accumulation": "f64"},
         "scatter_coincidences_per_sec": scatter_per_step * args.steps / dt,
         "smoothing_normalisation": next1,
+        "pair_pruning": pruned,
         "simulate_ms": float(np.mean(kernel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,

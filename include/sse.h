@@ -327,6 +327,19 @@ sse_status sse_load_sensitivity(sse_ctx* ctx, const float* sens, int has_tof_axi
 sse_status sse_simulate(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
                         uint64_t h_offset, const sse_outputs* out, void* stream);
 
+/* Pair pruning (enable = 1; off after sse_create): photon B of a history is
+ * not tracked when photon A ended outside the energy window (not detected,
+ * or detected outside [e_lo, e_hi]).  Such a history adds to no sinogram
+ * whatever photon B does, and every history keeps its own random stream, so
+ * counts are unchanged bit for bit and weights up to the order of their
+ * binary64 sums.  A history then costs about half the transport work when
+ * A misses.  Calls that collect statistics or per-history records track
+ * both photons whatever this setting, since both describe photon B.  Applies
+ * to sse_simulate and to the requests of servers started afterwards.
+ * Errors: SSE_EINVAL (enable not 0 or 1), SSE_EBUSY while a server runs on
+ * the context. */
+sse_status sse_set_pair_pruning(sse_ctx* ctx, int enable);
+
 /* Expected annihilations per simulated history: sum(activity) * voxel volume
  * (ml) * acq_seconds * factor / n_histories (binary64).  The simulator's
  * output is absolutely scaled (Discussion); `factor` carries a global

@@ -121,6 +121,7 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
     p.edge_na = c->gaps.edge_n_angle;
     p.edge_np = c->gaps.edge_n_pos;
   }
+  p.prune_b = c->prune_b;
   p.seed = seed;
   p.h0 = h0;
   p.rec_h0 = h0;
@@ -685,6 +686,14 @@ sse_status sse_load_sensitivity(sse_ctx* c, const float* sens, int has_tof_axis,
   }
   c->d_sens = d;
   c->sens_tof = has_tof_axis ? 1 : 0;
+  return SSE_OK;
+}
+
+sse_status sse_set_pair_pruning(sse_ctx* c, int enable) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  if (enable != 0 && enable != 1) return fail(SSE_EINVAL, "enable must be 0 or 1");
+  if (sse_status st = refuse_while_serving(c, "cannot change pair pruning"); st != SSE_OK) return st;
+  c->prune_b = enable;
   return SSE_OK;
 }
 

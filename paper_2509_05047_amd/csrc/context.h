@@ -58,6 +58,10 @@ struct sse_ctx {
   sse_gap_desc gaps{};
   float* d_edge[2] = {nullptr, nullptr};
   int sens_tof = 0;
+  // photon B is not tracked when photon A ended outside the energy window
+  // (the sinograms do not change; calls that collect statistics or records
+  // always track both photons)
+  int prune_b = 0;
   float* d_scratch[2] = {nullptr, nullptr};
   // pair buffer of the transport -> coincidence hand-over (kPairWords words
   // per pair), its counter, and an event after its last use so that a call

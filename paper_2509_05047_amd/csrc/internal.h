@@ -94,6 +94,9 @@ struct TransportParams {
   const float* edge_t;
   const float* edge_a;
   int edge_na, edge_np;
+  // photon B of a history is not tracked when photon A ended outside the
+  // energy window (production instantiation only)
+  int prune_b;
   // run
   uint64_t seed, h0, n;
   // outputs

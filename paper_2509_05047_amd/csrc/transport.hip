@@ -1111,17 +1111,26 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           stash[64u * kSPath + lane] = __float_as_uint(path);
           stash[64u * kSEbin + lane] = ebin;
         }
-        // photon B: back to back with A
-        side = 1;
-        px = ex; py = ey; pz = ez;
-        dx = -edx; dy = -edy; dz = -edz;
-        t = 0.0f; len = 0.0f;
-        texit = texit_b;
-        ec = p.e511;
-        nC = nR = nint = 0;
-        steps = 0;
-        fate = kEscaped;
-        phase = kTrack;
+        if (!kInstr && p.prune_b && !win) {
+          // Photon A ended outside the energy window: the history adds to
+          // no sinogram whatever photon B does, so with pruning on B is not
+          // tracked and the lane takes the next history.  (The instrumented
+          // instantiation, whose statistics and records describe photon B,
+          // always tracks it.)
+          phase = kEmit;
+        } else {
+          // photon B: back to back with A
+          side = 1;
+          px = ex; py = ey; pz = ez;
+          dx = -edx; dy = -edy; dz = -edz;
+          t = 0.0f; len = 0.0f;
+          texit = texit_b;
+          ec = p.e511;
+          nC = nR = nint = 0;
+          steps = 0;
+          fate = kEscaped;
+          phase = kTrack;
+        }
       } else {
         // ---------------- coincidence -------------------------------------
         // Not both detected (outcome 2) or not both in the window (3) is

@@ -132,3 +132,7 @@ def test_edge_lut_rejects_bad_geometry(bad):
     with pytest.raises(sse.SseError) as e:
         sse.build_edge_lut(g)
     assert e.value.status == sse.EINVAL
+
+
+def test_pair_pruning_rejects_null_context():
+    assert sse.lib().sse_set_pair_pruning(None, 1) == sse.EINVAL

@@ -187,14 +187,66 @@ def test_full_size_clinical_sampled_histories():
     ctx, pid = H.open_context(case)
     try:
         prod = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        ctx.set_pair_pruning(True)
+        pruned = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
     finally:
         ctx.close()
-    say(f"[full] production {w.n_histories / prod['seconds']:.3e} histories/s")
-    for c, wt in (("scatter_counts", "scatter_weights"), ("true_counts", "true_weights")):
-        assert np.array_equal(prod[c], g[c]), c
-        nz = g[wt] != 0
-        assert np.array_equal(prod[wt] != 0, nz)
-        assert np.max(np.abs(prod[wt][nz] - g[wt][nz]) / g[wt][nz]) < 1e-12
+    say(f"[full] production {w.n_histories / prod['seconds']:.3e} histories/s, "
+        f"with pair pruning {w.n_histories / pruned['seconds']:.3e}")
+    for run in (prod, pruned):
+        for c, wt in (("scatter_counts", "scatter_weights"), ("true_counts", "true_weights")):
+            assert np.array_equal(run[c], g[c]), c
+            nz = g[wt] != 0
+            assert np.array_equal(run[wt] != 0, nz)
+            assert np.max(np.abs(run[wt][nz] - g[wt][nz]) / g[wt][nz]) < 1e-12
+
+
+@pytest.mark.parametrize("policy", [None, "discard", "edge_lut"])
+def test_pair_pruning_keeps_sinograms(policy):
+    """Pair pruning (photon B not tracked once photon A ended outside the
+    energy window): the production kernel's sinograms equal the oracle's
+    full simulation of every history (counts bit for bit, weights within
+    the bar), with and without gaps and with TOF jitter, so that the
+    coincidence draws continue the stream where photon B left it; the
+    instrumented launch still tracks both photons."""
+    w = W.WORKLOADS["tiny"]
+    case = H.case_from("tiny", tof_sigma=15.0)
+    if policy is not None:
+        case = H.with_gaps(case, W.TINY_GAPS, policy)
+    o = H.run_oracle(case, w.n_histories, w.seed)
+    ctx, pid = H.open_context(case)
+    try:
+        full = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        ctx.set_pair_pruning(True)
+        pruned = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        inst = H.run_gpu(ctx, pid, w.n_histories, w.seed, record_stride=1)
+        ctx.set_pair_pruning(False)
+        again = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+    finally:
+        ctx.close()
+    same = H.identical_mask(inst["records"], o["records"])
+    assert same.all(), H.describe_mismatch(inst["records"], o["records"])
+    stats_match(inst["stats"], o["stats"])
+    for run in (full, pruned, again):
+        H.compare_sinograms(run, o, o["records"], o["records"], same)
+    assert np.array_equal(pruned["scatter_counts"], full["scatter_counts"])
+    assert int(o["scatter_counts"].sum()) > 0 and int(o["true_counts"].sum()) > 0
+    say(f"[pruning] gaps {policy}: {int(o['scatter_counts'].sum())} scatter, "
+        f"{int(o['true_counts'].sum())} true coincidences, "
+        f"{o['stats']['in_window'] / w.n_histories:.3f} singles in the window per history")
+
+
+def test_pair_pruning_argument_checks():
+    case = H.case_from("tiny")
+    ctx, pid = H.open_context(case)
+    try:
+        lib = sse.lib()
+        assert lib.sse_set_pair_pruning(ctx._h, 2) == 1  # SSE_EINVAL
+        assert lib.sse_set_pair_pruning(None, 1) == 1
+        assert lib.sse_set_pair_pruning(ctx._h, 1) == 0
+        assert lib.sse_set_pair_pruning(ctx._h, 0) == 0
+    finally:
+        ctx.close()
 
 
 def test_split_runs_sum_to_whole_run_and_repeat():

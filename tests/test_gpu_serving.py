@@ -141,6 +141,31 @@ def test_gap_model_requests_alone_and_in_the_mix():
     ctx.close()
 
 
+def test_pair_pruning_requests_match_full_tracking():
+    """With pair pruning on, the server's requests get the sinograms that
+    sse_simulate gives them alone with both photons of every history
+    tracked."""
+    ctx, pids = tiny_ctx()
+    reqs = [(pids[0], 3_000_000, 31, 0), (pids[1], 170_000, 32, 0), (pids[2], 90_000, 33, 0)]
+    ref = [alone(ctx, *r) for r in reqs]
+    ctx.set_pair_pruning(True)
+    srv = sse.Server(ctx, max_active=4, tick_histories=1_000_000, chunk_histories=4096)
+    ids = [srv.submit(pid, n, seed, h_offset=h0) for pid, n, seed, h0 in reqs]
+    results = {}
+
+    def on_done(c):
+        assert c["status"] == sse.REQ_DONE
+        results[c["id"]] = fetch(ctx, c)
+        srv.release(c["id"])
+
+    drain(srv, len(reqs), on_done)
+    srv.stop()
+    for rid, r in zip(ids, ref):
+        same(results[rid], r)
+    assert int(ref[0][0].sum()) > 0
+    ctx.close()
+
+
 def test_context_tables_are_locked_while_serving():
     """Calls that would replace or free device tables a running server's
     requests read are refused with SSE_EBUSY until the server stops."""
@@ -151,7 +176,7 @@ def test_context_tables_are_locked_while_serving():
     try:
         for call in (lambda: ctx.load_lut(ld, lut), lambda: ctx.set_gaps(None),
                      lambda: ctx.update_activity(pids[0], W.tiny_cylinder()[2]),
-                     lambda: ctx.unload_phantom(pids[2])):
+                     lambda: ctx.unload_phantom(pids[2]), lambda: ctx.set_pair_pruning(True)):
             with pytest.raises(sse.SseError) as e:
                 call()
             assert e.value.status == sse.EBUSY
