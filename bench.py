@@ -136,6 +136,7 @@ def large_loop(args):
     lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
     sens = W.make_sensitivity(w.sino, seed=3, tof_axis=True)
     ctx = sse.Context(w.scanner, w.sino, w.physics)
+    ctx.set_pair_pruning(args.pair_pruning)
     pid = ctx.load_phantom(pdesc, mu, acts[0])
     ctx.load_lut(lut_desc, lut)
     ctx.load_sensitivity(sens, has_tof_axis=True)
@@ -177,7 +178,7 @@ def large_loop(args):
         "config": {"workload": f"large loop: {pdesc.nx}x{pdesc.ny}x{pdesc.nz} phantom of 1.17 mm voxels, "
                                f"{reqs} requests x {n} histories with updated activity, fused "
                                f"scale/smooth(sigma {sigma} bins)/sensitivity finalize",
-                   "histories_per_step": n},
+                   "histories_per_step": n, "pair_pruning": bool(args.pair_pruning)},
         "request_latency_ms": lat,
         "request_latency_p50_ms": float(np.percentile(lat, 50)),
         "simulate_ms": float(np.mean([t[1] for t in timing])),
@@ -198,6 +199,7 @@ def serving(args):
     import paper_2509_05047_amd as sse
     w = W.WORKLOADS["clinical"]
     ctx = sse.Context(w.scanner, w.sino, w.physics)
+    ctx.set_pair_pruning(args.pair_pruning)
     lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
     ctx.load_lut(lut_desc, lut)
     n_pool = 12
@@ -264,7 +266,7 @@ def serving(args):
         "config": {"workload": f"serving: {nreq} Poisson requests at load {args.load} of single-stream "
                                f"throughput, budgets log-uniform 1e7-5e8, {n_pool} body phantoms "
                                "(64^3 / 128^3 / 192x192x89), Signa scanner, 357x224x89x29 sinogram",
-                   "histories_total": hist},
+                   "histories_total": hist, "pair_pruning": bool(args.pair_pruning)},
         "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
         "latency_max_ms": float(lat.max()), "single_stream_histories_per_sec": single,
         "arrival_rate_per_sec": lam, "max_active_seen": st["max_active_seen"], "ticks": st["ticks"],
@@ -295,6 +297,8 @@ def main():
     ap.add_argument("--copy-bytes", type=float, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pair-pruning", action="store_true",
+                    help="large and serving workloads: pair pruning on (both photons are tracked by default)")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the second timing with pair pruning (photon B not tracked once photon A "
                          "missed the energy window; identical sinograms)")
