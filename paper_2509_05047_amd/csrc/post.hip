@@ -64,10 +64,10 @@ __device__ __forceinline__ float load_in(const SmoothArgs& a, uint64_t i) {
   return v;
 }
 
-// n inputs of one thread (index idx[b] where ok[b]; 0, which every array
-// holds, elsewhere), 0 where not ok: all input loads issued unconditionally,
-// then all normalisation loads, then the products and selects, so that no
-// wait falls between two loads.
+// n inputs of one thread, read at idx[b] (an index that is in range even
+// where ok[b] is false) and set to 0 where ok[b] is false: all input loads
+// are issued unconditionally, then all normalisation loads, then the
+// products and selects, so that no wait falls between two loads.
 template <bool kFromF64, int n>
 __device__ __forceinline__ void load_batch(const SmoothArgs& a, const uint64_t* idx, const bool* ok, float* v) {
 #pragma unroll
@@ -123,11 +123,12 @@ constexpr int kLoadBatch = 16;
 // a tile of a.tile_len positions along the axis (plus the kernel's halo) by
 // kTC consecutive radial columns in LDS -- every input read once, in
 // 256-byte rows, one wavefront per row -- and computes the tile's outputs
-// from LDS.  The tile (dynamic LDS) is sized by the radius: the launch picks
-// the longest tile_len <= 128 whose tile fits kColTileBytes (three blocks
-// per CU at least; four or more for the finalize's radii).  Views are periodic over 180
-// degrees, and past the seam the same LOR is seen from the other end (radial
-// and TOF indices reversed); planes reflect at the ends.
+// from LDS.  The tile (dynamic LDS) is sized by the radius: the launch
+// picks the longest tile_len <= 128 whose tile fits kColTileBytes (three
+// blocks per CU at least; four or more for the finalize's radii).  Views
+// are periodic over 180 degrees, and past the seam the same LOR is seen
+// from the other end (radial and TOF indices reversed); planes reflect at
+// the ends.
 constexpr int kTC = 64;
 constexpr int kMaxTileLen = 128;
 constexpr size_t kColTileBytes = 48 * 1024;
