@@ -1134,11 +1134,15 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       } else {
         // ---------------- coincidence -------------------------------------
         // Not both detected (outcome 2) or not both in the window (3) is
-        // decided here; pairs in the window go to the queue.
+        // decided here; pairs in the window go to the queue -- in the
+        // production instantiation without a trues sinogram, only the
+        // scattered ones (an unscattered pair would add to nothing, and each
+        // pair draws its coincidence numbers from its own stream).
         const bool scattered = a_scat || (nC + nR) > 0;
         const bool both = a_win && win;
-        const uint64_t bm = __ballot(both);
-        if (both) {
+        const bool queued = both && (kInstr || scattered || p.tr_n != nullptr);
+        const uint64_t bm = __ballot(queued);
+        if (queued) {
           const uint64_t slot = res_next + static_cast<uint64_t>(__popcll(bm & below));
           if (slot < p.pair_cap) {  // always, by the launch size; a guard for the memory
             uint4* w = reinterpret_cast<uint4*>(p.pairs + slot * kPairWords);
@@ -1150,7 +1154,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
             w[4] = make_uint4(__float_as_uint(dy), __float_as_uint(dz), __float_as_uint(path), ebin);
           }
         }
-        pushed = both;
+        pushed = queued;
         SSE_COUNT(kStHist, true);
         if (kInstr && p.stats) atomicAdd(&s_stats[kStRngBlocks], blocks_used(r.blk * 4u - r.left));
         SSE_COUNT(kStRejWindow, a_det && det && !both);

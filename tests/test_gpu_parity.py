@@ -187,14 +187,19 @@ def test_full_size_clinical_sampled_histories():
     ctx, pid = H.open_context(case)
     try:
         prod = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        # the benchmark's launch: scatter sinogram only
+        bench_like = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False, trues=False)
         ctx.set_pair_pruning(True)
         pruned = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
     finally:
         ctx.close()
     say(f"[full] production {w.n_histories / prod['seconds']:.3e} histories/s, "
+        f"scatter only {w.n_histories / bench_like['seconds']:.3e}, "
         f"with pair pruning {w.n_histories / pruned['seconds']:.3e}")
-    for run in (prod, pruned):
+    for run in (prod, bench_like, pruned):
         for c, wt in (("scatter_counts", "scatter_weights"), ("true_counts", "true_weights")):
+            if run.get(c) is None:
+                continue
             assert np.array_equal(run[c], g[c]), c
             nz = g[wt] != 0
             assert np.array_equal(run[wt] != 0, nz)
@@ -204,11 +209,12 @@ def test_full_size_clinical_sampled_histories():
 @pytest.mark.parametrize("policy", [None, "discard", "edge_lut"])
 def test_pair_pruning_keeps_sinograms(policy):
     """Pair pruning (photon B not tracked once photon A ended outside the
-    energy window): the production kernel's sinograms equal the oracle's
-    full simulation of every history (counts bit for bit, weights within
-    the bar), with and without gaps and with TOF jitter, so that the
-    coincidence draws continue the stream where photon B left it; the
-    instrumented launch still tracks both photons."""
+    energy window), and production launches without a trues sinogram (which
+    queue only scattered pairs): the sinograms equal the oracle's full
+    simulation of every history (counts bit for bit, weights within the
+    bar), with and without gaps and with TOF jitter, so that the coincidence
+    draws continue the stream where photon B left it; the instrumented
+    launch still tracks both photons."""
     w = W.WORKLOADS["tiny"]
     case = H.case_from("tiny", tof_sigma=15.0)
     if policy is not None:
@@ -217,8 +223,12 @@ def test_pair_pruning_keeps_sinograms(policy):
     ctx, pid = H.open_context(case)
     try:
         full = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        # without a trues sinogram the production launch queues only the
+        # scattered pairs
+        scatter_only = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False, trues=False)
         ctx.set_pair_pruning(True)
         pruned = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
+        pruned_scatter_only = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False, trues=False)
         inst = H.run_gpu(ctx, pid, w.n_histories, w.seed, record_stride=1)
         ctx.set_pair_pruning(False)
         again = H.run_gpu(ctx, pid, w.n_histories, w.seed, stats=False)
@@ -227,8 +237,9 @@ def test_pair_pruning_keeps_sinograms(policy):
     same = H.identical_mask(inst["records"], o["records"])
     assert same.all(), H.describe_mismatch(inst["records"], o["records"])
     stats_match(inst["stats"], o["stats"])
-    for run in (full, pruned, again):
+    for run in (full, scatter_only, pruned, pruned_scatter_only, again):
         H.compare_sinograms(run, o, o["records"], o["records"], same)
+    assert scatter_only.get("true_counts") is None
     assert np.array_equal(pruned["scatter_counts"], full["scatter_counts"])
     assert int(o["scatter_counts"].sum()) > 0 and int(o["true_counts"].sum()) > 0
     say(f"[pruning] gaps {policy}: {int(o['scatter_counts'].sum())} scatter, "
