@@ -300,6 +300,18 @@ def test_results_do_not_depend_on_statistics_output():
         ctx.close()
 
 
+@pytest.mark.parametrize("h_offset", [(1 << 32) - 40_000, (1 << 40) + 12_345, (1 << 63) - 100_003])
+def test_history_indices_beyond_32_bits(h_offset):
+    """History indices whose upper 32 bits are not zero (the second counter
+    word of the stream), a range that crosses 2^32, and the top of the index
+    range: every history identical to the oracle's."""
+    case = H.case_from("tiny", tof_sigma=15.0)
+    g, o, same = check_case(case, 100_003, 4242, h_offset=h_offset)
+    assert same.all()
+    H.compare_sinograms(g, o, g["records"], o["records"], same)
+    stats_match(g["stats"], o["stats"])
+
+
 def test_edge_cases():
     case = H.case_from("tiny")
     ctx, pid = H.open_context(case)
