@@ -243,15 +243,16 @@ def serving(args):
         pd, mu, act = W.serving_phantom(k)
         pids.append(ctx.load_phantom(pd, mu, act))
     log(f"[bench] serving: {n_pool} resident phantoms")
-    # single-stream throughput on the pool (sets the arrival rate)
-    out = ctx.new_outputs(stats=False)
+    # single-stream throughput over the whole pool, with the requests'
+    # outputs (scatter sinogram only): sets the arrival rate
+    out = ctx.new_outputs(trues=False, stats=False)
     ctx.simulate(pids[0], 10_000_000, 1, out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     probe = 0
-    for k in range(3):
-        ctx.simulate(pids[k], 100_000_000, 2, out)
-        probe += 100_000_000
+    for k in range(n_pool):
+        ctx.simulate(pids[k], 50_000_000, 2, out)
+        probe += 50_000_000
     torch.cuda.synchronize()
     single = probe / (time.perf_counter() - t0)
     del out

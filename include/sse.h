@@ -430,7 +430,8 @@ typedef struct {
   int32_t reserved;
   uint64_t hbm_budget_bytes;   /* cap on library-allocated output buffers; 0 = 90 % of free device memory */
   uint64_t tick_histories;     /* histories per tick over all active requests; 0 = 32 Mi */
-  uint64_t chunk_histories;    /* histories per work-list sub-chunk (<= 2^31); 0 = about 8 per resident wave per tick */
+  uint64_t chunk_histories;    /* histories per work-list sub-chunk (<= 2^31; the kernel balances its launches by
+                                  claiming 256 histories at a time); 0 = a sixteenth of a tick, at least 256 */
 } sse_server_cfg;
 
 typedef struct {

@@ -211,12 +211,17 @@ struct WorkChunk {
   uint32_t item;
 };
 
+// Histories per claim of the work-list kernel; each chunk of a launch takes
+// its length rounded up to a multiple of this in the claim positions.
+constexpr uint32_t kBatchSlice = 256;
+
 // A list of sub-chunks over several requests, simulated by one launch.
 struct BatchParams {
   const TransportParams* items;  // device array, one per request slot
   const WorkChunk* chunks;       // device array
   uint32_t n_chunks;
-  uint32_t* counter;             // device, reset by the launcher
+  uint32_t n_positions;          // sum of the chunks' lengths rounded up to multiples of kBatchSlice
+  uint32_t* counter;             // device claim cursor (positions), reset by the launcher
   uint64_t n_histories;          // sum of the chunks' lengths
   uint32_t* pairs;               // the items' common pair buffer
   uint32_t* pair_count;

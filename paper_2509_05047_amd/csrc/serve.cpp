@@ -22,7 +22,10 @@ using namespace sse_detail;
 namespace {
 
 constexpr uint64_t kDefaultTick = 32ull << 20;
-constexpr uint64_t kChunksPerWave = 8;  // default chunk size: ~8 sub-chunks per resident wave per tick
+// Default sub-chunk size: about this many sub-chunks per tick.  The kernel
+// balances a launch by claiming kBatchSlice histories at a time, so
+// sub-chunks only split requests to fit launches.
+constexpr uint64_t kChunksPerTick = 16;
 constexpr int kInFlight = 2;  // ticks queued on the device at once
 
 struct Buffer {
@@ -275,14 +278,18 @@ void scheduler(sse_server* s) {
     // segments of whole chunks of at most pair_cap histories
     for (uint32_t c0 = 0; c0 < nc && e == hipSuccess;) {
       uint32_t c1 = c0;
-      uint64_t hist = 0;
-      while (c1 < nc && hist + list[c1].n <= s->segment_histories) hist += list[c1++].n;
+      uint64_t hist = 0, positions = 0;
+      while (c1 < nc && hist + list[c1].n <= s->segment_histories) {
+        hist += list[c1].n;
+        positions += (list[c1].n + sse::kBatchSlice - 1) / sse::kBatchSlice * sse::kBatchSlice;
+        ++c1;
+      }
       if (c1 == c0) {  // a chunk larger than the buffer: excluded at start-up
         e = hipErrorInvalidValue;
         break;
       }
-      sse::BatchParams b{s->d_items, s->d_chunks[s->parity] + c0, c1 - c0, s->d_counter,
-                         hist, s->d_pairs, s->d_pair_count, s->pair_cap, s->ctx->gaps_on};
+      sse::BatchParams b{s->d_items, s->d_chunks[s->parity] + c0, c1 - c0, static_cast<uint32_t>(positions),
+                         s->d_counter, hist, s->d_pairs, s->d_pair_count, s->pair_cap, s->ctx->gaps_on};
       e = sse::launch_transport_batch(b, s->stream);
       c0 = c1;
     }
@@ -328,13 +335,7 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
   s->cfg = *cfg;
   if (!s->cfg.tick_histories) s->cfg.tick_histories = kDefaultTick;
   if (!s->cfg.chunk_histories) {
-    // several sub-chunks per resident wavefront and tick, so no wave idles
-    // while others finish the tick
-    int dev = 0, cus = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t waves = static_cast<uint64_t>(cus > 0 ? cus : 1) * 12;  // 3 waves per SIMD
-    uint64_t chunk = s->cfg.tick_histories / (waves * kChunksPerWave);
+    uint64_t chunk = s->cfg.tick_histories / kChunksPerTick;
     chunk = std::max<uint64_t>(256, chunk / 64 * 64);
     s->cfg.chunk_histories = chunk;
   }

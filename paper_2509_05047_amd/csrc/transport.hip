@@ -761,16 +761,24 @@ __device__ __forceinline__ void pad_pairs(const TransportParams& p, uint64_t fro
 // (in LDS) when p.mu8 is set; s_stats the block's statistics counters (used
 // only when kInstr); stash the wavefront's LDS area for photon A's hit data
 // (kSingleWords columns of 64 lanes); eq its emission queue (kEmitWords
-// columns).
+// columns).  With kExtends, more(next, end), called converged whenever the
+// range is used up, may give the wavefront a further range of histories
+// with the same parameters (the lanes then go on without draining); it
+// leaves next >= end when there is none.
 // The palette pointer is typed as LDS so that its reads are LDS reads even
 // where the compiler merges them with the binary32-map path.
 typedef const __attribute__((address_space(3))) float LdsFloat;
 
-template <bool kInstr>
-__device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, const uint64_t end,
+// The range of a single-stream launch: nothing beyond [next, end).
+struct NoMore {
+  __device__ void operator()(uint64_t&, uint64_t&) const {}
+};
+
+template <bool kInstr, bool kExtends, class More>
+__device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, uint64_t end,
                                               unsigned long long* s_stats, LdsFloat* mu_tab,
                                               LdsWord* stash, LdsWord* rng_buf, LdsWord* eq,
-                                              uint64_t& res_next, uint64_t& res_end) {
+                                              uint64_t& res_next, uint64_t& res_end, More&& more) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   const uint64_t below = (1ull << lane) - 1ull;
@@ -847,7 +855,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       const uint32_t got = want < qn - qhead ? want : qn - qhead;
       if (phase == kEmit && rank < got) take_emission(qhead + rank);
       qhead += got;
-      if (want > got) {
+      if (want > got && !kExtends) {
         if (qnext < end) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -861,6 +869,31 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (phase == kEmit && rank >= got && rank - got < qn) take_emission(rank - got);
           qhead = want - got < qn ? want - got : qn;
+        }
+        if (phase == kEmit) phase = kDone;  // no history left for this lane
+      } else if (want > got) {
+        // Refill rounds, extending the range, until every waiting lane has a
+        // history or none is left (each round serves at least one lane, or
+        // ends the loop).
+        uint32_t given = got;
+        for (;;) {
+          if (qnext >= end) more(qnext, end);
+          if (qnext >= end) break;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          emit_to_queue(p, qnext + lane, eq);
+          qbase = qnext;
+          qn = end - qnext < 64u ? static_cast<uint32_t>(end - qnext) : 64u;
+          qnext += qn;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const uint32_t take = want - given < qn ? want - given : qn;
+          if (phase == kEmit && rank >= given && rank - given < take) take_emission(rank - given);
+          qhead = take;
+          given += take;
+          if (given == want) break;
         }
         if (phase == kEmit) phase = kDone;  // no history left for this lane
       }
@@ -1197,9 +1230,9 @@ transport_kernel(TransportParams p) {
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
   __syncthreads();
   uint64_t res_next = 0, res_end = 0;
-  run_histories<kInstr>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), (LdsWord*)(s_stash[threadIdx.x >> 6]),
+  run_histories<kInstr, false>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), (LdsWord*)(s_stash[threadIdx.x >> 6]),
                         (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next,
-                        res_end);
+                        res_end, NoMore{});
   pad_pairs(p, res_next, res_end);
   if (kInstr) {
     __syncthreads();
@@ -1208,9 +1241,18 @@ transport_kernel(TransportParams p) {
   }
 }
 
-// Work-list form for the request server: wavefronts claim sub-chunks
-// (request, history range) from a device counter until the list is
-// exhausted; each sub-chunk carries its own request's parameters.  The
+typedef const __attribute__((address_space(4))) WorkChunk ConstChunk;
+typedef const __attribute__((address_space(4))) TransportParams ConstParams;
+
+// Work-list form for the request server.  The launch's chunks (request,
+// history range) are laid end to end, each padded to a multiple of
+// kBatchSlice, and wavefronts claim slices of kBatchSlice positions from a
+// device cursor until it passes the end; a slice lies in one chunk, so it
+// carries that request's parameters.  A wavefront whose range runs out
+// claims the next slice at once: one of the same request extends the range
+// and the lanes go on without draining; one of another request waits until
+// the lanes have finished (the parameters are wave-uniform).  The small
+// slices balance the launch's end, at one drain per request change.  The
 // palette table is per wavefront because neighbouring wavefronts may work
 // on different requests.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTransportWavesPerEu)))
@@ -1223,24 +1265,70 @@ transport_batch_kernel(BatchParams b) {
   float* tab = s_tab[threadIdx.x >> 6];
   uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
   const TransportParams* last = nullptr;
-  for (;;) {
-    uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(b.counter, 1u);
-    c = __builtin_amdgcn_readfirstlane(__shfl(c, 0, 64));
-    if (c >= b.n_chunks) break;
-    const WorkChunk ch = b.chunks[c];
-    const TransportParams& p = b.items[ch.item];
+  // The next slice (converged call): its request and histories in ch;
+  // false once the cursor has passed the end.  Positions only grow for one
+  // wavefront, so the chunk it falls in is found by walking forward from
+  // the last one (ci, starting at position cstart).
+  uint32_t ci = 0;
+  uint64_t cstart = 0;
+  // The list and the requests' parameters are read through the constant
+  // address space (the host wrote them before the launch) with wave-uniform
+  // indices, so that their loads are scalar loads the compiler may keep or
+  // repeat; through generic pointers they were vector loads in the
+  // transport loop.
+  const ConstChunk* chunks = (const ConstChunk*)(b.chunks);
+  const ConstParams* items = (const ConstParams*)(b.items);
+  auto claim = [&](WorkChunk& ch) -> bool {
+    uint32_t pos = 0;
+    if (lane == 0) pos = atomicAdd(b.counter, kBatchSlice);
+    pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));
+    if (pos >= b.n_positions) return false;
+    for (;;) {
+      if (ci >= b.n_chunks) return false;  // only if n_positions overstates the list
+      const uint64_t len = (static_cast<uint64_t>(chunks[ci].n) + kBatchSlice - 1) / kBatchSlice * kBatchSlice;
+      if (pos < cstart + len) break;
+      cstart += len;
+      ++ci;
+    }
+    const WorkChunk c = {chunks[ci].h0, chunks[ci].n, chunks[ci].item};
+    const uint64_t off = pos - cstart;  // a multiple of kBatchSlice below c.n
+    ch.item = c.item;
+    ch.h0 = c.h0 + off;
+    ch.n = static_cast<uint32_t>(c.n - off < kBatchSlice ? c.n - off : kBatchSlice);
+    return true;
+  };
+  WorkChunk cur;
+  bool have = claim(cur);
+  while (have) {
+    const TransportParams& p = *(const TransportParams*)(items + __builtin_amdgcn_readfirstlane(cur.item));
     if (p.mu8) {
       for (uint32_t i = lane; i < 256u; i += 64u) tab[i] = p.mu_table[i];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    run_histories<false>(p, ch.h0, ch.h0 + ch.n, nullptr, (LdsFloat*)(tab), (LdsWord*)(s_stash[threadIdx.x >> 6]),
-                         (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next,
-                         res_end);
+    WorkChunk held;
+    bool holding = false, used_up = false;
+    auto more = [&](uint64_t& next, uint64_t& end) {
+      if (holding || used_up) return;
+      WorkChunk ch;
+      if (!claim(ch)) {
+        used_up = true;
+      } else if (ch.item == cur.item) {
+        next = ch.h0;
+        end = ch.h0 + ch.n;
+      } else {
+        held = ch;
+        holding = true;
+      }
+    };
+    run_histories<false, true>(p, cur.h0, cur.h0 + cur.n, nullptr, (LdsFloat*)(tab),
+                               (LdsWord*)(s_stash[threadIdx.x >> 6]), (LdsWord*)(s_rng[threadIdx.x >> 6]),
+                               (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next, res_end, more);
     last = &p;
     __builtin_amdgcn_wave_barrier();
+    have = holding;
+    if (holding) cur = held;
   }
   if (last) pad_pairs(*last, res_next, res_end);
 }
@@ -1434,12 +1522,15 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
   if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap ||
       b.n_histories > transport_batch_max_histories(b.pair_cap))
     return hipErrorInvalidValue;
+  if (b.n_positions < b.n_histories ||
+      b.n_positions > b.n_histories + static_cast<uint64_t>(b.n_chunks) * kBatchSlice)
+    return hipErrorInvalidValue;
   int cus = 0;
   hipError_t e = device_info(cus);
   if (e != hipSuccess) return e;
   const uint64_t resident = resident_blocks(transport_batch_kernel);
   if (resident == 0) return hipErrorInvalidDeviceFunction;
-  const uint64_t want = (static_cast<uint64_t>(b.n_chunks) + 3) / 4;  // one chunk per wave at least
+  const uint64_t want = (static_cast<uint64_t>(b.n_positions) / kBatchSlice + 3) / 4;  // a slice per wave at least
   const int grid = static_cast<int>(want < resident ? want : resident);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.pair_count);
