@@ -347,13 +347,18 @@ sse::PostParams post_params(const sse_ctx* c) {
   return sse::PostParams{c->sn.n_rad, c->sn.n_view, c->sn.n_plane, c->sn.n_tof};
 }
 
-// Pair buffer for runs of n histories: the records one launch of n needs,
-// at most 2^25 (2.7 GB; longer runs are split into launches), rounded up to
-// 2^16 and grown when needed (halved down to 2^22 while allocation fails).
+// Pair buffer for runs of n histories: the records one launch of n needs
+// (in either launch form), at most 2^26 (5.4 GB: longer runs are split into
+// launches, and fewer, longer launches lose less to each launch's end),
+// rounded up to 2^16 and grown when needed (halved down to 2^22 while
+// allocation fails); and the work-list scratch of the production path.
 sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
-  constexpr uint64_t kDefaultCap = 1ull << 25;
+  constexpr uint64_t kDefaultCap = 1ull << 26;
   constexpr uint64_t kMinCap = 1ull << 22;
-  const uint64_t want = sse::transport_pairs_needed(n);
+  if (!c->d_item) HIP_TRY(hipMalloc(&c->d_item, sizeof(sse::TransportParams)), "allocate work-list scratch");
+  if (!c->d_chunk) HIP_TRY(hipMalloc(&c->d_chunk, sizeof(sse::WorkChunk)), "allocate work-list scratch");
+  if (!c->d_cursor) HIP_TRY(hipMalloc(&c->d_cursor, sizeof(uint32_t)), "allocate work-list scratch");
+  const uint64_t want = std::max(sse::transport_pairs_needed(n), sse::transport_batch_pairs_needed(n));
   uint64_t cap = want < kDefaultCap ? want : kDefaultCap;
   cap = (cap + 0xffffull) & ~0xffffull;
   if (c->d_pairs && c->pair_cap >= cap) return SSE_OK;
@@ -497,6 +502,9 @@ sse_status sse_destroy(sse_ctx* c) {
   for (auto* s : c->d_scratch)
     if (s) release(s);
   if (c->d_pairs) release(c->d_pairs);
+  if (c->d_item) release(c->d_item);
+  if (c->d_chunk) release(c->d_chunk);
+  if (c->d_cursor) release(c->d_cursor);
   if (c->d_pair_count) release(c->d_pair_count);
   if (c->pair_done) (void)hipEventDestroy(c->pair_done);
   delete c;
@@ -839,7 +847,10 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   p.item = 0;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamWaitEvent(s, c->pair_done, 0), "order the pair buffer");
-  HIP_TRY(sse::launch_transport(p, s), "transport kernel launch");
+  if (p.stats || p.rec)
+    HIP_TRY(sse::launch_transport(p, s), "transport kernel launch");
+  else
+    HIP_TRY(sse::launch_transport_item(p, c->d_item, c->d_chunk, c->d_cursor, s), "transport kernel launch");
   HIP_TRY(hipEventRecord(c->pair_done, s), "record pair-buffer use");
   return SSE_OK;
 }

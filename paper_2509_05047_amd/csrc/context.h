@@ -69,6 +69,11 @@ struct sse_ctx {
   uint32_t* d_pairs = nullptr;
   uint32_t* d_pair_count = nullptr;
   uint64_t pair_cap = 0;
+  // the production simulate's work-list scratch: one parameter set, one
+  // chunk and the claim cursor (ordered like the pair buffer)
+  sse::TransportParams* d_item = nullptr;
+  sse::WorkChunk* d_chunk = nullptr;
+  uint32_t* d_cursor = nullptr;
   hipEvent_t pair_done = nullptr;
   // servers running on this context: their requests hold its device tables,
   // so calls that replace or free them are refused meanwhile

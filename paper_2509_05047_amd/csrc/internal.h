@@ -232,5 +232,12 @@ struct BatchParams {
 // One work list (at most transport_batch_max_histories(pair_cap) histories
 // in all): pair-counter reset, transport, coincidences.
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
+// Histories [p.h0, p.h0 + p.n) of one request through the work-list kernels
+// (the production path of a simulate call: no statistics, no records), in
+// launches of at most transport_batch_max_histories(p.pair_cap) histories;
+// d_item, d_chunk and d_cursor are device scratch of one parameter set, one
+// chunk and one claim cursor.
+hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
+                                 uint32_t* d_cursor, hipStream_t stream);
 
 }  // namespace sse

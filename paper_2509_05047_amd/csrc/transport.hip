@@ -1367,6 +1367,15 @@ __global__ void __launch_bounds__(256) coincidence_batch_kernel(BatchParams b) {
 
 __global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
 
+// One request's parameters and one chunk, stored where the work-list
+// kernels read them by a single thread, so that the store is ordered on the
+// stream with the launches that read it (and with earlier ones still
+// reading the previous values).
+__global__ void store_item_kernel(TransportParams p, WorkChunk c, TransportParams* item, WorkChunk* chunk) {
+  *item = p;
+  *chunk = c;
+}
+
 // Check of DevDiv against the IEEE operator: the refined reciprocal of every
 // significand in [1, 2) (counts[0]: differences from 1 / b), then n quotients
 // of operands with hashed significands and exponents in [-20, 20]
@@ -1504,6 +1513,28 @@ hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
     const hipError_t e = (p.stats || p.rec) ? launch<true>(q, stream) : launch<false>(q, stream);
     if (e != hipSuccess) return e;
     done += q.n;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
+                                 uint32_t* d_cursor, hipStream_t stream) {
+  if (!p.pairs || !p.pair_count || p.pair_cap == 0 || p.pair_cap > kMaxPairCap || !d_item || !d_chunk || !d_cursor)
+    return hipErrorInvalidValue;
+  const uint64_t most = transport_batch_max_histories(p.pair_cap);
+  if (most == 0) return hipErrorInvalidValue;
+  TransportParams q = p;
+  q.item = 0;
+  for (uint64_t done = 0; done < p.n;) {
+    const uint64_t n = p.n - done < most ? p.n - done : most;
+    const WorkChunk ch{p.h0 + done, static_cast<uint32_t>(n), 0u};
+    hipLaunchKernelGGL(store_item_kernel, dim3(1), dim3(1), 0, stream, q, ch, d_item, d_chunk);
+    const uint64_t positions = (n + kBatchSlice - 1) / kBatchSlice * kBatchSlice;
+    const BatchParams b{d_item, d_chunk, 1u, static_cast<uint32_t>(positions), d_cursor, n,
+                        p.pairs, p.pair_count, p.pair_cap, p.gap_on};
+    const hipError_t e = launch_transport_batch(b, stream);
+    if (e != hipSuccess) return e;
+    done += n;
   }
   return hipSuccess;
 }
