@@ -348,12 +348,12 @@ sse::PostParams post_params(const sse_ctx* c) {
 }
 
 // Pair buffer for runs of n histories: the records one launch of n needs
-// (in either launch form), at most 2^26 (5.4 GB: longer runs are split into
+// (in either launch form), at most 2^27 (10.7 GB: longer runs are split into
 // launches, and fewer, longer launches lose less to each launch's end),
 // rounded up to 2^16 and grown when needed (halved down to 2^22 while
 // allocation fails); and the work-list scratch of the production path.
 sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
-  constexpr uint64_t kDefaultCap = 1ull << 26;
+  constexpr uint64_t kDefaultCap = 1ull << 27;
   constexpr uint64_t kMinCap = 1ull << 22;
   if (!c->d_item) HIP_TRY(hipMalloc(&c->d_item, sizeof(sse::TransportParams)), "allocate work-list scratch");
   if (!c->d_chunk) HIP_TRY(hipMalloc(&c->d_chunk, sizeof(sse::WorkChunk)), "allocate work-list scratch");
