@@ -369,9 +369,10 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
   if (e == hipSuccess) e = hipMalloc(&s->d_counter, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_pair_count, sizeof(uint32_t));
   if (e == hipSuccess) {
-    // the records a tick needs (one pair per history at most), up to 2^25
-    // (2.7 GB; longer ticks run in segments), and room for one chunk at least
-    uint64_t cap = std::min<uint64_t>(sse::transport_batch_pairs_needed(s->cfg.tick_histories), 1ull << 25);
+    // the records a tick needs (one pair per history at most), up to 2^27
+    // (10.7 GB; longer ticks run in segments, and each segment ends with a
+    // drain), and room for one chunk at least
+    uint64_t cap = std::min<uint64_t>(sse::transport_batch_pairs_needed(s->cfg.tick_histories), 1ull << 27);
     cap = std::max<uint64_t>(cap, sse::transport_batch_pairs_needed(s->cfg.chunk_histories));
     s->pair_cap = (cap + 0xffffull) & ~0xffffull;
     s->segment_histories = sse::transport_batch_max_histories(s->pair_cap);
