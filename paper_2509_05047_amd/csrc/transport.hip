@@ -1244,10 +1244,11 @@ transport_kernel(TransportParams p) {
 typedef const __attribute__((address_space(4))) WorkChunk ConstChunk;
 typedef const __attribute__((address_space(4))) TransportParams ConstParams;
 
-// Work-list form for the request server.  The launch's chunks (request,
-// history range) are laid end to end, each padded to a multiple of
-// kBatchSlice, and wavefronts claim slices of kBatchSlice positions from a
-// device cursor until it passes the end; a slice lies in one chunk, so it
+// Work-list form: the request server's launches, and the production path of
+// a simulate call (one request, one chunk per launch).  The launch's chunks
+// (request, history range) are laid end to end, each padded to a multiple
+// of kBatchSlice, and wavefronts claim slices of kBatchSlice positions from
+// a device cursor until it passes the end; a slice lies in one chunk, so it
 // carries that request's parameters.  A wavefront whose range runs out
 // claims the next slice at once: one of the same request extends the range
 // and the lanes go on without draining; one of another request waits until
@@ -1272,10 +1273,10 @@ transport_batch_kernel(BatchParams b) {
   uint32_t ci = 0;
   uint64_t cstart = 0;
   // The list and the requests' parameters are read through the constant
-  // address space (the host wrote them before the launch) with wave-uniform
-  // indices, so that their loads are scalar loads the compiler may keep or
-  // repeat; through generic pointers they were vector loads in the
-  // transport loop.
+  // address space (they are written before the launch, by the host or by an
+  // earlier kernel on the stream) with wave-uniform indices, so that their
+  // loads are scalar loads the compiler may keep or repeat; through generic
+  // pointers they would be vector loads inside the transport loop.
   const ConstChunk* chunks = (const ConstChunk*)(b.chunks);
   const ConstParams* items = (const ConstParams*)(b.items);
   auto claim = [&](WorkChunk& ch) -> bool {
