@@ -317,8 +317,10 @@ class Context:
         return (MEM_DEVICE,) + tuple(out)
 
     # -- compute -------------------------------------------------------------
-    def new_outputs(self, trues: bool = False, stats: bool = True, records: int = 0, record_stride: int = 1):
-        """Zeroed device output tensors for simulate()."""
+    def new_outputs(self, trues: bool = False, stats: bool = False, records: int = 0, record_stride: int = 1):
+        """Zeroed device output tensors for simulate().  Statistics counters
+        (stats=True) or per-history records make simulate() run the
+        instrumented kernel, which is slower; the default asks for neither."""
         import torch
         dev = torch.device("cuda", self.device)
         o = {"scatter_counts": torch.zeros(self.n_bins, dtype=torch.int32, device=dev),
