@@ -341,8 +341,8 @@ def main():
 
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(histories shard by index; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(histories shard by index).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -26,11 +26,11 @@
  * assignment LUT", closing paragraph).
  *
  * The paper leaves the photon physics, the random number generator and the
- * sinogram conventions to its simulator; the readings used here are listed in
- * the design notes and are followed step for step below.
+ * sinogram conventions to its simulator; the readings used here are stated
+ * at the steps below that follow them.
  *
  * Parity unpinned: the Rayleigh angular model (Thomson factor times an
- * analytic squared form factor) is this builder's choice, not the paper's;
+ * analytic squared form factor) is a choice made here, not the paper's;
  * its sampler is pinned to its own pdf, but nothing fixes the model itself.
  *
  * Precision.  The file is compiled twice.  With ORACLE_REAL=float every step
