@@ -92,6 +92,7 @@ def _lib(variant: str = "f32"):
         lib.orc_u01.argtypes = [C.c_uint32]
         lib.orc_u01.restype = C.c_float
         lib.orc_neg_log.argtypes = [_P, _P, C.c_uint64]
+        lib.orc_log_table.argtypes = [_P]
         lib.orc_sincos_2pi.argtypes = [_P, _P, _P, C.c_uint64]
         lib.orc_transport_coefs.argtypes = [_P, C.c_float, _P]
         lib.orc_emit.argtypes = [_P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, _P]
@@ -205,6 +206,13 @@ def neg_log(u, variant="f32"):
     u = np.ascontiguousarray(u, dtype=np.float32)
     out = np.empty_like(u)
     _lib(variant).orc_neg_log(_ptr(u), _ptr(out), u.size)
+    return out
+
+
+def log_table():
+    """The free-path logarithm's table: 129 rows of (c_i, hi_i, lo_i)."""
+    out = np.zeros((129, 3), np.float32)
+    _lib().orc_log_table(_ptr(out))
     return out
 
 

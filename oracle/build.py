@@ -24,7 +24,7 @@ def build(verbose: bool = False) -> None:
         out = lib_path(variant)
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
                "-Wall", "-Wextra", "-Wno-unused-parameter", f"-DORACLE_REAL={real}",
-               src, "-o", out + ".tmp", "-lm"]
+               src, "-o", out + ".tmp", "-lm", "-pthread"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

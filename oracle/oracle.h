@@ -167,6 +167,7 @@ float orc_u01(uint32_t x);
 /* -ln(u) for n uniforms as the transport's free-path sampling evaluates it
  * (binary32 build: the faithful binary32 logarithm; binary64: the library's). */
 void orc_neg_log(const float* u, float* out, uint64_t n);
+void orc_log_table(float* out); /* 129 x 3 floats */
 /* (sin 2 pi u, cos 2 pi u) as the transport's azimuth sampling evaluates it. */
 void orc_sincos_2pi(const float* u, float* sn, float* cs, uint64_t n);
 /* The transport's coefficients g, fC, fC + fR at energy e_kev in the build's

@@ -46,6 +46,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -127,13 +128,10 @@ float orc_u01(uint32_t x) { return (float)((x >> 8) | 1u) * 5.9604644775390625e-
 
 static real u01(rng_t* r) { return (real)((next32(r) >> 8) | 1u) * R(5.9604644775390625e-08); }
 
-/* -ln(u) of a transport uniform u in (0, 1], the free-path sample of the
- * Woodcock step (Methods, "Scatter simulator description").
- *
- * Binary64 build: the library logarithm.  Binary32 build: a faithful
- * logarithm (error below one unit in the last place for every uniform the
- * generator can produce) defined operation by operation, so that any IEEE
- * binary32 arithmetic without contraction gives the same bits:
+/* -ln(u) for a positive normal binary32 u: the logarithm of the energy
+ * model (Klein-Nishina total cross-section), a faithful binary32 logarithm
+ * defined operation by operation, so that any IEEE binary32 arithmetic
+ * without contraction gives the same bits:
  *   u = f 2^e with f in [sqrt(1/2), sqrt(2))         (frexp, exact)
  *   s = f - 1                                        (exact)
  *   r = s / (2 + s),  z = r^2,  ln f = 2 atanh(r)
@@ -160,8 +158,84 @@ static float neg_log_f32(float u) {
   return n * 0.693145751953125f + (n * 1.4286068e-06f - lnf);
 }
 
+/* -ln(u) of a transport uniform u in (0, 1), the free-path sample of the
+ * Woodcock step (Methods, "Scatter simulator description").
+ *
+ * Binary64 build: the library logarithm.  Binary32 build: a faithful
+ * logarithm (error below 0.85 units in the last place for every uniform the
+ * generator can produce; 99.7 % correctly rounded), defined operation by
+ * operation with fused multiply-adds (fmaf, correctly rounded), after the
+ * table method of Tang (1990):
+ *   u = F 2^k with F in [sqrt(1/2), sqrt(2))             (frexp, exact)
+ *   i = (bits(F) - 0x3F348000) >> 16, 0 <= i <= 128: the table entry whose
+ *     F range (2^16 consecutive binary32 values) holds F; entry 75 is the
+ *     range around F = 1
+ *   c_i = RN(1 / mid_i), mid_i the midpoint of the range, and c_i = 1 for
+ *     entries 73..77 (|F - 1| < 0.02), so that no table term cancels a
+ *     small result
+ *   T_i = -ln(c_i) = hi_i + lo_i, hi_i = T_i rounded to a multiple of
+ *     2^-16, lo_i = RN(T_i - hi_i)
+ *   r = RN(F c_i - 1)                                    (one fused rounding)
+ *   ln(1 + r) = r + r^2 (-1/2 + r (1/3 + r (-1/4 + r/5))) (|r| < 0.02 or
+ *     below 2^-8: the next term is below 2^-27 relative)
+ *   ln u = (k ln2_hi + hi_i) + ((ln(1 + r) + lo_i) + k ln2_lo), ln 2 split
+ *     so that the first sum is exact (multiples of 2^-16 below 2^5). */
+enum { kLogEntries = 129 };
+static const uint32_t kLogBase = 0x3F348000u;  /* bits of 1.0 - 2^15 - 75 * 2^16 */
+static float log_tab[kLogEntries][3];           /* c_i, hi_i, lo_i */
+static pthread_once_t log_tab_once = PTHREAD_ONCE_INIT;
+
+static float float_of_bits(uint32_t b) {
+  float x;
+  memcpy(&x, &b, sizeof x);
+  return x;
+}
+
+static void build_log_tab(void) {
+  for (int i = 0; i < kLogEntries; ++i) {
+    const double a = float_of_bits(kLogBase + ((uint32_t)i << 16));
+    const double b = float_of_bits(kLogBase + ((uint32_t)(i + 1) << 16));
+    const float c = (i >= 73 && i <= 77) ? 1.0f : (float)(1.0 / (0.5 * (a + b)));
+    const double t = -log((double)c);
+    const double hi = nearbyint(t * 65536.0) / 65536.0;
+    log_tab[i][0] = c;
+    log_tab[i][1] = (float)hi;
+    log_tab[i][2] = (float)(t - hi);
+  }
+}
+
+static float free_path_log_f32(float u) {
+  pthread_once(&log_tab_once, build_log_tab);
+  int e;
+  float f = frexpf(u, &e);
+  if (f < 0.70710678f) {
+    f = f + f;
+    e -= 1;
+  }
+  uint32_t fb;
+  memcpy(&fb, &f, sizeof fb);
+  const float* t = log_tab[(fb - kLogBase) >> 16];
+  const float r = fmaf(f, t[0], -1.0f);
+  const float q0 = fmaf(r, 0.2f, -0.25f);
+  const float q1 = fmaf(r, q0, 0.33333334f);
+  const float q2 = fmaf(r, q1, -0.5f);
+  const float r2 = r * r;
+  const float l1p = fmaf(r2, q2, r);
+  const float k = (float)e;
+  const float hi = fmaf(k, 0.693145751953125f, t[1]);
+  const float lo = fmaf(k, 1.4286068e-06f, l1p + t[2]);
+  return -(hi + lo);
+}
+
 static real neg_log(real u) {
-  return sizeof(real) == sizeof(float) ? (real)neg_log_f32((float)u) : (real)(-log((double)u));
+  return sizeof(real) == sizeof(float) ? (real)free_path_log_f32((float)u) : (real)(-log((double)u));
+}
+
+/* The table of the free-path logarithm (kLogEntries rows of c_i, hi_i,
+ * lo_i). */
+void orc_log_table(float* out) {
+  pthread_once(&log_tab_once, build_log_tab);
+  memcpy(out, log_tab, sizeof log_tab);
 }
 
 /* (sin 2 pi u, cos 2 pi u) for u in [0, 1): the azimuth of a direction.

@@ -474,6 +474,7 @@ sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner
   HIP_TRY(hipGetDeviceCount(&count), "count devices");
   if (device < 0 || device >= count) return fail(SSE_EINVAL, "no such HIP device");
   HIP_TRY(hipSetDevice(device), "set device");
+  HIP_TRY(sse::upload_log_table(), "upload the free-path logarithm's table");
   sse_ctx* c = new (std::nothrow) sse_ctx();
   if (!c) return fail(SSE_ENOMEM, "host allocation");
   c->device = device;

@@ -116,10 +116,10 @@ struct TransportParams {
   uint32_t item;            // request slot, for the work-list form
 };
 
-// -ln(u) for a positive normal u: a faithful binary32 logarithm (error below
-// one unit in the last place for the transport's uniforms), fixed operation
-// by operation so that host and device, and any IEEE binary32 arithmetic
-// without contraction, give the same bits:
+// -ln(u) for a positive normal u, the logarithm of the energy model (the
+// free-path sample uses the table logarithm in transport.hip): a faithful
+// binary32 logarithm, fixed operation by operation so that host and device,
+// and any IEEE binary32 arithmetic without contraction, give the same bits:
 // u = f 2^e with f in [sqrt(1/2), sqrt(2)); s = f - 1 (exact);
 // ln f = 2 atanh(r), r = s / (2 + s), whose Taylor series to z^4, z = r^2,
 // is arranged as s - (s^2/2 - r (s^2/2 + R)) so the exact s is not rounded
@@ -200,6 +200,11 @@ uint64_t transport_pairs_needed(uint64_t n);
 uint64_t transport_max_histories(uint64_t cap);
 uint64_t transport_batch_pairs_needed(uint64_t n);
 uint64_t transport_batch_max_histories(uint64_t cap);
+
+// The free-path logarithm's table, built on the host and copied to the
+// current device's constant memory (once per context is enough; every copy
+// is the same).
+hipError_t upload_log_table();
 
 // The device division check (counts: two zeroed device words).
 hipError_t launch_check_division(uint64_t n, uint32_t seed, unsigned long long* counts, hipStream_t stream);

@@ -30,6 +30,8 @@
 // draws and the TOF jitter, so a history's result does not depend on the
 // launch geometry.
 #include "internal.h"
+#include <cmath>
+#include <cstring>
 
 namespace sse {
 namespace {
@@ -102,6 +104,61 @@ constexpr uint32_t kRngSlots = 16;
 __device__ __forceinline__ float to_uniform(uint32_t x) {
   // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
   return static_cast<float>((x >> 8) | 1u) * 5.9604644775390625e-08f;
+}
+
+// ---------------------------------------------------------------------------
+// free-path logarithm
+// ---------------------------------------------------------------------------
+// -ln(u) of a transport uniform u in (0, 1), the free-path sample of the
+// Woodcock step (Methods, "Scatter simulator description"): a faithful
+// binary32 logarithm (below 0.85 units in the last place for every uniform
+// the generator can produce; 99.7 % correctly rounded), fixed operation by
+// operation with fused multiply-adds, after the table method of Tang (1990):
+//   u = F 2^k with F in [sqrt(1/2), sqrt(2))             (frexp, exact)
+//   i = (bits(F) - kLogBase) >> 16, 0 <= i < kLogEntries: the row whose F
+//     range (2^16 consecutive binary32 values) holds F; row 75 is the range
+//     around F = 1
+//   c_i = RN(1 / mid_i), mid_i the midpoint of the range, and c_i = 1 for
+//     rows 73..77 (|F - 1| < 0.02), so that no table term cancels a small
+//     result
+//   T_i = -ln(c_i) = hi_i + lo_i, hi_i = T_i rounded to a multiple of
+//     2^-16, lo_i = RN(T_i - hi_i)
+//   r = RN(F c_i - 1)                                    (one fused rounding)
+//   ln(1 + r) = r + r^2 (-1/2 + r (1/3 + r (-1/4 + r/5)))
+//   ln u = (k ln2_hi + hi_i) + ((ln(1 + r) + lo_i) + k ln2_lo), ln 2 split
+//     so that the first sum is exact (multiples of 2^-16 below 2^5).
+// The table (c_i, hi_i, lo_i, 0 per row) is built on the host in binary64
+// and kept in constant memory; each block stages it in LDS.
+constexpr int kLogEntries = 129;
+constexpr uint32_t kLogBase = 0x3F348000u;  // bits of 1.0, less 2^15 and 75 rows of 2^16
+__constant__ float4 c_log_rows[kLogEntries];
+// (a generic pointer to the block's LDS copy: the loads stay LDS loads once
+// the kernel is inlined, as the pointer's origin is known)
+typedef const float4 LdsLogRow;
+
+__device__ __forceinline__ float free_path_log32(float u, LdsLogRow* rows) {
+  int e;
+  float f = frexpf(u, &e);
+  if (f < 0.70710678f) {
+    f = f + f;
+    e -= 1;
+  }
+  const float4 t = rows[(__float_as_uint(f) - kLogBase) >> 16];
+  const float r = __builtin_fmaf(f, t.x, -1.0f);
+  const float q0 = __builtin_fmaf(r, 0.2f, -0.25f);
+  const float q1 = __builtin_fmaf(r, q0, 0.33333334f);
+  const float q2 = __builtin_fmaf(r, q1, -0.5f);
+  const float r2 = r * r;
+  const float l1p = __builtin_fmaf(r2, q2, r);
+  const float k = static_cast<float>(e);
+  const float hi = __builtin_fmaf(k, 0.693145751953125f, t.y);
+  const float lo = __builtin_fmaf(k, 1.4286068e-06f, l1p + t.z);
+  return -(hi + lo);
+}
+
+// the block's copy of the table (all threads; a barrier follows)
+__device__ __forceinline__ void stage_log_rows(float4* rows) {
+  for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(kLogEntries); i += blockDim.x) rows[i] = c_log_rows[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -777,7 +834,7 @@ struct NoMore {
 template <bool kInstr, bool kExtends, class More>
 __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t next, uint64_t end,
                                               unsigned long long* s_stats, LdsFloat* mu_tab,
-                                              LdsWord* stash, LdsWord* rng_buf, LdsWord* eq,
+                                              LdsWord* stash, LdsWord* rng_buf, LdsWord* eq, LdsLogRow* log_rows,
                                               uint64_t& res_next, uint64_t& res_end, More&& more) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
@@ -936,7 +993,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       const bool trk = phase == kTrack;
       const bool go = trk && steps < static_cast<uint32_t>(kMaxSteps);
       const uint32_t x0 = r.peek(0u), x1 = r.peek(1u);
-      const float tn = t + neg_log32<DevDiv>(to_uniform(x0)) * ec.inv_maj;
+      const float tn = t + free_path_log32(to_uniform(x0), log_rows) * ec.inv_maj;
       const bool inside = go && tn < texit;
       const float qx = px + tn * dx;
       const float qy = py + tn * dy;
@@ -1226,13 +1283,15 @@ transport_kernel(TransportParams p) {
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][kRngSlots * 64];
   __shared__ uint32_t s_emit[4][kEmitWords * 64];
+  __shared__ float4 s_log[kLogEntries];
   if (kInstr && threadIdx.x < kStatCount) s_stats[threadIdx.x] = 0;
   if (p.mu_table) s_mu_table[threadIdx.x] = p.mu_table[threadIdx.x];
+  stage_log_rows(s_log);
   __syncthreads();
   uint64_t res_next = 0, res_end = 0;
   run_histories<kInstr, false>(p, begin, end, s_stats, (LdsFloat*)(s_mu_table), (LdsWord*)(s_stash[threadIdx.x >> 6]),
-                        (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next,
-                        res_end, NoMore{});
+                               (LdsWord*)(s_rng[threadIdx.x >> 6]), (LdsWord*)(s_emit[threadIdx.x >> 6]),
+                               (LdsLogRow*)(s_log), res_next, res_end, NoMore{});
   pad_pairs(p, res_next, res_end);
   if (kInstr) {
     __syncthreads();
@@ -1262,6 +1321,9 @@ transport_batch_kernel(BatchParams b) {
   __shared__ uint32_t s_stash[4][kSingleWords * 64];
   __shared__ uint32_t s_rng[4][kRngSlots * 64];
   __shared__ uint32_t s_emit[4][kEmitWords * 64];
+  __shared__ float4 s_log[kLogEntries];
+  stage_log_rows(s_log);
+  __syncthreads();
   const uint32_t lane = threadIdx.x & 63u;
   float* tab = s_tab[threadIdx.x >> 6];
   uint64_t res_next = 0, res_end = 0;  // the wavefront's pair-buffer block, kept across chunks
@@ -1325,7 +1387,7 @@ transport_batch_kernel(BatchParams b) {
     };
     run_histories<false, true>(p, cur.h0, cur.h0 + cur.n, nullptr, (LdsFloat*)(tab),
                                (LdsWord*)(s_stash[threadIdx.x >> 6]), (LdsWord*)(s_rng[threadIdx.x >> 6]),
-                               (LdsWord*)(s_emit[threadIdx.x >> 6]), res_next, res_end, more);
+                               (LdsWord*)(s_emit[threadIdx.x >> 6]), (LdsLogRow*)(s_log), res_next, res_end, more);
     last = &p;
     __builtin_amdgcn_wave_barrier();
     have = holding;
@@ -1538,6 +1600,21 @@ hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_it
     done += n;
   }
   return hipSuccess;
+}
+
+hipError_t upload_log_table() {
+  float4 rows[kLogEntries];
+  for (int i = 0; i < kLogEntries; ++i) {
+    float a, b;
+    const uint32_t ba = kLogBase + (static_cast<uint32_t>(i) << 16), bb = kLogBase + (static_cast<uint32_t>(i + 1) << 16);
+    std::memcpy(&a, &ba, sizeof a);
+    std::memcpy(&b, &bb, sizeof b);
+    const float c = (i >= 73 && i <= 77) ? 1.0f : static_cast<float>(1.0 / (0.5 * (static_cast<double>(a) + b)));
+    const double t = -std::log(static_cast<double>(c));
+    const double hi = std::nearbyint(t * 65536.0) / 65536.0;
+    rows[i] = make_float4(c, static_cast<float>(hi), static_cast<float>(t - hi), 0.0f);
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_log_rows), rows, sizeof rows);
 }
 
 hipError_t launch_check_division(uint64_t n, uint32_t seed, unsigned long long* counts, hipStream_t stream) {
