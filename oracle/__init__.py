@@ -105,6 +105,9 @@ def _lib(variant: str = "f32"):
         lib.orc_edge_paths.argtypes = [_P, C.c_double, C.c_double, _P, _P]
         lib.orc_edge_prob.argtypes = [_P, C.c_double, C.c_double]
         lib.orc_edge_prob.restype = C.c_double
+        lib.orc_rotate.argtypes = [_P, C.c_double, C.c_double, C.c_double, _P]
+        lib.orc_transport_photons.argtypes = [_P, _P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, C.c_double, _P]
+        lib.orc_transport_photons.restype = C.c_int
         lib.orc_locate.argtypes = [_P, _P, C.c_float, C.c_float, C.c_float, _P, _P]
         lib.orc_locate.restype = C.c_int
         _libs[variant] = lib
@@ -281,6 +284,32 @@ def locate(scanner, gaps, hx, hy, hz):
     d = {k: int(v) for k, v in zip(LOCATE_FIELDS, out)}
     d["tfrac"], d["afrac"] = float(frac[0]), float(frac[1])
     return d
+
+
+def rotate(u, ct, cp, sp, variant="f32"):
+    """The transport's turn of direction u by polar cosine ct and azimuth
+    (cos, sin) = (cp, sp), in the build's precision."""
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(3)
+    _lib(variant).orc_rotate(_ptr(u), float(ct), float(cp), float(sp), _ptr(out))
+    return out
+
+
+def transport_photons(scanner, physics, pdesc, mu, p0, d, e_kev, seed=1, variant="f32"):
+    """Photons started at p0[i] along d[i] with energy e_kev, transported to the
+    cylinder; returns PHOTON_DTYPE records (hit, direction, energy, path,
+    interactions and fate)."""
+    mu = np.ascontiguousarray(mu, np.float32).ravel()
+    p0 = np.ascontiguousarray(p0, np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    n = p0.shape[0]
+    assert d.shape[0] == n
+    out = np.zeros(n, PHOTON_DTYPE)
+    s_sc, s_ph, s_pd = scanner_struct(scanner), physics_struct(physics), phantom_struct(pdesc)
+    if _lib(variant).orc_transport_photons(C.byref(s_sc), C.byref(s_ph), C.byref(s_pd), _ptr(mu), seed, n,
+                                           _ptr(p0), _ptr(d), float(e_kev), _ptr(out)) != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
 
 
 def real_size(variant="f32") -> int:

@@ -181,6 +181,17 @@ void orc_emit(const orc_phantom* pd, const uint32_t* alias_thresh, const uint32_
 void orc_sample_compton(uint64_t seed, double e_kev, uint64_t n, double* cos_theta, double* e_out);
 /* n Rayleigh samples of cos(theta) at energy e_kev. */
 void orc_sample_rayleigh(uint64_t seed, double e_kev, float beta, uint64_t n, double* cos_theta);
+/* The transport's change of direction: u turned by polar cosine ct and
+ * azimuth (cos phi, sin phi) = (cp, sp), in the build's precision. */
+void orc_rotate(const double u[3], double ct, double cp, double sp, double out[3]);
+/* n photons, photon i from p0[3i..] along the unit dir[3i..] with energy
+ * e_kev, each on its own stream (seed, h = i, substream 1), transported to
+ * the cylinder as the simulation transports annihilation photons (out:
+ * hit, direction, energy, path, interactions and fate; no crystal or LUT
+ * index).  Returns -1 on bad arguments. */
+int orc_transport_photons(const orc_scanner* sc, const orc_physics* ph, const orc_phantom* pd,
+                          const float* mu, uint64_t seed, uint64_t n, const double* p0, const double* dir,
+                          double e_kev, orc_photon_rec* out);
 /* Attenuation model: g(E) = mu(E)/mu(511) and the Compton / Rayleigh parts. */
 void orc_energy_model(const orc_physics* ph, double e_kev, double out[3]);
 /* Sinogram coordinates of an LOR between crystals c1 (photon A) and c2

@@ -565,20 +565,28 @@ static int sample_rayleigh(rng_t* r, real alpha, real beta, real* cos_out) {
 static void azimuth(rng_t* r, real* cp, real* sp) { sincos_2pi(u01(r), sp, cp); }
 
 /* New direction after scattering by polar cosine ct and azimuth (cp, sp)
- * about the old direction. */
+ * about the old direction u: d' = ct u + st (cp e1 + sp e2) in the frame
+ *   e1 = (ux uz / s, uy uz / s, -s),  e2 = (-uy / s, ux / s, 0),
+ *   s = sqrt(ux^2 + uy^2),
+ * which is orthogonal to u with |e1| = |u| and |e2| = 1 whatever the rounding
+ * of u's norm, so d' . u = ct to rounding.  Only a direction within 1e-10 of
+ * the axis (s^2 <= 1e-20) takes the axis itself as u, with (e1, e2) = (x, y)
+ * for uz > 0 and (x, -y) for uz < 0 (limits of the frame above, so that
+ * (e1, e2, u) stays right-handed); the angle that costs is below 1e-10. */
 static void rotate(vec3* d, real ct, real cp, real sp) {
   real st = (real)sqrt((double)((R(1) - ct) * (R(1) + ct)));
   real ux = d->x, uy = d->y, uz = d->z;
-  if (fabs((double)uz) > (double)R(0.99999)) {
+  real tt = ux * ux + uy * uy;
+  if (!(tt > R(1e-20))) {
     real sg = uz > R(0) ? R(1) : R(-1);
     d->x = st * cp;
-    d->y = st * sp;
+    d->y = sg * st * sp;
     d->z = sg * ct;
   } else {
-    real tmp = (real)sqrt((double)((R(1) - uz) * (R(1) + uz)));
-    d->x = ux * ct + st * (ux * uz * cp - uy * sp) / tmp;
-    d->y = uy * ct + st * (uy * uz * cp + ux * sp) / tmp;
-    d->z = uz * ct - tmp * st * cp;
+    real s = (real)sqrt((double)tt);
+    d->x = ux * ct + st * (ux * uz * cp - uy * sp) / s;
+    d->y = uy * ct + st * (uy * uz * cp + ux * sp) / s;
+    d->z = uz * ct - s * st * cp;
   }
 }
 
@@ -593,9 +601,11 @@ typedef struct {
   uint32_t steps;
 } photon_t;
 
-static void transport(const ctx_t* C, rng_t* r, vec3 p0, vec3 d, photon_t* o, uint64_t* st) {
+/* Photon from p0 along unit d with energy e0 (511 keV for annihilation
+ * photons). */
+static void transport(const ctx_t* C, rng_t* r, vec3 p0, vec3 d, real e0, photon_t* o, uint64_t* st) {
   ecoef_t ec;
-  set_energy(&ec, R(MEC2_KEV), C);
+  set_energy(&ec, e0, C);
   real len = R(0);
   real t = R(0);
   real texit = box_exit(C, p0, d);
@@ -966,8 +976,8 @@ static void history(const ctx_t* C, uint64_t seed, uint64_t h,
   emit(C, &r, &voxel, &p, &d);
   dm.x = -d.x; dm.y = -d.y; dm.z = -d.z;
   photon_t A, B;
-  transport(C, &r, p, d, &A, st);
-  transport(C, &r, p, dm, &B, st);
+  transport(C, &r, p, d, R(MEC2_KEV), &A, st);
+  transport(C, &r, p, dm, R(MEC2_KEV), &B, st);
   st[ORC_ST_HISTORIES] += 1;
 
   uint32_t outcome;
@@ -1182,6 +1192,55 @@ void orc_sample_rayleigh(uint64_t seed, double e_kev, float beta, uint64_t n, do
     sample_rayleigh(&r, alpha, (real)beta, &c);
     cos_theta[i] = (double)c;
   }
+}
+
+void orc_rotate(const double u[3], double ct, double cp, double sp, double out[3]) {
+  vec3 d;
+  d.x = (real)u[0]; d.y = (real)u[1]; d.z = (real)u[2];
+  rotate(&d, (real)ct, (real)cp, (real)sp);
+  out[0] = (double)d.x; out[1] = (double)d.y; out[2] = (double)d.z;
+}
+
+int orc_transport_photons(const orc_scanner* sc, const orc_physics* ph, const orc_phantom* pd,
+                          const float* mu, uint64_t seed, uint64_t n, const double* p0, const double* dir,
+                          double e_kev, orc_photon_rec* out) {
+  if (!sc || !ph || !pd || !mu || !p0 || !dir || !out) return -1;
+  if (pd->nx <= 0 || pd->ny <= 0 || pd->nz <= 0 || !(ph->rayleigh_beta > 0.0f)) return -1;
+  ctx_t C;
+  memset(&C, 0, sizeof(C));
+  C.sc = sc; C.ph = ph; C.pd = pd; C.mu = mu;
+  C.nvox = (uint64_t)pd->nx * (uint64_t)pd->ny * (uint64_t)pd->nz;
+  C.vox.x = (real)pd->voxel_mm[0]; C.vox.y = (real)pd->voxel_mm[1]; C.vox.z = (real)pd->voxel_mm[2];
+  C.lo.x = (real)pd->lo_mm[0]; C.lo.y = (real)pd->lo_mm[1]; C.lo.z = (real)pd->lo_mm[2];
+  C.hi.x = C.lo.x + (real)pd->nx * C.vox.x;
+  C.hi.y = C.lo.y + (real)pd->ny * C.vox.y;
+  C.hi.z = C.lo.z + (real)pd->nz * C.vox.z;
+  C.inv_vox.x = R(1) / C.vox.x; C.inv_vox.y = R(1) / C.vox.y; C.inv_vox.z = R(1) / C.vox.z;
+  float mmax = 0.0f;
+  for (uint64_t i = 0; i < C.nvox; ++i) {
+    if (!(mu[i] >= 0.0f)) return -1;
+    if (mu[i] > mmax) mmax = mu[i];
+  }
+  if (ph->mu_majorant > 0.0f) {
+    if (ph->mu_majorant < mmax) return -1;
+    mmax = ph->mu_majorant;
+  }
+  C.mu_maj = (real)mmax;
+  C.RR = (real)sc->radius_mm * (real)sc->radius_mm;
+  C.half_len = R(0.5) * (real)sc->length_mm;
+  uint64_t st[ORC_ST_COUNT];
+  memset(st, 0, sizeof(st));
+  for (uint64_t i = 0; i < n; ++i) {
+    rng_t r;
+    rng_init(&r, seed, i, 1);
+    vec3 p, d;
+    p.x = (real)p0[3 * i]; p.y = (real)p0[3 * i + 1]; p.z = (real)p0[3 * i + 2];
+    d.x = (real)dir[3 * i]; d.y = (real)dir[3 * i + 1]; d.z = (real)dir[3 * i + 2];
+    photon_t o;
+    transport(&C, &r, p, d, (real)e_kev, &o, st);
+    fill_photon_rec(&out[i], &o);
+  }
+  return 0;
 }
 
 int orc_locate(const orc_scanner* sc, const orc_gaps* gaps, float hx, float hy, float hz,

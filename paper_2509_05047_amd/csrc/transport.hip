@@ -318,20 +318,27 @@ __device__ __forceinline__ void sincos_2pi(float u, float& sn, float& cs) {
 // physics
 // ---------------------------------------------------------------------------
 
+// New direction after scattering by polar cosine ct and azimuth (cp, sp)
+// about the old direction u: d' = ct u + st (cp e1 + sp e2) in the frame
+// e1 = (ux uz / s, uy uz / s, -s), e2 = (-uy / s, ux / s, 0) with
+// s = sqrt(ux^2 + uy^2), orthogonal to u whatever the rounding of u's norm.
+// A direction within 1e-10 of the axis takes the axis itself as u, with
+// (e1, e2) = (x, y) about +z and (x, -y) about -z (right-handed, as the
+// frame's limits).  The quotients have s >= 1e-10 as divisor.
 __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct, float cp, float sp) {
   const float st = sqrtf((1.0f - ct) * (1.0f + ct));
   const float ux = dx, uy = dy, uz = dz;
-  if (fabsf(uz) > 0.99999f) {
+  const float tt = ux * ux + uy * uy;
+  if (!(tt > 1e-20f)) {
     const float sg = uz > 0.0f ? 1.0f : -1.0f;
     dx = st * cp;
-    dy = st * sp;
+    dy = sg * st * sp;
     dz = sg * ct;
   } else {
-    const float tmp = sqrtf((1.0f - uz) * (1.0f + uz));
-    // tmp = sin of the polar angle, above 0.0045 on this branch
-    dx = ux * ct + fdiv(st * (ux * uz * cp - uy * sp), tmp);
-    dy = uy * ct + fdiv(st * (uy * uz * cp + ux * sp), tmp);
-    dz = uz * ct - tmp * st * cp;
+    const float s = sqrtf(tt);
+    dx = ux * ct + fdiv(st * (ux * uz * cp - uy * sp), s);
+    dy = uy * ct + fdiv(st * (uy * uz * cp + ux * sp), s);
+    dz = uz * ct - s * st * cp;
   }
 }
 
