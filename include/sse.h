@@ -198,9 +198,11 @@ sse_status sse_load_phantom(sse_ctx* ctx, const sse_phantom_desc* desc, const fl
 
 /* Replace a loaded phantom's activity (rebuilds its emission sampler); the
  * iterative estimation loop re-simulates with updated activity (Methods,
- * "Unknown activity distribution, very limited simulation time").
- * Errors: SSE_EINVAL, SSE_EBUSY while a server runs on the context (its
- * requests read the sampler). */
+ * "Unknown activity distribution, very limited simulation time").  The call
+ * first waits for every sse_simulate / sse_simulate_noalloc enqueued earlier
+ * on the context, on any stream (they read the sampler), and returns with
+ * the new sampler in place.  Errors: SSE_EINVAL, SSE_EBUSY while a server
+ * runs on the context (its requests read the sampler). */
 sse_status sse_update_activity(sse_ctx* ctx, sse_phantom_id id, const float* activity, int mem,
                                void* stream);
 
@@ -444,7 +446,11 @@ typedef struct {
   double* scatter_weights;     /* NULL: the server allocates them within the budget */
 } sse_request;
 
-enum { SSE_REQ_DONE = 0, SSE_REQ_CANCELLED = 1 };
+/* Completion status.  SSE_REQ_FAILED: the server could not allocate the
+ * request's output sinograms (the device had less free memory than the
+ * budget allowed for) and no buffer it holds could come back; nothing was
+ * simulated. */
+enum { SSE_REQ_DONE = 0, SSE_REQ_CANCELLED = 1, SSE_REQ_FAILED = 2 };
 
 typedef struct {
   uint64_t id;
@@ -461,6 +467,7 @@ typedef struct {
   uint64_t max_active_seen;    /* largest number of requests active in one tick */
   uint64_t bytes_allocated;    /* library-allocated output buffers (in use or pooled) */
   uint64_t budget_bytes;
+  uint64_t failed;             /* requests completed as SSE_REQ_FAILED */
 } sse_server_stats;
 
 /* Start a server on a context (the context must outlive it and have a LUT

@@ -96,10 +96,10 @@ class Completion(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "cancelled", "ticks", "histories",
-                                          "max_active_seen", "bytes_allocated", "budget_bytes")]
+                                          "max_active_seen", "bytes_allocated", "budget_bytes", "failed")]
 
 
-REQ_DONE, REQ_CANCELLED = 0, 1
+REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2
 
 # every entry point of include/sse.h: name -> (argtypes, restype)
 _P = C.c_void_p

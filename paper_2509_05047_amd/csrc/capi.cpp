@@ -592,6 +592,10 @@ sse_status sse_update_activity(sse_ctx* c, sse_phantom_id id, const float* activ
     if (st != SSE_OK) return st;
     host_act = p->alias_work->act.data();
   }
+  // Simulations queued before this call, on any stream, may still read the
+  // table: every simulate records pair_done when it is enqueued, and each one
+  // waits for the previous record, so the last record covers them all.
+  if (c->pair_done) HIP_TRY(hipEventSynchronize(c->pair_done), "wait for simulations reading the phantom");
   return upload_alias(host_act, s, *p);
 }
 

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -65,6 +66,8 @@ struct sse_server {
   std::deque<sse_completion> completions;
   std::vector<Buffer> pool;                 // free library-allocated outputs
   std::map<uint64_t, Buffer> held;          // completed, not yet released
+  std::set<uint64_t> finished_ids;          // every completed request
+  bool alloc_blocked = false;               // an output allocation failed; none until a release
   uint64_t next_id = 1;
   bool stopping = false;
   sse_server_stats st{};
@@ -106,6 +109,7 @@ void complete(sse_server* s, int slot) {
   c.scatter_counts = q.out.counts;
   c.scatter_weights = q.out.weights;
   if (q.owned) s->held[q.id] = q.out;
+  s->finished_ids.insert(q.id);
   s->completions.push_back(c);
   if (q.cancelled) ++s->st.cancelled; else ++s->st.completed;
   s->used[slot] = false;
@@ -126,6 +130,28 @@ void note_error(sse_server* s, hipError_t e, const char* what) {
   s->done.notify_all();
 }
 
+// The front request needs library-allocated outputs that neither the pool
+// nor a new allocation can give it.  If no buffer can come back either (none
+// held by completed requests, none in use by active ones), waiting is futile:
+// it completes as failed and true is returned.  Called with the lock held.
+bool fail_if_starved(sse_server* s) {
+  if (!s->held.empty()) return false;
+  for (size_t i = 0; i < s->slots.size(); ++i)
+    if (s->used[i] && s->slots[i].owned) return false;
+  Req& q = s->pending.front();
+  sse_completion c{};
+  c.id = q.id;
+  c.status = SSE_REQ_FAILED;
+  c.t_submit = q.t_submit;
+  c.t_admit = c.t_complete = s->now();
+  s->completions.push_back(c);
+  ++s->st.failed;
+  s->finished_ids.insert(q.id);
+  s->pending.pop_front();
+  s->done.notify_all();
+  return true;
+}
+
 // Admit queued requests first-in first-out while a slot is free and their
 // output buffers fit the budget.  Called with the lock held.
 void admit(sse_server* s) {
@@ -139,6 +165,7 @@ void admit(sse_server* s) {
       c.t_admit = c.t_complete = s->now();
       s->completions.push_back(c);
       ++s->st.cancelled;
+      s->finished_ids.insert(q.id);
       s->pending.pop_front();
       s->done.notify_all();
       continue;
@@ -153,16 +180,31 @@ void admit(sse_server* s) {
       if (!s->pool.empty()) {
         b = s->pool.back();
         s->pool.pop_back();
-      } else if (s->st.bytes_allocated + s->footprint <= s->st.budget_bytes) {
+      } else if (s->st.bytes_allocated + s->footprint <= s->st.budget_bytes && !s->alloc_blocked) {
         const uint64_t nb = s->ctx->n_bins;
-        if (hipMalloc(&b.counts, nb * sizeof(uint32_t)) != hipSuccess) return;
-        if (hipMalloc(&b.weights, nb * sizeof(double)) != hipSuccess) {
-          release(b.counts);
-          return;
+        hipError_t ea = hipMalloc(&b.counts, nb * sizeof(uint32_t));
+        if (ea == hipSuccess) {
+          ea = hipMalloc(&b.weights, nb * sizeof(double));
+          if (ea != hipSuccess) {
+            release(b.counts);
+            b.counts = nullptr;
+          }
+        }
+        if (ea != hipSuccess) {
+          // The device is fuller than the budget assumed (memory allocated
+          // outside the server).  Clear the error so that it does not
+          // surface at the next launch, and allocate nothing more until a
+          // release; the request waits for buffers to come back, or fails
+          // if none can.
+          (void)hipGetLastError();
+          s->alloc_blocked = true;
+          if (!fail_if_starved(s)) return;
+          continue;
         }
         s->st.bytes_allocated += s->footprint;
       } else {
-        return;  // wait for a release
+        if (!fail_if_starved(s)) return;  // wait for a release
+        continue;
       }
     }
     const uint64_t nb = s->ctx->n_bins;
@@ -344,16 +386,6 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
     return fail(SSE_EINVAL, "chunk_histories too large");
   }
   s->footprint = c->n_bins * (sizeof(uint32_t) + sizeof(double));
-  if (cfg->hbm_budget_bytes) {
-    s->st.budget_bytes = cfg->hbm_budget_bytes;
-  } else {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-      delete s;
-      return fail(SSE_EDEVICE, "query free memory");
-    }
-    s->st.budget_bytes = static_cast<uint64_t>(0.9 * static_cast<double>(free_b));
-  }
   const int na = cfg->max_active;
   s->slots.assign(na, Req());
   s->used.assign(na, false);
@@ -381,6 +413,17 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
   if (e != hipSuccess) {
     free_server(s);
     return hip_fail(e, "server resources");
+  }
+  // the default budget: what is free once the server's own buffers exist
+  if (cfg->hbm_budget_bytes) {
+    s->st.budget_bytes = cfg->hbm_budget_bytes;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      free_server(s);
+      return fail(SSE_EDEVICE, "query free memory");
+    }
+    s->st.budget_bytes = static_cast<uint64_t>(0.9 * static_cast<double>(free_b));
   }
   s->t0 = std::chrono::steady_clock::now();
   try {
@@ -448,9 +491,15 @@ sse_status sse_server_release(sse_server* s, uint64_t id) {
   if (!s) return fail(SSE_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(s->m);
   auto it = s->held.find(id);
-  if (it == s->held.end()) return SSE_OK;  // caller-owned outputs, or nothing held
+  if (it == s->held.end()) {
+    // a completed request with caller-owned outputs (or released before):
+    // nothing to do; an id never issued, queued or still active: an error
+    if (s->finished_ids.count(id)) return SSE_OK;
+    return fail(SSE_EINVAL, "no completed request with this id");
+  }
   s->pool.push_back(it->second);
   s->held.erase(it);
+  s->alloc_blocked = false;
   s->wake.notify_one();
   return SSE_OK;
 }

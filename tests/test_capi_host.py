@@ -44,7 +44,7 @@ def test_structure_sizes_match_header_layout():
     assert C.sizeof(sse.ServerCfg) == 32
     assert C.sizeof(sse.Request) == 48
     assert C.sizeof(sse.Completion) == 64
-    assert C.sizeof(sse.ServerStats) == 64
+    assert C.sizeof(sse.ServerStats) == 72
     assert C.sizeof(sse.GapDesc) == 24
     assert C.sizeof(sse.EdgeGeom) == 24
 
