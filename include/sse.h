@@ -329,6 +329,24 @@ sse_status sse_load_sensitivity(sse_ctx* ctx, const float* sens, int has_tof_axi
 sse_status sse_simulate(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
                         uint64_t h_offset, const sse_outputs* out, void* stream);
 
+/* sse_simulate without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid it).  Same histories, arguments and results as sse_simulate
+ * (counts bit for bit; weights up to the order of their binary64 sums), on
+ * the production path only: out->stats and out->records must be NULL.  The
+ * kernels' scratch (work-list parameters, counters and the pair buffer) is a
+ * fixed 256 MiB device array of the library, one per GPU, held from the
+ * first sse_create on that GPU until the process ends; runs longer than one
+ * launch's share of it are split into launches, which costs a little speed.
+ * The call allocates nothing and frees nothing.  Calls of one context are
+ * ordered with its other simulations; calls of different contexts on one GPU
+ * share the array and race if they overlap: order them (one stream).
+ * Asynchronous on `stream`.  Errors: those of sse_simulate, SSE_EINVAL for
+ * stats or records, or if the GPU's resident transport grid would need more
+ * pair records than the array holds. */
+sse_status sse_simulate_noalloc(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
+                                uint64_t h_offset, const sse_outputs* out, void* stream);
+
 /* Pair pruning (enable = 1; off after sse_create): photon B of a history is
  * not tracked when photon A ended outside the energy window (not detected,
  * or detected outside [e_lo, e_hi]).  Such a history adds to no sinogram

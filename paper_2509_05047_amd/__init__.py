@@ -118,6 +118,7 @@ SIGNATURES = {
     "sse_build_edge_lut": ([_P, _P], C.c_int),
     "sse_check_division": ([_P, C.c_uint64, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], C.c_int),
     "sse_simulate": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
+    "sse_simulate_noalloc": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
     "sse_emission_scale": ([_P, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
     "sse_gaussian_smooth": ([_P, _P, _P, _P, C.c_float, _P], C.c_int),
@@ -342,6 +343,17 @@ class Context:
                     _ptr(outputs.get("stats")), _ptr(outputs.get("records")),
                     int(outputs.get("record_stride", 1)) if outputs.get("records") is not None else 0)
         _check(lib().sse_simulate(self._h, pid, n_histories, seed, h_offset, C.byref(o), _stream_ptr(stream)))
+
+    def simulate_noalloc(self, pid: int, n_histories: int, seed: int, outputs: dict, h_offset: int = 0,
+                         stream=None):
+        """simulate() through the allocation-free entry point (scatter and
+        trues sinograms only: no statistics, no records)."""
+        o = Outputs(_ptr(outputs["scatter_counts"]), _ptr(outputs["scatter_weights"]),
+                    _ptr(outputs.get("true_counts")), _ptr(outputs.get("true_weights")),
+                    _ptr(outputs.get("stats")), _ptr(outputs.get("records")),
+                    int(outputs.get("record_stride", 1)) if outputs.get("records") is not None else 0)
+        _check(lib().sse_simulate_noalloc(self._h, pid, n_histories, seed, h_offset, C.byref(o),
+                                          _stream_ptr(stream)))
 
     def emission_scale(self, pid: int, n_histories: int, acq_seconds: float = 1.0, factor: float = 1.0) -> float:
         v = C.c_double()

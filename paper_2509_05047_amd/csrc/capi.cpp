@@ -363,7 +363,6 @@ sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
   cap = (cap + 0xffffull) & ~0xffffull;
   if (c->d_pairs && c->pair_cap >= cap) return SSE_OK;
   if (!c->d_pair_count) HIP_TRY(hipMalloc(&c->d_pair_count, sizeof(uint32_t)), "allocate pair counter");
-  if (!c->pair_done) HIP_TRY(hipEventCreateWithFlags(&c->pair_done, hipEventDisableTiming), "create event");
   if (c->d_pairs) {  // the freeing waits for the device
     release(c->d_pairs);
     c->d_pairs = nullptr;
@@ -475,8 +474,16 @@ sse_status sse_create(sse_ctx** out, int device, const sse_scanner_desc* scanner
   if (device < 0 || device >= count) return fail(SSE_EINVAL, "no such HIP device");
   HIP_TRY(hipSetDevice(device), "set device");
   HIP_TRY(sse::upload_log_table(), "upload the free-path logarithm's table");
+  // the device's allocation-free scratch (looked up once per device)
+  HIP_TRY(sse::noalloc_scratch_init(device), "find the allocation-free scratch");
+  hipEvent_t ev = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "create event");
   sse_ctx* c = new (std::nothrow) sse_ctx();
-  if (!c) return fail(SSE_ENOMEM, "host allocation");
+  if (!c) {
+    (void)hipEventDestroy(ev);
+    return fail(SSE_ENOMEM, "host allocation");
+  }
+  c->pair_done = ev;
   c->device = device;
   c->sc = *scanner;
   c->sn = *sino;
@@ -857,6 +864,41 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   else
     HIP_TRY(sse::launch_transport_item(p, c->d_item, c->d_chunk, c->d_cursor, s), "transport kernel launch");
   HIP_TRY(hipEventRecord(c->pair_done, s), "record pair-buffer use");
+  return SSE_OK;
+}
+
+sse_status sse_simulate_noalloc(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
+                                uint64_t h_offset, const sse_outputs* out, void* stream) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  Phantom* ph = get_phantom(c, id);
+  if (!ph) return fail(SSE_EINVAL, "unknown phantom id");
+  if (!c->d_lut) return fail(SSE_ESTATE, "no LUT loaded");
+  if (c->gaps_on && !lut_fits_gaps(c->sc, c->lut)) return fail(SSE_ESTATE, "the loaded LUT lacks the gap layout");
+  if (!out || !out->scatter_counts || !out->scatter_weights) return fail(SSE_EINVAL, "scatter outputs are required");
+  if (out->stats || out->records)
+    return fail(SSE_EINVAL, "statistics and records need sse_simulate (the allocation-free call has neither)");
+  if (reinterpret_cast<uintptr_t>(out->scatter_counts) % 4 || reinterpret_cast<uintptr_t>(out->scatter_weights) % 8 ||
+      reinterpret_cast<uintptr_t>(out->true_counts) % 4 || reinterpret_cast<uintptr_t>(out->true_weights) % 8)
+    return fail(SSE_EINVAL, "misaligned output buffer");
+  if (n_histories > ~static_cast<uint64_t>(0) - h_offset) return fail(SSE_EINVAL, "history range overflows");
+  if (n_histories == 0) return SSE_OK;
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (sse::noalloc_max_histories() == 0)
+    return fail(SSE_EINVAL, "the device's resident transport grid needs more pair records than the " +
+                                std::to_string(sse::kNoAllocScratchBytes >> 20) + " MiB allocation-free scratch holds");
+  sse::TransportParams p;
+  build_transport_params(c, ph, seed, h_offset, n_histories, p);
+  p.sc_n = out->scatter_counts;
+  p.sc_w = out->scatter_weights;
+  p.tr_n = out->true_counts;
+  p.tr_w = out->true_weights;
+  p.item = 0;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // ordered after the context's earlier simulations, like sse_simulate (the
+  // chain lets sse_update_activity wait for all of them)
+  HIP_TRY(hipStreamWaitEvent(s, c->pair_done, 0), "order after earlier simulations");
+  HIP_TRY(sse::launch_transport_noalloc(c->device, p, s), "transport kernel launch");
+  HIP_TRY(hipEventRecord(c->pair_done, s), "record the simulation");
   return SSE_OK;
 }
 

@@ -245,4 +245,16 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
 hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
                                  uint32_t* d_cursor, hipStream_t stream);
 
+// Allocation-free simulate (sse_simulate_noalloc): the kernels' scratch --
+// work-list parameters, counters and pair buffer -- is a file-scope device
+// array of kNoAllocScratchBytes.  noalloc_scratch_init looks its address up
+// on `device` (which must be current) once per device; the launch then
+// splits [p.h0, p.h0 + p.n) into work-list launches that fit it (p's pair
+// buffer fields are replaced).  noalloc_max_histories: the most histories
+// one launch takes (0 if the resident grid needs more than the scratch).
+constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
+hipError_t noalloc_scratch_init(int device);
+uint64_t noalloc_max_histories();
+hipError_t launch_transport_noalloc(int device, const TransportParams& p, hipStream_t stream);
+
 }  // namespace sse

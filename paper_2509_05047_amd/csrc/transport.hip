@@ -32,6 +32,7 @@
 #include "internal.h"
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace sse {
 namespace {
@@ -1631,6 +1632,65 @@ hipError_t launch_check_division(uint64_t n, uint32_t seed, unsigned long long* 
   hipLaunchKernelGGL(check_division_kernel, dim3(static_cast<unsigned>(cus) * 16u), dim3(kBlock), 0, stream, n,
                      seed, counts);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free simulate
+// ---------------------------------------------------------------------------
+// The device scratch of sse_simulate_noalloc: one parameter set, one chunk,
+// the claim cursor and the pair counter (each at a multiple of 256 bytes),
+// then the pair buffer.  Each GPU the library runs on holds its own copy until the process
+// ends; calls that use it on one GPU at the same time race (the library
+// orders the calls of one context; calls of different contexts on one GPU
+// are the caller's to order).
+constexpr uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+constexpr uint64_t kNoAllocChunkAt = align256(sizeof(TransportParams));
+constexpr uint64_t kNoAllocCursorAt = kNoAllocChunkAt + align256(sizeof(WorkChunk));
+constexpr uint64_t kNoAllocCountAt = kNoAllocCursorAt + 256;
+constexpr uint64_t kNoAllocHeader = kNoAllocCountAt + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+uint64_t noalloc_max_histories() {
+  return transport_batch_max_histories((kNoAllocScratchBytes - kNoAllocHeader) / (kPairWords * sizeof(uint32_t)));
+}
+
+hipError_t launch_transport_noalloc(int device, const TransportParams& p0, hipStream_t stream) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (device >= 0 && device < kMaxDevices) base = g_scratch_ptr[device];
+  }
+  if (!base) return hipErrorNotInitialized;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  TransportParams p = p0;
+  TransportParams* d_item = reinterpret_cast<TransportParams*>(b);
+  WorkChunk* d_chunk = reinterpret_cast<WorkChunk*>(b + kNoAllocChunkAt);
+  uint32_t* d_cursor = reinterpret_cast<uint32_t*>(b + kNoAllocCursorAt);
+  p.pair_count = reinterpret_cast<uint32_t*>(b + kNoAllocCountAt);
+  p.pairs = reinterpret_cast<uint32_t*>(b + kNoAllocHeader);
+  p.pair_cap = (kNoAllocScratchBytes - kNoAllocHeader) / (kPairWords * sizeof(uint32_t));
+  return launch_transport_item(p, d_item, d_chunk, d_cursor, stream);
 }
 
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
