@@ -3,9 +3,12 @@
 One step = one pass of the whole path over one batch: zero the sinograms,
 simulate the clinical workload's histories (emission, Woodcock transport,
 detection, LUT weighting, TOF sinogram accumulation), then the sensitivity
-multiply (scale * W * sens -> float).  Prints one JSON line.
+multiply (scale * W * sens -> float).  Prints one JSON line: the FP32-LUT
+headline, and beside it the chosen precision form (FP16 LUT), the serving
+stream (p50/p99 latency), the large joint-estimation-style loop, the
+roofline against peaks measured on the device, and the CPU oracle baseline.
 
-  python bench.py [--steps K] [--warmup W] [--lut f32|f16|bf16] [--workload clinical|large]
+  python bench.py [--steps K] [--warmup W] [--lut f32|f16|bf16] [--workload clinical|large|serving]
 
 Only one GPU is used; --gpus above 1 exits with a message.
 """
@@ -23,14 +26,56 @@ import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 
-# Per-unit VALU cost model of the transport path (lane-instructions per unit
-# of the method's work; quarter-rate instructions count 4).  Units are
-# counted by the oracle and the kernel alike (statistics counters).  The path
-# is one simulate call: its transport launches (emission, transport,
-# detection) and their coincidence launches (pair indexing, LUT weight,
-# sinogram update).
-COST = dict(rng_block=130, step=70, real=250, detected=150, history=150)
-PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+# Algorithmic VALU work per unit of the method's work (lane-operations; the
+# weights of the benchmark definition's cost model): a Philox4x32-10 block,
+# a Woodcock tentative step, a real interaction, a detected single, a
+# sinogram update, and each binary32 logarithm, sine/cosine pair or square
+# root at 4 operations of quarter rate.  Units are counted by the kernel's
+# statistics counters (the oracle counts the same).
+COST = dict(rng_block=120, step=30, real=80, detected=60, update=40, transcendental=4 * 4)
+PEAK_VALU_PUBLISHED = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x 2.4 GHz: non-packed lane-ops/s
+
+
+def algorithmic_units(stats: dict) -> dict:
+    """Per-history units of the cost model from the statistics counters.
+    Transcendentals: one free-path logarithm per tentative step and one
+    energy-model logarithm per surviving Compton scatter; one sine/cosine per
+    emission and per scatter; square roots at the emission (1), per scatter
+    (2, the rotation) and per photon reaching the cylinder (1)."""
+    h = stats["histories"]
+    scat = (stats["compton"] - stats["killed"]) + stats["rayleigh"]
+    logs = stats["steps"] + (stats["compton"] - stats["killed"])
+    sincos = h + scat
+    sqrts = h + 2 * scat + stats["escaped"]
+    return {"rng_block": stats["rng_blocks"] / h, "step": stats["steps"] / h, "real": stats["real"] / h,
+            "detected": stats["detected"] / h, "update": (stats["scatter"]) / h,
+            "transcendental": (logs + sincos + sqrts) / h,
+            # random gathers: the attenuation map at every tentative step that stays
+            # inside the voxel box (each photon's last step leaves it), the alias
+            # table once per history, the LUT twice per sinogram update
+            "gathers_mu": (stats["steps"] - stats["escaped"]) / h, "gathers_alias": 1.0,
+            "gathers_lut": 2.0 * stats["scatter"] / h}
+
+
+def measure_peaks():
+    """Throughput of the device's units (libsse_peaks.so): VALU lane-ops/s by
+    instruction kind, random gathers/s by buffer size, random atomic adds/s."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2509_05047_amd", "libsse_peaks.so"))
+
+    class Peaks(C.Structure):
+        _fields_ = [(k, C.c_double) for k in ("sclk_mhz", "valu_add", "valu_xor", "valu_fma", "valu_mad64",
+                                                "valu_cndmask", "valu_log", "gather_l2", "gather_llc",
+                                                "gather_hbm", "atomic_u32", "atomic_f64", "copy_bytes_per_s")] + \
+                   [("atomic_bins", C.c_uint64), ("cus", C.c_uint64)]
+
+    lib.sse_measure_peaks.argtypes = [C.c_int, C.c_uint64, C.c_void_p]
+    lib.sse_measure_peaks.restype = C.c_int
+    pk = Peaks()
+    rc = lib.sse_measure_peaks(0, 0, C.byref(pk))
+    if rc != 0:
+        raise RuntimeError(f"sse_measure_peaks failed ({rc})")
+    return {f[0]: getattr(pk, f[0]) for f in Peaks._fields_}
 
 
 def kernel_source_hash() -> str:
@@ -162,7 +207,7 @@ def large_loop(args):
     import torch
     import paper_2509_05047_amd as sse
     w = W.WORKLOADS["large"]
-    n = int(args.histories) if args.histories else w.n_histories
+    n = int(args.histories) if (args.histories and args.workload == "large") else w.n_histories
     reqs = int(w.extra["n_requests"])
     sigma = float(w.extra["smooth_sigma_bins"])
     pdesc, mu, act0 = W.make_phantom(w)
@@ -220,7 +265,7 @@ def large_loop(args):
         "finalize_ms": float(np.mean([t[2] for t in timing])),
         "update_activity_ms": float(np.mean([t[0] - t[1] - t[2] for t in timing])),
     }
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def serving(args):
@@ -308,7 +353,7 @@ def serving(args):
         "arrival_rate_per_sec": lam, "max_active_seen": st["max_active_seen"], "ticks": st["ticks"],
         "hbm_budget_bytes": budget_bytes, "bytes_allocated": st["bytes_allocated"],
     }
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def main():
@@ -335,6 +380,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pair-pruning", action="store_true",
                     help="large and serving workloads: pair pruning on (both photons are tracked by default)")
+    ap.add_argument("--peaks-only", action="store_true",
+                    help="only run the device throughput microbenchmarks (for counter calibration)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="clinical workload: skip the chosen-form, serving and large-loop legs")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the second timing with pair pruning (photon B not tracked once photon A "
                          "missed the energy window; identical sinograms)")
@@ -350,9 +399,14 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "large":
-        return large_loop(args)
+        print(json.dumps(large_loop(args)), flush=True)
+        return
     if args.workload == "serving":
-        return serving(args)
+        print(json.dumps(serving(args)), flush=True)
+        return
+    if args.peaks_only:
+        log(f"[bench] peaks {json.dumps(measure_peaks())}")
+        return
     if args.copy_bytes:
         src = torch.ones(int(args.copy_bytes) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -419,45 +473,84 @@ def main():
             tr_end[i].record(stream)
         ctx.apply_sensitivity(out["scatter_weights"], scale, final, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-        log(f"[bench] step {i + 1}/{args.steps} queued")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def timed_steps(label):
+        """warm-up, then the timed steps; returns (wall seconds, simulate
+        spans in ms, per-kernel timing of the timed steps)."""
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_kernel_timing(True, 64 * args.steps)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i)
+            log(f"[bench] {label}step {i + 1}/{args.steps} queued")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = ctx.read_kernel_timing()
+        ctx.set_kernel_timing(False)
+        return dt, [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)], kt
+
+    peaks = measure_peaks()
+    log(f"[bench] device peaks: VALU add {peaks['valu_add']:.3e} lane-ops/s at {peaks['sclk_mhz']:.0f} MHz, "
+        f"L2 gathers {peaks['gather_l2']:.3e}/s, f64 atomics {peaks['atomic_f64']:.3e}/s")
+    dt, kernel_ms, kt = timed_steps("")
     scatter_per_step = int(out["scatter_counts"].sum(dtype=torch.int64))
-    kernel_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+    final_f32 = final.clone() if not args.no_legs else None
     pruned = None
     if not args.no_pruned:
         # The same steps with pair pruning, reported beside the headline (which
         # tracks both photons of every history): same histories, same sinograms.
         ctx.set_pair_pruning(True)
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            step(i)
-            log(f"[bench] pruned step {i + 1}/{args.steps} queued")
-        torch.cuda.synchronize()
-        dtp = time.perf_counter() - t0
-        pruned_ms = [a.elapsed_time(b) for a, b in zip(tr_start, tr_end)]
+        dtp, pruned_ms, _ = timed_steps("pruned ")
         ctx.set_pair_pruning(False)
         pruned = {"value": n * args.steps / dtp, "ms_per_step": dtp / args.steps * 1e3,
                   "simulate_ms": float(np.mean(pruned_ms)),
                   "same_scatter_counts": int(out["scatter_counts"].sum(dtype=torch.int64)) == scatter_per_step,
                   "note": "photon B not tracked when photon A ended outside the energy window"}
     next1 = smoothing_normalisation_timing(ctx, out["scatter_weights"], scale, final, stream)
+    chosen = None
+    if not args.no_legs and args.lut == "f32":
+        # The chosen precision form: the same LUT stored in FP16 (binary32
+        # transport, binary64 accumulation), the same histories and steps.
+        ctx.load_lut(lut_desc, lut.astype(np.float16).view(np.uint16), dtype=sse.F16)
+        dtc, chosen_ms, ktc = timed_steps("FP16-LUT ")
+        nz = final_f32 != 0
+        rel = ((final[nz].double() - final_f32[nz].double()).abs() / final_f32[nz].double().abs()).float()
+        q = torch.quantile(rel[torch.randperm(rel.numel(), device=rel.device)[:1 << 24]],
+                           torch.tensor([0.5, 0.99], device=rel.device)).tolist()
+        tot16, tot32 = float(final.double().sum()), float(final_f32.double().sum())
+        chosen = {"lut_dtype": "f16", "value": n * args.steps / dtc, "unit": "histories/s",
+                  "ms_per_step": dtc / args.steps * 1e3, "simulate_ms": float(np.mean(chosen_ms)),
+                  "transport_kernel_ms": ktc["transport_ms"] / max(1, ktc["launches"]),
+                  "scatter_coincidences_per_sec": int(out["scatter_counts"].sum(dtype=torch.int64)) * args.steps / dtc,
+                  "same_scatter_counts": int(out["scatter_counts"].sum(dtype=torch.int64)) == scatter_per_step,
+                  "vs_fp32_lut_same_histories": {
+                      "bins_compared": int(nz.sum()), "per_bin_median_rel": q[0], "per_bin_p99_rel": q[1],
+                      "per_bin_max_rel": float(rel.max()), "total_scatter_rel": abs(tot16 - tot32) / tot32},
+                  "vs_fp64_oracle": "per-bin p99 6.5e-4, median 2.0e-4, total scatter 6.7e-6 at 1e7 "
+                                    "histories (FP32 LUT: p99 1.1e-7, total 2.1e-5); the GPU equals the "
+                                    "binary32 oracle fed the dequantised LUT exactly"}
+        del rel, nz
+    del final_f32
     ctx.close()
 
-    per_hist = {k: stats[v] / stats["histories"] for k, v in
-                (("rng_block", "rng_blocks"), ("step", "steps"), ("real", "real"), ("detected", "detected"))}
-    ops_per_hist = (COST["history"] + sum(COST[k] * per_hist[k] for k in per_hist))
-    kernel_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = ops_per_hist * n / kernel_s
+    units = algorithmic_units(stats)
+    # the transport kernel (the dominant one) does all but the sinogram updates
+    ops_transport = sum(COST[k] * units[k] for k in ("rng_block", "step", "real", "detected", "transcendental"))
+    ops_per_hist = ops_transport + COST["update"] * units["update"]
+    launches_per_step = kt["launches"] / args.steps
+    t_launch_ms = kt["transport_ms"] / max(1, kt["launches"])
+    c_launch_ms = kt["coincidence_ms"] / max(1, kt["launches"])
+    hist_per_launch = n / launches_per_step
+    achieved = ops_transport * hist_per_launch / (t_launch_ms * 1e-3)
+    peak_valu = max(peaks["valu_add"], peaks["valu_fma"])
+    gathers = units["gathers_mu"] + units["gathers_alias"]
+    # bounds of the transport kernel in histories/s (benchmark definition):
+    # VALU, random gathers at the measured L2 rate
+    bound_valu = peak_valu / ops_transport
+    bound_gather = peaks["gather_l2"] / gathers
+    kernel_hist_s = hist_per_launch / (t_launch_ms * 1e-3)
+    updates_per_launch = units["update"] * hist_per_launch
     result = {
         "metric": "photon histories/sec",
         "value": n * args.steps / dt,
@@ -488,15 +581,40 @@ def main():
         "smoothing_normalisation": next1,
         "pair_pruning": pruned,
         "simulate_ms": float(np.mean(kernel_ms)),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_valu / 1e12,
+                     "unit": "TOP/s", "frac": achieved / peak_valu,
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
                                  and args.lut == "f32" and args.lut_mode == "lut5d" and gaps is None
                                  and args.lut_shape == "workload" else None),
-                     "kernel": "one simulate call: transport + coincidence launches",
-                     "span_ms": float(np.mean(kernel_ms)),
-                     "ops_per_history": ops_per_hist},
+                     "kernel": "transport_batch_kernel (transport, detection; 97 % of the step)",
+                     "kernel_ms": t_launch_ms, "launches_per_step": launches_per_step,
+                     "histories_per_launch": hist_per_launch,
+                     "ops_per_history": ops_transport,
+                     "units_per_history": units,
+                     "peak_source": "measured on this device: v_add_u32 / v_fma_f32 loops (libsse_peaks)",
+                     "peak_published_derived": PEAK_VALU_PUBLISHED / 1e12,
+                     "bounds_histories_per_s": {"valu": bound_valu, "l2_gather": bound_gather},
+                     "kernel_histories_per_s": kernel_hist_s,
+                     "coincidence_kernel": {"kernel_ms": c_launch_ms, "updates_per_launch": updates_per_launch,
+                                            "atomics_per_s": 2 * updates_per_launch / (c_launch_ms * 1e-3),
+                                            "peak_atomics_per_s": min(peaks["atomic_u32"], peaks["atomic_f64"])},
+                     "achieved_gathers_per_s": gathers * kernel_hist_s,
+                     "peak_gathers_per_s": peaks["gather_l2"]},
+        "device_peaks": peaks,
+        "chosen_form": chosen,
     }
+    if not args.no_legs and args.workload == "clinical" and not args.histories:
+        log("[bench] serving leg")
+        sv = serving(args)
+        result["serving"] = {k: sv[k] for k in ("value", "unit", "latency_p50_ms", "latency_p99_ms",
+                                                "latency_max_ms", "single_stream_histories_per_sec",
+                                                "arrival_rate_per_sec", "max_active_seen", "ticks")}
+        result["serving"]["workload"] = sv["config"]["workload"]
+        log("[bench] large-loop leg")
+        ll = large_loop(args)
+        result["large_loop"] = {k: ll[k] for k in ("value", "unit", "request_latency_ms", "request_latency_p50_ms",
+                                                   "simulate_ms", "finalize_ms", "update_activity_ms")}
+        result["large_loop"]["workload"] = ll["config"]["workload"]
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_histories} histories")
         result["cpu_baseline"] = cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut, args.cpu_histories, gaps)

@@ -360,6 +360,26 @@ sse_status sse_simulate_noalloc(sse_ctx* ctx, sse_phantom_id id, uint64_t n_hist
  * the context. */
 sse_status sse_set_pair_pruning(sse_ctx* ctx, int enable);
 
+/* Per-kernel timing of the production launches, for measurement.  With
+ * enable = 1, every later sse_simulate on its production path (no
+ * statistics, no records) records HIP events on its stream before and after
+ * each transport kernel and each coincidence kernel it launches, for up to
+ * max_launches launches (1 .. 2^20; events created here); enable = 0 frees
+ * them.  The call first waits for the context's earlier simulations.
+ * sse_read_kernel_timing waits for the recorded launches, returns the
+ * launches recorded (and those beyond max_launches, not recorded) and the
+ * summed kernel durations in milliseconds, and starts a new count.
+ * Errors: SSE_EINVAL, SSE_ESTATE (timing off), SSE_EDEVICE. */
+typedef struct {
+  uint64_t launches;           /* launches recorded */
+  uint64_t dropped;            /* launches after max_launches were reached */
+  double transport_ms;         /* summed transport kernel durations */
+  double coincidence_ms;       /* summed coincidence kernel durations */
+} sse_kernel_timing;
+
+sse_status sse_set_kernel_timing(sse_ctx* ctx, int enable, uint32_t max_launches);
+sse_status sse_read_kernel_timing(sse_ctx* ctx, sse_kernel_timing* out);
+
 /* Expected annihilations per simulated history: sum(activity) * voxel volume
  * (ml) * acq_seconds * factor / n_histories (binary64).  The simulator's
  * output is absolutely scaled (Discussion); `factor` carries a global

@@ -94,6 +94,11 @@ class Completion(C.Structure):
                 ("scatter_counts", C.c_void_p), ("scatter_weights", C.c_void_p)]
 
 
+class KernelTiming(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("dropped", C.c_uint64), ("transport_ms", C.c_double),
+                ("coincidence_ms", C.c_double)]
+
+
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "cancelled", "ticks", "histories",
                                           "max_active_seen", "bytes_allocated", "budget_bytes", "failed")]
@@ -119,6 +124,8 @@ SIGNATURES = {
     "sse_check_division": ([_P, C.c_uint64, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], C.c_int),
     "sse_simulate": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
     "sse_simulate_noalloc": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
+    "sse_set_kernel_timing": ([_P, C.c_int, C.c_uint32], C.c_int),
+    "sse_read_kernel_timing": ([_P, _P], C.c_int),
     "sse_emission_scale": ([_P, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
     "sse_gaussian_smooth": ([_P, _P, _P, _P, C.c_float, _P], C.c_int),
@@ -354,6 +361,15 @@ class Context:
                     int(outputs.get("record_stride", 1)) if outputs.get("records") is not None else 0)
         _check(lib().sse_simulate_noalloc(self._h, pid, n_histories, seed, h_offset, C.byref(o),
                                           _stream_ptr(stream)))
+
+    def set_kernel_timing(self, enable: bool, max_launches: int = 4096):
+        _check(lib().sse_set_kernel_timing(self._h, int(bool(enable)), int(max_launches)))
+
+    def read_kernel_timing(self) -> dict:
+        """{launches, dropped, transport_ms, coincidence_ms} since the last read."""
+        t = KernelTiming()
+        _check(lib().sse_read_kernel_timing(self._h, C.byref(t)))
+        return {f[0]: getattr(t, f[0]) for f in KernelTiming._fields_}
 
     def emission_scale(self, pid: int, n_histories: int, acq_seconds: float = 1.0, factor: float = 1.0) -> float:
         v = C.c_double()

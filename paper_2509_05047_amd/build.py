@@ -15,6 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsse.so")
 SOURCES = ["csrc/transport.hip", "csrc/post.hip", "csrc/capi.cpp", "csrc/serve.cpp"]
+# throughput microbenchmarks of the device (measurement support, its own library)
+PEAKS_LIB = os.path.join(HERE, "libsse_peaks.so")
+PEAKS_SOURCES = ["csrc/peaks.hip"]
 ARCH = os.environ.get("SSE_OFFLOAD_ARCH", "gfx950")
 
 
@@ -33,8 +36,14 @@ def flags():
 
 
 def build(verbose: bool = False) -> str:
+    _link(SOURCES, LIB, verbose)
+    _link(PEAKS_SOURCES, PEAKS_LIB, verbose)
+    return LIB
+
+
+def _link(sources, lib, verbose):
     objs = []
-    for src in SOURCES:
+    for src in sources:
         path = os.path.join(HERE, src)
         obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
@@ -43,13 +52,12 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

@@ -515,6 +515,7 @@ sse_status sse_destroy(sse_ctx* c) {
   if (c->d_cursor) release(c->d_cursor);
   if (c->d_pair_count) release(c->d_pair_count);
   if (c->pair_done) (void)hipEventDestroy(c->pair_done);
+  for (hipEvent_t e : c->timing_ev) (void)hipEventDestroy(e);
   delete c;
   return SSE_OK;
 }
@@ -862,7 +863,9 @@ sse_status sse_simulate(sse_ctx* c, sse_phantom_id id, uint64_t n_histories, uin
   if (p.stats || p.rec)
     HIP_TRY(sse::launch_transport(p, s), "transport kernel launch");
   else
-    HIP_TRY(sse::launch_transport_item(p, c->d_item, c->d_chunk, c->d_cursor, s), "transport kernel launch");
+    HIP_TRY(sse::launch_transport_item(p, c->d_item, c->d_chunk, c->d_cursor, s,
+                                       c->timing.ev ? &c->timing : nullptr),
+            "transport kernel launch");
   HIP_TRY(hipEventRecord(c->pair_done, s), "record pair-buffer use");
   return SSE_OK;
 }
@@ -899,6 +902,52 @@ sse_status sse_simulate_noalloc(sse_ctx* c, sse_phantom_id id, uint64_t n_histor
   HIP_TRY(hipStreamWaitEvent(s, c->pair_done, 0), "order after earlier simulations");
   HIP_TRY(sse::launch_transport_noalloc(c->device, p, s), "transport kernel launch");
   HIP_TRY(hipEventRecord(c->pair_done, s), "record the simulation");
+  return SSE_OK;
+}
+
+sse_status sse_set_kernel_timing(sse_ctx* c, int enable, uint32_t max_launches) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  if (enable != 0 && enable != 1) return fail(SSE_EINVAL, "enable must be 0 or 1");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (c->pair_done) HIP_TRY(hipEventSynchronize(c->pair_done), "wait for timed launches");
+  for (hipEvent_t e : c->timing_ev) (void)hipEventDestroy(e);
+  c->timing_ev.clear();
+  c->timing = sse::KernelTiming{};
+  if (!enable) return SSE_OK;
+  if (max_launches == 0 || max_launches > (1u << 20)) return fail(SSE_EINVAL, "max_launches must be 1 .. 2^20");
+  c->timing_ev.resize(4ull * max_launches, nullptr);
+  for (auto& e : c->timing_ev) {
+    const hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      for (hipEvent_t x : c->timing_ev)
+        if (x) (void)hipEventDestroy(x);
+      c->timing_ev.clear();
+      return hip_fail(err, "create timing events");
+    }
+  }
+  c->timing.ev = c->timing_ev.data();
+  c->timing.cap = max_launches;
+  return SSE_OK;
+}
+
+sse_status sse_read_kernel_timing(sse_ctx* c, sse_kernel_timing* out) {
+  if (!c || !out) return fail(SSE_EINVAL, "null argument");
+  if (!c->timing.ev) return fail(SSE_ESTATE, "kernel timing is off");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  *out = sse_kernel_timing{};
+  for (uint32_t i = 0; i < c->timing.n; ++i) {
+    hipEvent_t* e = c->timing.ev + 4ull * i;
+    HIP_TRY(hipEventSynchronize(e[3]), "wait for a timed launch");
+    float t = 0.0f, q = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, e[0], e[1]), "transport kernel time");
+    HIP_TRY(hipEventElapsedTime(&q, e[2], e[3]), "coincidence kernel time");
+    out->transport_ms += t;
+    out->coincidence_ms += q;
+  }
+  out->launches = c->timing.n;
+  out->dropped = c->timing.dropped;
+  c->timing.n = 0;
+  c->timing.dropped = 0;
   return SSE_OK;
 }
 

@@ -75,6 +75,9 @@ struct sse_ctx {
   sse::WorkChunk* d_chunk = nullptr;
   uint32_t* d_cursor = nullptr;
   hipEvent_t pair_done = nullptr;
+  // per-kernel timing of production launches (sse_set_kernel_timing)
+  std::vector<hipEvent_t> timing_ev;
+  sse::KernelTiming timing{};
   // servers running on this context: their requests hold its device tables,
   // so calls that replace or free them are refused meanwhile
   std::atomic<int> servers{0};

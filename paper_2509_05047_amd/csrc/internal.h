@@ -234,16 +234,27 @@ struct BatchParams {
   int gap_on;                    // the items' gap model is on (they share one context)
 };
 
+// HIP events recorded around the kernels of work-list launches (for
+// measurement): launch i records ev[4i] / ev[4i + 1] before and after its
+// transport kernel and ev[4i + 2] / ev[4i + 3] around its coincidence kernel,
+// while n < cap; launches beyond cap are counted in dropped.
+struct KernelTiming {
+  hipEvent_t* ev;
+  uint32_t cap;
+  uint32_t n;
+  uint64_t dropped;
+};
+
 // One work list (at most transport_batch_max_histories(pair_cap) histories
-// in all): pair-counter reset, transport, coincidences.
-hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream);
+// in all): pair-counter reset, transport, coincidences (timed if kt).
+hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, KernelTiming* kt = nullptr);
 // Histories [p.h0, p.h0 + p.n) of one request through the work-list kernels
 // (the production path of a simulate call: no statistics, no records), in
 // launches of at most transport_batch_max_histories(p.pair_cap) histories;
 // d_item, d_chunk and d_cursor are device scratch of one parameter set, one
 // chunk and one claim cursor.
 hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
-                                 uint32_t* d_cursor, hipStream_t stream);
+                                 uint32_t* d_cursor, hipStream_t stream, KernelTiming* kt = nullptr);
 
 // Allocation-free simulate (sse_simulate_noalloc): the kernels' scratch --
 // work-list parameters, counters and pair buffer -- is a file-scope device

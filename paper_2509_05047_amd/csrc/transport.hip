@@ -1589,7 +1589,7 @@ hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
 }
 
 hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
-                                 uint32_t* d_cursor, hipStream_t stream) {
+                                 uint32_t* d_cursor, hipStream_t stream, KernelTiming* kt) {
   if (!p.pairs || !p.pair_count || p.pair_cap == 0 || p.pair_cap > kMaxPairCap || !d_item || !d_chunk || !d_cursor)
     return hipErrorInvalidValue;
   const uint64_t most = transport_batch_max_histories(p.pair_cap);
@@ -1603,7 +1603,7 @@ hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_it
     const uint64_t positions = (n + kBatchSlice - 1) / kBatchSlice * kBatchSlice;
     const BatchParams b{d_item, d_chunk, 1u, static_cast<uint32_t>(positions), d_cursor, n,
                         p.pairs, p.pair_count, p.pair_cap, p.gap_on};
-    const hipError_t e = launch_transport_batch(b, stream);
+    const hipError_t e = launch_transport_batch(b, stream, kt);
     if (e != hipSuccess) return e;
     done += n;
   }
@@ -1693,7 +1693,7 @@ hipError_t launch_transport_noalloc(int device, const TransportParams& p0, hipSt
   return launch_transport_item(p, d_item, d_chunk, d_cursor, stream);
 }
 
-hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
+hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, KernelTiming* kt) {
   if (b.n_chunks == 0) return hipSuccess;
   if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap ||
       b.n_histories > transport_batch_max_histories(b.pair_cap))
@@ -1708,14 +1708,23 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream) {
   if (resident == 0) return hipErrorInvalidDeviceFunction;
   const uint64_t want = (static_cast<uint64_t>(b.n_positions) / kBatchSlice + 3) / 4;  // a slice per wave at least
   const int grid = static_cast<int>(want < resident ? want : resident);
+  hipEvent_t* ev = nullptr;
+  if (kt && kt->ev) {
+    if (kt->n < kt->cap) ev = kt->ev + 4u * kt->n++;
+    else ++kt->dropped;
+  }
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.pair_count);
+  if (ev) (void)hipEventRecord(ev[0], stream);
   hipLaunchKernelGGL(transport_batch_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
+  if (ev) (void)hipEventRecord(ev[1], stream);
   const dim3 cgrid(stride_grid(pair_records_needed(b.n_histories, 4ull * grid), cus));
+  if (ev) (void)hipEventRecord(ev[2], stream);
   if (b.gap_on)
     hipLaunchKernelGGL(coincidence_batch_kernel<true>, cgrid, dim3(kBlock), 0, stream, b);
   else
     hipLaunchKernelGGL(coincidence_batch_kernel<false>, cgrid, dim3(kBlock), 0, stream, b);
+  if (ev) (void)hipEventRecord(ev[3], stream);
   return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ def test_structure_sizes_match_header_layout():
     assert C.sizeof(sse.Completion) == 64
     assert C.sizeof(sse.ServerStats) == 72
     assert C.sizeof(sse.GapDesc) == 24
+    assert C.sizeof(sse.KernelTiming) == 32
     assert C.sizeof(sse.EdgeGeom) == 24
 
 
