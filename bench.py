@@ -89,10 +89,9 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes of one simulate call (all its transport and coincidence
-    launches) from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
-    calibrated by a plain copy), or None when the kernels have changed since
-    the counters were taken."""
+    """HBM bytes of one launch of the transport kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy),
+    or None when the kernels have changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", "transport_clinical_hbm_counters.md")
     try:
@@ -102,7 +101,7 @@ def measured_traffic():
     fields = dict(re.findall(r"^(\w+): (\S+)$", text, flags=re.M))
     if fields.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return float(fields["fetch_bytes_per_step"]) + float(fields["write_bytes_per_step"])
+    return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
 
 
 # The paper's smoothing of the scatter estimate: FWHM [9, 6, 10.5] radial,
