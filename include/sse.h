@@ -394,6 +394,18 @@ sse_status sse_emission_scale(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histor
 sse_status sse_apply_sensitivity(sse_ctx* ctx, const double* W, double scale, float* out,
                                  void* stream);
 
+/* Total scatter of the estimate in binary64: total[0] = sum over bins of
+ * (scale * W[b]) * sens[b] (the sensitivity broadcast over TOF when it has
+ * no TOF axis), reduced on the device in a fixed order, so repeated calls
+ * give the same bits.  With a smoothed estimate the paper's smoothing keeps
+ * the total of the LUT scatter but not of its product with the
+ * sensitivity; this is the total of the unsmoothed estimate (Methods,
+ * "Scatter sensitivity sinogram": the LUT scatter times the sensitivity is
+ * the absolutely scaled scatter estimate).  W: device, n_bins binary64;
+ * total: device, one binary64 (caller-owned).  Asynchronous on stream.
+ * Errors: SSE_EINVAL, SSE_ESTATE (no sensitivity), SSE_ENOMEM. */
+sse_status sse_total_scatter(sse_ctx* ctx, const double* W, double scale, double* total, void* stream);
+
 /* Separable Gaussian smoothing of a float sinogram (device, n_bins each;
  * in == out allowed) with sigma_bins = {radial, view, plane} (0 skips an
  * axis), kernel truncated at floor(truncate * sigma + 0.5) bins and

@@ -33,6 +33,18 @@ def apply_sensitivity(weights: np.ndarray, scale: float, sens: np.ndarray) -> np
     return ((scale * w) * s).astype(np.float32)
 
 
+def total_scatter(weights: np.ndarray, scale: float, sens: np.ndarray) -> float:
+    """Total of the estimate: the sum over bins of the binary64 products
+    (scale * W) * sens, summed exactly and rounded once (math.fsum).  ``sens``
+    as in apply_sensitivity."""
+    import math
+    w = np.asarray(weights, np.float64)
+    s = np.asarray(sens, np.float64)
+    if s.ndim == w.ndim - 1:
+        s = s[None]
+    return math.fsum(((scale * w) * s).ravel().tolist())
+
+
 def gaussian_kernel(sigma: float, truncate: float = 4.0):
     radius = int(truncate * sigma + 0.5)
     x = np.arange(-radius, radius + 1, dtype=np.float64)

@@ -128,6 +128,7 @@ SIGNATURES = {
     "sse_read_kernel_timing": ([_P, _P], C.c_int),
     "sse_emission_scale": ([_P, C.c_uint32, C.c_uint64, C.c_double, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "sse_apply_sensitivity": ([_P, _P, C.c_double, _P, _P], C.c_int),
+    "sse_total_scatter": ([_P, _P, C.c_double, _P, _P], C.c_int),
     "sse_gaussian_smooth": ([_P, _P, _P, _P, C.c_float, _P], C.c_int),
     "sse_finalize": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
     "sse_smoothing_normalisation": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
@@ -378,6 +379,14 @@ class Context:
 
     def apply_sensitivity(self, weights, scale: float, out, stream=None):
         _check(lib().sse_apply_sensitivity(self._h, _ptr(weights), scale, _ptr(out), _stream_ptr(stream)))
+
+    def total_scatter(self, weights, scale: float, stream=None):
+        """Binary64 total of scale * W * sens, reduced on the device; returns
+        a one-element float64 device tensor."""
+        import torch
+        t = torch.empty(1, dtype=torch.float64, device=torch.device("cuda", self.device))
+        _check(lib().sse_total_scatter(self._h, _ptr(weights), scale, _ptr(t), _stream_ptr(stream)))
+        return t
 
     def gaussian_smooth(self, x, out, sigma_bins, truncate: float = 4.0, stream=None):
         s = (C.c_float * 3)(*sigma_bins)

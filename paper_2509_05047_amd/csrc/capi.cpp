@@ -509,6 +509,7 @@ sse_status sse_destroy(sse_ctx* c) {
   for (float* e : c->d_edge) release(e);
   for (auto* s : c->d_scratch)
     if (s) release(s);
+  if (c->d_partials) release(c->d_partials);
   if (c->d_pairs) release(c->d_pairs);
   if (c->d_item) release(c->d_item);
   if (c->d_chunk) release(c->d_chunk);
@@ -971,6 +972,21 @@ sse_status sse_apply_sensitivity(sse_ctx* c, const double* W, double scale, floa
   HIP_TRY(sse::launch_apply_sensitivity(post_params(c), W, scale, c->d_sens, c->sens_tof, out,
                                         static_cast<hipStream_t>(stream)),
           "sensitivity kernel");
+  return SSE_OK;
+}
+
+sse_status sse_total_scatter(sse_ctx* c, const double* W, double scale, double* total, void* stream) {
+  if (!c || !W || !total) return fail(SSE_EINVAL, "null argument");
+  if (!c->d_sens) return fail(SSE_ESTATE, "no sensitivity sinogram loaded");
+  if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
+  if (reinterpret_cast<uintptr_t>(W) % 8 || reinterpret_cast<uintptr_t>(total) % 8)
+    return fail(SSE_EINVAL, "misaligned buffer");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (!c->d_partials)
+    HIP_TRY(hipMalloc(&c->d_partials, sse::kTotalPartials * sizeof(double)), "allocate reduction scratch");
+  HIP_TRY(sse::launch_total_scatter(post_params(c), W, scale, c->d_sens, c->sens_tof, c->d_partials, total,
+                                    static_cast<hipStream_t>(stream)),
+          "total-scatter kernels");
   return SSE_OK;
 }
 

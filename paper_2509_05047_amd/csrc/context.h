@@ -63,6 +63,7 @@ struct sse_ctx {
   // always track both photons)
   int prune_b = 0;
   float* d_scratch[2] = {nullptr, nullptr};
+  double* d_partials = nullptr;  // the total-scatter reduction's partial sums
   // pair buffer of the transport -> coincidence hand-over (kPairWords words
   // per pair), its counter, and an event after its last use so that a call
   // on another stream waits for it

@@ -29,6 +29,11 @@ struct Taps {
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
                               const float* norm_in, float* out, const Taps& taps, const float* norm_out,
                               const float* sens, int sens_tof, hipStream_t stream);
+// total[0] = sum over bins of (scale * W) * sens in binary64, in a fixed
+// order (partial: device scratch of kTotalPartials doubles).
+constexpr int kTotalPartials = 1024;
+hipError_t launch_total_scatter(const PostParams& g, const double* W, double scale, const float* sens, int sens_tof,
+                                double* partial, double* total, hipStream_t stream);
 // norm[b] = G[b] / S[b] with S = float(scale * W[b]), or 1 where S or G is
 // not positive (norm holds G on entry).
 hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale, float* norm, hipStream_t stream);

@@ -30,6 +30,48 @@ __global__ void __launch_bounds__(256) apply_sens_kernel(const double* __restric
     out[base + j] = static_cast<float>((scale * W[base + j]) * static_cast<double>(sens[sbase + j]));
 }
 
+// Total of the estimate scale * W * sens in binary64 (sens broadcast over
+// TOF when it has no TOF axis), in a fixed order: block b sums the bins of
+// its contiguous chunk, thread k those at offsets k, k + 256, ... in turn,
+// then a tree over the block's threads; total_final sums the kTotalBlocks
+// partial sums by the same tree.  The order depends only on n, so the
+// result is the same bits on every run.
+constexpr int kTotalBlocks = 1024;
+
+__device__ __forceinline__ double block_tree_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (unsigned w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(256) total_partial_kernel(const double* __restrict__ W, double scale,
+                                                             const float* __restrict__ sens, uint64_t n,
+                                                             uint64_t inner, int sens_tof,
+                                                             double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const uint64_t chunk = (n + kTotalBlocks - 1) / kTotalBlocks;
+  const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * chunk;
+  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+  double acc = 0.0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double sv = static_cast<double>(sens[sens_tof ? i : i % inner]);
+    acc += (scale * W[i]) * sv;
+  }
+  const double t = block_tree_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(1024) total_final_kernel(const double* __restrict__ partial,
+                                                           double* __restrict__ total) {
+  __shared__ double sh[kTotalBlocks];
+  const double t = block_tree_sum(partial[threadIdx.x], sh);
+  if (threadIdx.x == 0) *total = t;
+}
+
 __device__ __forceinline__ int reflect(int i, int n) {
   const int period = 2 * n;
   int m = i % period;
@@ -323,6 +365,16 @@ hipError_t launch_apply_sensitivity(const PostParams& g, const double* W, double
   const uint64_t inner = inner_bins(g);
   hipLaunchKernelGGL(apply_sens_kernel, dim3(blocks_for(inner), g.n_tof), dim3(256), 0, stream, W, scale, sens, inner,
                      sens_tof, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_total_scatter(const PostParams& g, const double* W, double scale, const float* sens, int sens_tof,
+                                double* partial, double* total, hipStream_t stream) {
+  const uint64_t inner = static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane;
+  const uint64_t n = inner * static_cast<uint64_t>(g.n_tof);
+  hipLaunchKernelGGL(total_partial_kernel, dim3(kTotalBlocks), dim3(256), 0, stream, W, scale, sens, n, inner,
+                     sens_tof, partial);
+  hipLaunchKernelGGL(total_final_kernel, dim3(1), dim3(kTotalBlocks), 0, stream, partial, total);
   return hipGetLastError();
 }
 

@@ -129,3 +129,18 @@ def test_normalisation_removes_and_restores_detector_structure():
     err_norm = np.abs(norm_est / target - 1).max()
     err_plain = np.abs(plain_est / target - 1).max()
     assert err_norm < 0.2 * err_plain, (err_norm, err_plain)
+
+
+def test_total_scatter_is_the_exact_sum_of_the_products():
+    """Integer-valued products sum exactly; a sum whose naive order loses
+    the small terms keeps them; the TOF broadcast of a sensitivity without
+    TOF axis equals the full-shape sensitivity."""
+    rng = np.random.default_rng(4)
+    w = rng.integers(0, 1000, (3, 2, 4, 5)).astype(np.float64)
+    sens = rng.integers(1, 4, (2, 4, 5)).astype(np.float64)
+    assert post.total_scatter(w, 2.0, sens) == float((2 * w * sens[None]).sum())
+    big = np.zeros((1, 1, 1, 4))
+    big[0, 0, 0] = [1e16, 1.0, -1e16, 1.0]
+    assert post.total_scatter(big, 1.0, np.ones((1, 1, 4))) == 2.0
+    full = np.broadcast_to(sens[None], w.shape)
+    assert post.total_scatter(w, 0.37, sens) == post.total_scatter(w, 0.37, full)
