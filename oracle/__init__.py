@@ -105,6 +105,13 @@ def _lib(variant: str = "f32"):
         lib.orc_edge_paths.argtypes = [_P, C.c_double, C.c_double, _P, _P]
         lib.orc_edge_prob.argtypes = [_P, C.c_double, C.c_double]
         lib.orc_edge_prob.restype = C.c_double
+        lib.orc_recon_lor_table.argtypes = [C.c_int32, C.c_int32, _P, _P]
+        lib.orc_recon_project.argtypes = [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int]
+        lib.orc_recon_project.restype = C.c_int
+        lib.orc_recon_backproject.argtypes = [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int]
+        lib.orc_recon_backproject.restype = C.c_int
+        lib.orc_recon_osem.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int, C.c_int]
+        lib.orc_recon_osem.restype = C.c_int
         lib.orc_rotate.argtypes = [_P, C.c_double, C.c_double, C.c_double, _P]
         lib.orc_transport_photons.argtypes = [_P, _P, _P, _P, C.c_uint64, C.c_uint64, _P, _P, C.c_double, _P]
         lib.orc_transport_photons.restype = C.c_int
@@ -310,6 +317,59 @@ def transport_photons(scanner, physics, pdesc, mu, p0, d, e_kev, seed=1, variant
                                            _ptr(p0), _ptr(d), float(e_kev), _ptr(out)) != 0:
         raise ValueError("oracle rejected its arguments")
     return out
+
+
+# --------------------------------------------------------------------------
+# reconstruction (the estimation loop's TOF-OSEM; binary64)
+# --------------------------------------------------------------------------
+
+def recon_lor_table(n_crystals, n_rad):
+    """(a, b): for each (view, rad) the crystal pair the simulator bins there,
+    a the TOF-positive end; -1 where none.  Shape (n_view, n_rad)."""
+    nv = n_crystals // 2
+    a = np.zeros(nv * n_rad, np.int32)
+    b = np.zeros(nv * n_rad, np.int32)
+    _lib().orc_recon_lor_table(n_crystals, n_rad, _ptr(a), _ptr(b))
+    return a.reshape(nv, n_rad), b.reshape(nv, n_rad)
+
+
+def _recon_structs(scanner, sino, pdesc):
+    return scanner_struct(scanner), sino_struct(sino), phantom_struct(pdesc)
+
+
+def recon_project(scanner, sino, pdesc, img, tof=True, subset=0, n_subsets=1, out=None):
+    """Forward projection of img ([n_plane][ny][nx]) over the subset's views:
+    TOF sinogram [tof][plane][view][rad] (or [plane][view][rad] with
+    tof=False); bins of other views are zero (or kept from `out`)."""
+    img = np.ascontiguousarray(img, np.float64)
+    shape = (sino.n_tof,) * bool(tof) + (sino.n_plane, sino.n_view, sino.n_rad)
+    out = np.zeros(shape) if out is None else out
+    s = _recon_structs(scanner, sino, pdesc)
+    if _lib().orc_recon_project(*(C.byref(x) for x in s), _ptr(img), _ptr(out), int(tof), subset, n_subsets):
+        raise ValueError("oracle rejected its arguments")
+    return out
+
+
+def recon_backproject(scanner, sino, pdesc, y, tof=True, subset=0, n_subsets=1):
+    """Transpose of recon_project: image [n_plane][ny][nx]."""
+    y = np.ascontiguousarray(y, np.float64)
+    img = np.zeros((sino.n_plane, pdesc.ny, pdesc.nx))
+    s = _recon_structs(scanner, sino, pdesc)
+    if _lib().orc_recon_backproject(*(C.byref(x) for x in s), _ptr(y), _ptr(img), int(tof), subset, n_subsets):
+        raise ValueError("oracle rejected its arguments")
+    return img
+
+
+def recon_osem(scanner, sino, pdesc, prompts, mult, add, img, n_iter=1, n_subsets=1):
+    """TOF-OSEM iterations from img (returns the new image)."""
+    img = np.array(img, np.float64, order="C", copy=True)
+    p = np.ascontiguousarray(prompts, np.float64)
+    m = np.ascontiguousarray(mult, np.float64)
+    a = np.ascontiguousarray(add, np.float64)
+    s = _recon_structs(scanner, sino, pdesc)
+    if _lib().orc_recon_osem(*(C.byref(x) for x in s), _ptr(p), _ptr(m), _ptr(a), _ptr(img), n_iter, n_subsets):
+        raise ValueError("oracle rejected its arguments")
+    return img
 
 
 def real_size(variant="f32") -> int:

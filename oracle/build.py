@@ -1,6 +1,7 @@
 """Build the C oracle (test infrastructure) with gcc.
 
-Two shared libraries come out of the one source file:
+Two shared libraries come out of the sources (sse_oracle.c, and recon.c,
+the reconstruction of the estimation loop, binary64 in both):
   liboracle_f32.so  transport in binary32 (the kernel's precision)
   liboracle_f64.so  transport in binary64
 Flags: -O2, no fast-math, no floating-point contraction, SSE arithmetic
@@ -20,11 +21,12 @@ def lib_path(variant: str) -> str:
 
 def build(verbose: bool = False) -> None:
     src = os.path.join(HERE, "sse_oracle.c")
+    recon = os.path.join(HERE, "recon.c")
     for variant, real in VARIANTS.items():
         out = lib_path(variant)
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
                "-Wall", "-Wextra", "-Wno-unused-parameter", f"-DORACLE_REAL={real}",
-               src, "-o", out + ".tmp", "-lm", "-pthread"]
+               src, recon, "-o", out + ".tmp", "-lm", "-pthread"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -217,6 +217,25 @@ double orc_edge_prob(const orc_edge_geom* g, double theta, double x0);
 int orc_locate(const orc_scanner* sc, const orc_gaps* gaps, float hx, float hy, float hz,
                int32_t out[10], double frac[2]);
 
+/* Reconstruction of the joint estimation loop (recon.c; binary64 whatever
+ * the build): TOF Joseph projector on the simulator's sinogram geometry and
+ * TOF-OSEM.  The image has n_plane slices [plane][y][x] on the transaxial
+ * grid of pd (nx, ny, voxel_mm[0..1], lo_mm[0..1]; pd's nz is not used).
+ * Sinograms [tof][plane][view][rad], or [plane][view][rad] without TOF.
+ * project: bins of the subset's views (view mod n_subsets == subset; all
+ * with n_subsets <= 1) are overwritten, others left; backproject: img is
+ * overwritten with the transpose over the subset's views.  osem: n_iter
+ * iterations of n_subsets subsets in place (mult without TOF axis, prompts
+ * and add with it).  Each returns 0, or -1 on bad arguments.
+ * lor_table: the crystal pair of each (view, rad), TOF-positive end in a. */
+void orc_recon_lor_table(int32_t n_crystals, int32_t n_rad, int32_t* a, int32_t* b);
+int orc_recon_project(const orc_scanner* sc, const orc_sino* sn, const orc_phantom* pd, const double* img,
+                      double* sino, int tof, int subset, int n_subsets);
+int orc_recon_backproject(const orc_scanner* sc, const orc_sino* sn, const orc_phantom* pd, const double* sino,
+                          double* img, int tof, int subset, int n_subsets);
+int orc_recon_osem(const orc_scanner* sc, const orc_sino* sn, const orc_phantom* pd, const double* prompts,
+                   const double* mult, const double* add, double* img, int n_iter, int n_subsets);
+
 /* Compiled-in transport precision: 4 (binary32) or 8 (binary64). */
 int orc_real_size(void);
 
