@@ -450,6 +450,65 @@ sse_status sse_smoothing_normalisation(sse_ctx* ctx, const double* W, double sca
 sse_status sse_finalize_normalised(sse_ctx* ctx, const double* W, double scale, const float* norm,
                                    const float sigma_bins[3], float truncate, float* out, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Reconstruction for the joint activity / scatter estimation loop           */
+/* ------------------------------------------------------------------------ */
+/* The paper estimates scatter iteratively when the activity is unknown:
+ * reconstruct the activity with the current scatter estimate (TOF-OSEM, 1
+ * iteration of 28 subsets per loop iteration), simulate scatter from it with
+ * the known attenuation map, smooth, repeat (Methods, "Unknown activity
+ * distribution, very limited simulation time"); the attenuation sinogram is
+ * a forward projection of the attenuation map (Methods, "Evaluation
+ * metrics").  The projector is not specified in the paper; this one:
+ *  - image: n_plane slices [plane][y][x] of float on the transaxial grid of
+ *    a loaded phantom (`grid`: its nx, ny, voxel and lo in x and y), slice p
+ *    at sinogram plane p;
+ *  - LOR of bin (view, rad): the line joining the centres (azimuth
+ *    2 pi (c + 1/2) / n_crystals on the detection cylinder) of the crystal
+ *    pair the simulator bins there; plane p at the mean z of its two rings;
+ *  - Joseph sampling: one sample per pixel column (row) along the LOR's
+ *    major axis, linear interpolation between the two nearest pixels along
+ *    the minor axis, weight = pixel size / |major direction component|;
+ *  - TOF: a sample at signed distance s from the LOR midpoint towards the
+ *    simulator's TOF-positive crystal adds to TOF bin j with weight
+ *    Phi((hi_j - s) / sigma) - Phi((lo_j - s) / sigma) (sigma the context's
+ *    tof_sigma_mm), for bins within 5 sigma of s; with sigma = 0 the bin
+ *    holding s gets weight 1.
+ * Views are taken in subsets: view v belongs to subset v mod n_subsets.
+ * Binary32 arithmetic.  All pointers device, caller-owned; asynchronous on
+ * stream.  Errors: SSE_EINVAL (null pointers, unknown grid phantom, subset
+ * out of range, tof not 0 / 1, more than 48 TOF bins for the TOF
+ * projector), SSE_ENOMEM. */
+
+/* Forward projection of the subset's views: sino is [tof][plane][view][rad]
+ * (tof = 1) or [plane][view][rad] (tof = 0, the plain line integral); the
+ * bins of other views are not written. */
+sse_status sse_project(sse_ctx* ctx, sse_phantom_id grid, const float* image, float* sino, int tof, int subset,
+                       int n_subsets, void* stream);
+
+/* Back projection (the transpose of sse_project up to the order of binary32
+ * sums) of the subset's views of sino into image (overwritten). */
+sse_status sse_backproject(sse_ctx* ctx, sse_phantom_id grid, const float* sino, float* image, int tof,
+                           int subset, int n_subsets, void* stream);
+
+/* n_iter iterations of TOF-OSEM (Hudson and Larkin 1994) with n_subsets
+ * subsets, in place on image: for each subset s in order,
+ *   image_j <- image_j (P_s^T (m y / (m P_s image + a)))_j / (P_s^T m)_j
+ * with prompts y and additive sinogram a (scatter) of the TOF shape, and the
+ * multiplicative sinogram m (attenuation factors times detector
+ * sensitivity) without TOF axis, shared by the TOF bins.  Ratios with a
+ * non-positive denominator count 0; pixels with zero sensitivity in a subset
+ * keep their value.  The library holds projection scratch for one subset. */
+sse_status sse_osem(sse_ctx* ctx, sse_phantom_id grid, const float* prompts, const float* mult, const float* additive,
+                    float* image, int n_iter, int n_subsets, void* stream);
+
+/* Replace phantom id's activity by a reconstructed image (device, on the
+ * phantom's own transaxial grid, n_plane slices): voxel slice iz takes the
+ * image slice of the plane nearest its centre; negative or non-finite values
+ * count 0.  Then as sse_update_activity (synchronous).  Errors: SSE_EINVAL
+ * (also for an all-zero image), SSE_EBUSY while a server runs. */
+sse_status sse_image_to_activity(sse_ctx* ctx, sse_phantom_id id, const float* image, void* stream);
+
 /* Host helper: the integer alias table the library samples emission voxels
  * with.  Activity is quantised to integer masses q_i summing to n 2^32
  * (q_i = floor(a_i n 2^32 / sum a), remainder to the first largest voxel);

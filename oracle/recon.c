@@ -24,7 +24,11 @@
  *    pixel column (row) at the column's centre, linear interpolation between
  *    the two pixels next to the crossing point along the minor axis (pixels
  *    outside the image count 0), weight = pixel size / |direction component
- *    on the major axis| (the path length per column).
+ *    on the major axis| (the path length per column).  The major axis is
+ *    decided from the crystal indices, not from rounded direction components:
+ *    the LOR of crystals a, b runs at angle pi q / (2 n) with q = (2 k + n)
+ *    mod 2n, k = (a + b + 1) mod n, so x is the major axis when 2q <= n or
+ *    2q >= 3n (x at exactly 45 degrees).
  *  - TOF.  The TOF coordinate of a point of the LOR is its signed distance s
  *    from the LOR's midpoint towards the crystal the simulator takes as the
  *    TOF-positive end, as the simulator's tau = (path_B - path_A) / 2 is for
@@ -72,6 +76,7 @@ typedef struct {
   const orc_phantom* pd;   /* transaxial grid: nx, ny, voxel_mm[0..1], lo_mm[0..1] */
   int32_t* a;
   int32_t* b;
+  int mx;                  /* major axis of the LOR last taken by lor_of: 1 = x */
 } geo_t;
 
 static int geo_init(geo_t* g, const orc_scanner* sc, const orc_sino* sn, const orc_phantom* pd) {
@@ -90,7 +95,7 @@ static void geo_free(geo_t* g) { free(g->a); free(g->b); }
 
 /* LOR of bin (view, rad): midpoint m, unit direction u towards the
  * TOF-positive end; 0 if no crystal pair maps there. */
-static int lor_of(const geo_t* g, int view, int rad, double m[2], double u[2]) {
+static int lor_of(geo_t* g, int view, int rad, double m[2], double u[2]) {
   const int k = view * g->sn->n_rad + rad;
   if (g->a[k] < 0) return 0;
   const double R = g->sc->radius_mm, n = g->sc->n_crystals;
@@ -101,6 +106,8 @@ static int lor_of(const geo_t* g, int view, int rad, double m[2], double u[2]) {
   const double dx = ax - bx, dy = ay - by, len = sqrt(dx * dx + dy * dy);
   u[0] = dx / len;
   u[1] = dy / len;
+  const int nc = g->sc->n_crystals, kk = (g->a[k] + g->b[k] + 1) % nc, q = (2 * kk + nc) % (2 * nc);
+  g->mx = 2 * q <= nc || 2 * q >= 3 * nc;
   return 1;
 }
 
@@ -118,9 +125,7 @@ static double tof_weight(const orc_sino* sn, int j, double s) {
  * path length dl.  Samples run over the columns (major axis x) or rows. */
 typedef struct { int p0, p1; double w0, w1, s, dl; } sample_t;
 
-static int major_x(const double u[2]) { return fabs(u[0]) >= fabs(u[1]); }
-
-static int n_samples(const geo_t* g, const double u[2]) { return major_x(u) ? g->pd->nx : g->pd->ny; }
+static int n_samples(const geo_t* g) { return g->mx ? g->pd->nx : g->pd->ny; }
 
 static void sample(const geo_t* g, const double m[2], const double u[2], int k, sample_t* o) {
   const orc_phantom* pd = g->pd;
@@ -128,7 +133,7 @@ static void sample(const geo_t* g, const double m[2], const double u[2], int k, 
   const double vx = pd->voxel_mm[0], vy = pd->voxel_mm[1], lox = pd->lo_mm[0], loy = pd->lo_mm[1];
   double f;
   int i0, n_minor;
-  if (major_x(u)) {
+  if (g->mx) {
     const double xc = lox + (k + 0.5) * vx;
     o->s = (xc - m[0]) / u[0];
     const double y = m[1] + o->s * u[1];
@@ -148,7 +153,7 @@ static void sample(const geo_t* g, const double m[2], const double u[2], int k, 
   o->w0 = 1.0 - fr;
   o->w1 = fr;
   const int j0 = i0, j1 = i0 + 1;
-  if (major_x(u)) {
+  if (g->mx) {
     o->p0 = (j0 >= 0 && j0 < n_minor) ? j0 * nx + k : -1;
     o->p1 = (j1 >= 0 && j1 < n_minor) ? j1 * nx + k : -1;
   } else {
@@ -176,7 +181,7 @@ int orc_recon_project(const orc_scanner* sc, const orc_sino* sn, const orc_phant
         double m[2], u[2];
         if (!lor_of(&g, v, r, m, u)) continue;
         const double* im = img + (size_t)p * npix;
-        const int ns = n_samples(&g, u);
+        const int ns = n_samples(&g);
         for (int k = 0; k < ns; ++k) {
           sample_t o;
           sample(&g, m, u, k, &o);
@@ -209,7 +214,7 @@ int orc_recon_backproject(const orc_scanner* sc, const orc_sino* sn, const orc_p
         double m[2], u[2];
         if (!lor_of(&g, v, r, m, u)) continue;
         double* im = img + (size_t)p * npix;
-        const int ns = n_samples(&g, u);
+        const int ns = n_samples(&g);
         for (int k = 0; k < ns; ++k) {
           sample_t o;
           sample(&g, m, u, k, &o);

@@ -133,6 +133,10 @@ SIGNATURES = {
     "sse_finalize": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
     "sse_smoothing_normalisation": ([_P, _P, C.c_double, _P, C.c_float, _P, _P], C.c_int),
     "sse_finalize_normalised": ([_P, _P, C.c_double, _P, _P, C.c_float, _P, _P], C.c_int),
+    "sse_project": ([_P, C.c_uint32, _P, _P, C.c_int, C.c_int, C.c_int, _P], C.c_int),
+    "sse_backproject": ([_P, C.c_uint32, _P, _P, C.c_int, C.c_int, C.c_int, _P], C.c_int),
+    "sse_osem": ([_P, C.c_uint32, _P, _P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
+    "sse_image_to_activity": ([_P, C.c_uint32, _P, _P], C.c_int),
     "sse_build_alias_table": ([_P, C.c_uint64, _P, _P], C.c_int),
     "sse_server_start": ([_P, _P, C.POINTER(C.c_void_p)], C.c_int),
     "sse_server_submit": ([_P, _P, C.POINTER(C.c_uint64)], C.c_int),
@@ -379,6 +383,24 @@ class Context:
 
     def apply_sensitivity(self, weights, scale: float, out, stream=None):
         _check(lib().sse_apply_sensitivity(self._h, _ptr(weights), scale, _ptr(out), _stream_ptr(stream)))
+
+    # reconstruction (joint estimation loop): images are [n_plane][ny][nx]
+    # float32 device tensors on the grid of phantom `grid`
+    def project(self, grid: int, image, sino, tof: bool = True, subset: int = 0, n_subsets: int = 1, stream=None):
+        _check(lib().sse_project(self._h, grid, _ptr(image), _ptr(sino), int(bool(tof)), subset, n_subsets,
+                                 _stream_ptr(stream)))
+
+    def backproject(self, grid: int, sino, image, tof: bool = True, subset: int = 0, n_subsets: int = 1,
+                    stream=None):
+        _check(lib().sse_backproject(self._h, grid, _ptr(sino), _ptr(image), int(bool(tof)), subset, n_subsets,
+                                     _stream_ptr(stream)))
+
+    def osem(self, grid: int, prompts, mult, additive, image, n_iter: int = 1, n_subsets: int = 1, stream=None):
+        _check(lib().sse_osem(self._h, grid, _ptr(prompts), _ptr(mult), _ptr(additive), _ptr(image), n_iter,
+                              n_subsets, _stream_ptr(stream)))
+
+    def image_to_activity(self, pid: int, image, stream=None):
+        _check(lib().sse_image_to_activity(self._h, pid, _ptr(image), _stream_ptr(stream)))
 
     def total_scatter(self, weights, scale: float, stream=None):
         """Binary64 total of scale * W * sens, reduced on the device; returns

@@ -14,7 +14,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsse.so")
-SOURCES = ["csrc/transport.hip", "csrc/post.hip", "csrc/capi.cpp", "csrc/serve.cpp"]
+SOURCES = ["csrc/transport.hip", "csrc/post.hip", "csrc/recon.hip", "csrc/capi.cpp", "csrc/serve.cpp",
+           "csrc/recon_api.cpp"]
 # throughput microbenchmarks of the device (measurement support, its own library)
 PEAKS_LIB = os.path.join(HERE, "libsse_peaks.so")
 PEAKS_SOURCES = ["csrc/peaks.hip"]

@@ -510,6 +510,12 @@ sse_status sse_destroy(sse_ctx* c) {
   for (auto* s : c->d_scratch)
     if (s) release(s);
   if (c->d_partials) release(c->d_partials);
+  release(c->d_lor);
+  release(c->d_view);
+  release(c->d_major);
+  release(c->d_recon_fp);
+  release(c->d_recon_img[0]);
+  release(c->d_recon_img[1]);
   if (c->d_pairs) release(c->d_pairs);
   if (c->d_item) release(c->d_item);
   if (c->d_chunk) release(c->d_chunk);

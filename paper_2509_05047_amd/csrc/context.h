@@ -64,6 +64,14 @@ struct sse_ctx {
   int prune_b = 0;
   float* d_scratch[2] = {nullptr, nullptr};
   double* d_partials = nullptr;  // the total-scatter reduction's partial sums
+  // reconstruction: LOR and view tables of the projector, OSEM scratch
+  void* d_lor = nullptr;
+  void* d_view = nullptr;
+  void* d_major = nullptr;
+  float* d_recon_fp = nullptr;
+  uint64_t recon_fp_cap = 0;
+  float* d_recon_img[2] = {nullptr, nullptr};
+  uint64_t recon_img_cap = 0;
   // pair buffer of the transport -> coincidence hand-over (kPairWords words
   // per pair), its counter, and an event after its last use so that a call
   // on another stream waits for it

@@ -1,0 +1,51 @@
+// Declarations of the reconstruction kernels of the estimation loop (TOF
+// Joseph projector, its transpose, OSEM update), shared by the library's
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sse {
+
+// Geometry of one projection: the image grid (nx x ny pixels of vx x vy mm
+// from (lox, loy), one slice per sinogram plane), the sinogram, the LOR table
+// lor[view * n_rad + rad] = (midpoint x, y, unit direction x, y towards the
+// TOF-positive crystal; direction 0 where no crystal pair maps) with its
+// major axis decided from the crystal indices (see recon.hip), and the
+// views taken: subset + sv * n_subsets for sv in [0, n_sv).  view_tab[view]
+// = (normal x, y of the view's centre LOR, +-1 so that the radial index
+// grows with the signed distance along that normal, 0) and the window
+// parameters of the back projector's search (see recon.hip).
+struct ReconGeom {
+  int n_rad, n_view, n_plane, n_tof;
+  float tof_bin, tof_sigma, inv_sigma_sqrt2;
+  int nx, ny;
+  float vx, vy, lox, loy;
+  const float4* lor;
+  const uint8_t* major;        // per (view, rad): 1 if x is the LOR's major axis
+  const float4* view_tab;
+  int subset, n_subsets, n_sv;
+  float radius, rho_scale, rho_max, win_num, win_extra;
+};
+
+// A sinogram as the kernels address it: bin (t, plane, sv, rad) at
+// p[t ts + plane ps + sv vs + rad].
+struct SinoOut {
+  float* p;
+  uint64_t ts, ps, vs;
+};
+struct SinoIn {
+  const float* p;
+  uint64_t ts, ps, vs;
+};
+
+hipError_t launch_project(const ReconGeom& g, const float* img, const SinoOut& out, int tof, hipStream_t s);
+hipError_t launch_backproject(const ReconGeom& g, const SinoIn& in, float* img, int tof, hipStream_t s);
+// One OSEM subset update of img in place; fp: scratch of n_tof n_plane n_sv
+// n_rad floats; back, sens: scratch images.
+hipError_t launch_osem_subset(const ReconGeom& g, const float* prompts, const float* mult, const float* add,
+                              float* img, float* fp, float* back, float* sens, hipStream_t s);
+
+}  // namespace sse
