@@ -267,6 +267,78 @@ def large_loop(args):
     return result
 
 
+def joint_loop(args):
+    """The joint activity / scatter estimation loop on the clinical workload
+    (Methods, "Unknown activity distribution, very limited simulation
+    time"): 10 iterations of (activity from the image, short simulation,
+    normalised smoothing with the paper's FWHM, 1 TOF-OSEM iteration of 28
+    subsets), from a reconstruction without scatter compensation, on a
+    synthetic acquisition made with the library's models (true scatter from
+    a 2e10-history simulation of the true activity, 34 % scatter fraction,
+    5e8 Poisson prompts)."""
+    import torch
+    import paper_2509_05047_amd as sse
+    from paper_2509_05047_amd import joint
+    w = W.WORKLOADS["clinical"]
+    pdesc, mu, act = W.make_phantom(w)
+    lut_desc, lut = W.make_lut(w.lut_dims, w.lut_seed)
+    ctx = sse.Context(w.scanner, w.sino, w.physics)
+    ctx.load_lut(lut_desc, lut)
+    ctx.load_sensitivity(W.make_sensitivity(w.sino, seed=3, tof_axis=False), has_tof_axis=False)
+    pid = ctx.load_phantom(pdesc, mu, act)
+    x_true = torch.from_numpy(W.plane_image(pdesc, act, w.scanner)).cuda()
+    detector = torch.from_numpy(W.make_sensitivity(w.sino, seed=11, tof_axis=False)).cuda()
+    log("[bench] joint loop: synthetic acquisition")
+    prompts, mult, s_true, t = joint.synthetic_acquisition(ctx, pid, x_true, detector)
+    # Smoothing normalisation from the reference cylinder (the paper: a 40 cm
+    # cylinder; here 28 cm, the grid's width).  The LUT's structures do not
+    # depend on TOF, so the reference weights are averaged over the TOF bins
+    # first: a 2e10-history reference then has ~30x the counts per bin.
+    ref_mu, ref_act = W.reference_cylinder(pdesc, 140.0)
+    rid = ctx.load_phantom(pdesc, ref_mu, ref_act)
+    out = ctx.new_outputs()
+    n_ref = 20_000_000_000
+    ctx.simulate(rid, n_ref, 3, out)
+    wref = out["scatter_weights"].view(prompts.shape)
+    wref.copy_(wref.mean(dim=0, keepdim=True).expand_as(wref))
+    sigma = tuple(f / 2.35482 for f in PAPER_FWHM_BINS)
+    norm = torch.empty(prompts.shape, dtype=torch.float32, device="cuda")
+    ctx.smoothing_normalisation(out["scatter_weights"], ctx.emission_scale(rid, n_ref), norm,
+                                tuple(3 * x for x in sigma))
+    del out, wref
+    ctx.unload_phantom(rid)
+    errs = []
+    s_true_nt = s_true.sum(dim=0)   # TOF-summed: the per-bin noise of the reference is lower
+
+    def cb(k, image, scatter):
+        errs.append((float((scatter.sum(dim=0) - s_true_nt).norm() / s_true_nt.norm()),
+                     float((scatter.double().sum() / s_true.double().sum() - 1).abs()),
+                     float((image - x_true).norm() / x_true.norm())))
+        log(f"[bench] joint iteration {k + 1}: scatter error {errs[-1][0]:.4f} (total {errs[-1][1]:.4f}), "
+            f"image error {errs[-1][2]:.4f}")
+
+    n_short = 1_500_000_000
+    image0 = torch.full_like(x_true, float(x_true.mean()))
+    image, scatter, timing = joint.joint_estimation(ctx, pid, prompts, mult, norm, sigma, n_iter=10, n_subsets=28,
+                                                    n_histories=n_short, seed=w.seed, acq_seconds=t,
+                                                    image=image0, callback=cb)
+    ctx.close()
+    lat = timing.iteration_ms
+    return {"iterations": len(lat), "iteration_ms": lat, "iteration_p50_ms": float(np.percentile(lat, 50)),
+            "initial_reconstruction_ms": timing.initial_ms,
+            "step_ms": {"activity_update": float(np.mean(timing.activity_ms)),
+                        "simulate": float(np.mean(timing.simulate_ms)),
+                        "normalised_smoothing": float(np.mean(timing.smooth_ms)),
+                        "osem_1x28": float(np.mean(timing.osem_ms))},
+            "scatter_rel_l2_error_tof_summed": [e[0] for e in errs],
+            "total_scatter_rel_error": [e[1] for e in errs],
+            "image_rel_l2_error": [e[2] for e in errs],
+            "workload": f"clinical body {pdesc.nx}x{pdesc.ny}x{pdesc.nz}, image {pdesc.nx}x{pdesc.ny}x"
+                        f"{w.sino.n_plane}, 10 iterations x ({n_short:.2g}-history simulation, normalised "
+                        f"smoothing FWHM {list(PAPER_FWHM_BINS)} bins, TOF-OSEM 1 x 28 subsets); synthetic "
+                        f"acquisition of 5e8 Poisson prompts, 34 % scatter"}
+
+
 def serving(args):
     """Serving stream: Poisson arrivals of scatter-estimate requests on
     body-like phantoms of 64^3, 128^3 and 192x192x89 voxels (a pool of
@@ -360,7 +432,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="clinical", choices=["clinical", "large", "serving"])
+    ap.add_argument("--workload", default="clinical", choices=["clinical", "large", "serving", "joint"])
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs single-stream throughput")
     ap.add_argument("--histories", type=float, default=0, help="override histories per step")
@@ -402,6 +474,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(serving(args)), flush=True)
+        return
+    if args.workload == "joint":
+        print(json.dumps(joint_loop(args)), flush=True)
         return
     if args.peaks_only:
         log(f"[bench] peaks {json.dumps(measure_peaks())}")
@@ -614,6 +689,8 @@ def main():
         result["large_loop"] = {k: ll[k] for k in ("value", "unit", "request_latency_ms", "request_latency_p50_ms",
                                                    "simulate_ms", "finalize_ms", "update_activity_ms")}
         result["large_loop"]["workload"] = ll["config"]["workload"]
+        log("[bench] joint-estimation leg")
+        result["joint_loop"] = joint_loop(args)
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_histories} histories")
         result["cpu_baseline"] = cpu_baseline(w, physics, pdesc, mu, act, lut_desc, lut, args.cpu_histories, gaps)

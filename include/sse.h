@@ -497,10 +497,19 @@ sse_status sse_backproject(sse_ctx* ctx, sse_phantom_id grid, const float* sino,
  * with prompts y and additive sinogram a (scatter) of the TOF shape, and the
  * multiplicative sinogram m (attenuation factors times detector
  * sensitivity) without TOF axis, shared by the TOF bins.  Ratios with a
- * non-positive denominator count 0; pixels with zero sensitivity in a subset
- * keep their value.  The library holds projection scratch for one subset. */
+ * non-positive denominator count 0, and denominators below 1e-20 count as
+ * 1e-20; pixels with zero sensitivity in a subset keep their value.  The library holds projection scratch for one subset. */
 sse_status sse_osem(sse_ctx* ctx, sse_phantom_id grid, const float* prompts, const float* mult, const float* additive,
                     float* image, int n_iter, int n_subsets, void* stream);
+
+/* Attenuation factors of the multiplicative sinogram: out[plane][view][rad]
+ * = exp(-line integral of mu511) along each LOR, by the projector above
+ * (without TOF) over phantom id's own attenuation map; plane p reads the
+ * voxel slice that holds its z (the paper derives its attenuation sinogram
+ * from a forward projection of the attenuation map, Methods, "Evaluation
+ * metrics").  out: device, n_plane n_view n_rad floats.  Synchronous.
+ * Errors: SSE_EINVAL, SSE_ENOMEM. */
+sse_status sse_attenuation_factors(sse_ctx* ctx, sse_phantom_id id, float* out, void* stream);
 
 /* Replace phantom id's activity by a reconstructed image (device, on the
  * phantom's own transaxial grid, n_plane slices): voxel slice iz takes the

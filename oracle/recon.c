@@ -41,8 +41,10 @@
  *    order; per subset x_j <- x_j (P_s^T (m y / (m P_s x + a)))_j /
  *    (P_s^T m)_j, with m the multiplicative sinogram (attenuation, detector
  *    sensitivity) shared by all TOF bins, a the additive one (scatter);
- *    ratios with a non-positive denominator count 0, and pixels the subset
- *    does not see (zero sensitivity) keep their value.
+ *    ratios with a non-positive denominator count 0, positive denominators
+ *    below 1e-20 count as 1e-20 (so that counts in a bin the model holds
+ *    empty cannot overflow binary32 arithmetic), and pixels the subset does
+ *    not see (zero sensitivity) keep their value.
  */
 #include <math.h>
 #include <stdint.h>
@@ -256,7 +258,7 @@ int orc_recon_osem(const orc_scanner* sc, const orc_sino* sn, const orc_phantom*
         const int v = (int)((i / nr) % nv);
         if (!in_subset(v, s, n_subsets)) { fp[i] = 0.0; continue; }
         const double den = mt[i] * fp[i] + add[i];
-        fp[i] = den > 0.0 ? mt[i] * prompts[i] / den : 0.0;
+        fp[i] = den > 0.0 ? mt[i] * prompts[i] / (den > 1e-20 ? den : 1e-20) : 0.0;
       }
       rc |= orc_recon_backproject(sc, sn, pd, fp, back, 1, s, n_subsets);
       rc |= orc_recon_backproject(sc, sn, pd, mt, sens, 1, s, n_subsets);

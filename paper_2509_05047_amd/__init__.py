@@ -137,6 +137,7 @@ SIGNATURES = {
     "sse_backproject": ([_P, C.c_uint32, _P, _P, C.c_int, C.c_int, C.c_int, _P], C.c_int),
     "sse_osem": ([_P, C.c_uint32, _P, _P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
     "sse_image_to_activity": ([_P, C.c_uint32, _P, _P], C.c_int),
+    "sse_attenuation_factors": ([_P, C.c_uint32, _P, _P], C.c_int),
     "sse_build_alias_table": ([_P, C.c_uint64, _P, _P], C.c_int),
     "sse_server_start": ([_P, _P, C.POINTER(C.c_void_p)], C.c_int),
     "sse_server_submit": ([_P, _P, C.POINTER(C.c_uint64)], C.c_int),
@@ -230,7 +231,9 @@ class Context:
     def __init__(self, scanner, sino, physics: dict, device: int = 0):
         self._sc, self._sn, self._ph = scanner_desc(scanner), sino_desc(sino), physics_desc(physics)
         self.sino = sino
+        self.scanner = scanner
         self.device = device
+        self._grids = {}
         h = C.c_void_p()
         _check(lib().sse_create(C.byref(h), device, C.byref(self._sc), C.byref(self._sn), C.byref(self._ph)))
         self._h = h
@@ -263,7 +266,12 @@ class Context:
         pid = C.c_uint32()
         _check(lib().sse_load_phantom(self._h, C.byref(d), _ptr(mu_), _ptr(act_), mem,
                                       _stream_ptr(stream) if mem == MEM_DEVICE else None, C.byref(pid)))
+        self._grids[pid.value] = (desc.ny, desc.nx)
         return pid.value
+
+    def phantom_grid(self, pid: int):
+        """(ny, nx) of a loaded phantom: the image grid of the reconstruction calls."""
+        return self._grids[pid]
 
     def update_activity(self, pid: int, activity, stream=None):
         mem, act_ = self._as_input(activity)
@@ -398,6 +406,10 @@ class Context:
     def osem(self, grid: int, prompts, mult, additive, image, n_iter: int = 1, n_subsets: int = 1, stream=None):
         _check(lib().sse_osem(self._h, grid, _ptr(prompts), _ptr(mult), _ptr(additive), _ptr(image), n_iter,
                               n_subsets, _stream_ptr(stream)))
+
+    def attenuation_factors(self, pid: int, out, stream=None):
+        """exp(-line integral of the phantom's attenuation) per LOR, [plane][view][rad]."""
+        _check(lib().sse_attenuation_factors(self._h, pid, _ptr(out), _stream_ptr(stream)))
 
     def image_to_activity(self, pid: int, image, stream=None):
         _check(lib().sse_image_to_activity(self._h, pid, _ptr(image), _stream_ptr(stream)))

@@ -43,6 +43,11 @@ struct SinoIn {
 
 hipError_t launch_project(const ReconGeom& g, const float* img, const SinoOut& out, int tof, hipStream_t s);
 hipError_t launch_backproject(const ReconGeom& g, const SinoIn& in, float* img, int tof, hipStream_t s);
+// Attenuation factors exp(-line integral) of all views ([plane][view][rad])
+// from the phantom's attenuation volume mu: image slice p is volume slice
+// iz_of[p] (device table), staged in mu_img (image-sized scratch).
+hipError_t launch_attenuation_factors(const ReconGeom& g, const float* mu, const int* iz_of, float* mu_img,
+                                      float* out, hipStream_t s);
 // One OSEM subset update of img in place; fp: scratch of n_tof n_plane n_sv
 // n_rad floats; back, sens: scratch images.
 hipError_t launch_osem_subset(const ReconGeom& g, const float* prompts, const float* mult, const float* add,

@@ -219,7 +219,8 @@ __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g,
 }
 
 // ratio[b] = m y / (m fp + a) over a subset's bins (compact layout of fp and
-// ratio; prompts and additive in the full layout; m without TOF axis).
+// ratio; prompts and additive in the full layout; m without TOF axis): 0 for
+// a non-positive denominator, which counts as 1e-20 when smaller than that.
 __global__ void __launch_bounds__(256) ratio_kernel(ReconGeom g, const float* __restrict__ prompts,
                                                     const float* __restrict__ mult, const float* __restrict__ add,
                                                     float* __restrict__ fp_ratio) {
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256) ratio_kernel(ReconGeom g, const float* __
     const uint64_t full = t * static_cast<uint64_t>(g.n_plane) * g.n_view * g.n_rad + inner;
     const float m = mult[inner];
     const float den = m * fp_ratio[i] + add[full];
-    fp_ratio[i] = den > 0.0f ? m * prompts[full] / den : 0.0f;
+    fp_ratio[i] = den > 0.0f ? m * prompts[full] / fmaxf(den, 1e-20f) : 0.0f;
   }
 }
 
@@ -264,6 +265,22 @@ __global__ void __launch_bounds__(256) update_kernel(float* __restrict__ x, cons
   }
 }
 
+// image slice p = volume slice iz_of[p] (nearest voxel slice to plane p)
+__global__ void __launch_bounds__(256) plane_slices_kernel(const float* __restrict__ vol,
+                                                           const int* __restrict__ iz_of, uint64_t slice,
+                                                           uint64_t n_plane, float* __restrict__ img) {
+  const uint64_t n = slice * n_plane;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    img[i] = vol[static_cast<uint64_t>(iz_of[i / slice]) * slice + i % slice];
+}
+
+__global__ void __launch_bounds__(256) exp_neg_kernel(float* __restrict__ x, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    x[i] = expf(-x[i]);
+}
+
 int grid_for(uint64_t n) {
   const uint64_t b = (n + 255) / 256;
   return static_cast<int>(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -283,6 +300,20 @@ hipError_t launch_backproject(const ReconGeom& g, const SinoIn& in, float* img, 
   const uint64_t n = static_cast<uint64_t>(g.nx) * g.ny * g.n_plane;
   hipLaunchKernelGGL(backproject_kernel, dim3(static_cast<unsigned>((n + kReconThreads - 1) / kReconThreads)),
                      dim3(kReconThreads), 0, s, g, in, img, tof);
+  return hipGetLastError();
+}
+
+hipError_t launch_attenuation_factors(const ReconGeom& g, const float* mu, const int* iz_of, float* mu_img,
+                                      float* out, hipStream_t s) {
+  const uint64_t slice = static_cast<uint64_t>(g.nx) * g.ny;
+  hipLaunchKernelGGL(plane_slices_kernel, dim3(grid_for(slice * g.n_plane)), dim3(256), 0, s, mu, iz_of, slice,
+                     static_cast<uint64_t>(g.n_plane), mu_img);
+  const uint64_t plane_bins = static_cast<uint64_t>(g.n_view) * g.n_rad;
+  const SinoOut o{out, 0, plane_bins, static_cast<uint64_t>(g.n_rad)};
+  hipError_t e = launch_project(g, mu_img, o, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(exp_neg_kernel, dim3(grid_for(plane_bins * g.n_plane)), dim3(256), 0, s, out,
+                     plane_bins * g.n_plane);
   return hipGetLastError();
 }
 

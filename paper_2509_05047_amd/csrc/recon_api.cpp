@@ -115,7 +115,7 @@ sse_status check_grid(sse_ctx* c, sse_phantom_id grid, Phantom*& ph) {
 }
 
 sse_status ensure_recon_scratch(sse_ctx* c, uint64_t fp_floats, uint64_t img_floats) {
-  if (c->recon_fp_cap < fp_floats) {
+  if (fp_floats && c->recon_fp_cap < fp_floats) {
     release(c->d_recon_fp);
     c->d_recon_fp = nullptr;
     c->recon_fp_cap = 0;
@@ -210,6 +210,37 @@ sse_status sse_osem(sse_ctx* c, sse_phantom_id grid, const float* prompts, const
                                       c->d_recon_img[1], s),
               "OSEM subset");
     }
+  return SSE_OK;
+}
+
+sse_status sse_attenuation_factors(sse_ctx* c, sse_phantom_id id, float* out, void* stream) {
+  if (!c || !out) return fail(SSE_EINVAL, "null argument");
+  Phantom* ph = get_phantom(c, id);
+  if (!ph) return fail(SSE_EINVAL, "unknown phantom id");
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (sse_status st = ensure_lor_tables(c); st != SSE_OK) return st;
+  const sse_phantom_desc& d = ph->desc;
+  const int np = c->sn.n_plane;
+  const uint64_t img = static_cast<uint64_t>(d.nx) * d.ny * np;
+  if (sse_status st = ensure_recon_scratch(c, 0, img); st != SSE_OK) return st;
+  // plane p reads the voxel slice nearest its z
+  const double half_pitch = 0.5 * static_cast<double>(c->sc.length_mm) / c->sc.n_rings;
+  std::vector<int> iz_of(np);
+  for (int p = 0; p < np; ++p) {
+    const double z = -0.5 * c->sc.length_mm + (p + 1) * half_pitch;
+    double iz = std::floor((z - d.lo_mm[2]) / d.voxel_mm[2]);
+    iz = iz < 0.0 ? 0.0 : (iz > d.nz - 1 ? static_cast<double>(d.nz - 1) : iz);
+    iz_of[p] = static_cast<int>(iz);
+  }
+  int* d_iz = nullptr;
+  HIP_TRY(hipMalloc(&d_iz, np * sizeof(int)), "allocate plane table");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(d_iz, iz_of.data(), np * sizeof(int), hipMemcpyHostToDevice, s);
+  const sse::ReconGeom g = geom_of(c, ph, 0, 1);
+  if (e == hipSuccess) e = sse::launch_attenuation_factors(g, ph->d_mu, d_iz, c->d_recon_img[0], out, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release(d_iz);
+  if (e != hipSuccess) return hip_fail(e, "attenuation factors");
   return SSE_OK;
 }
 

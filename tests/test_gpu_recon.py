@@ -194,3 +194,22 @@ def test_image_to_activity_feeds_the_simulation():
     o = H.run_oracle(c2, 20_000, 77)
     same = H.identical_mask(g["records"], o["records"])
     assert same.mean() >= 0.999, H.describe_mismatch(g["records"], o["records"])
+
+
+@pytest.mark.parametrize("which", ["tiny", "clinical"])
+def test_attenuation_factors_match_oracle(which):
+    """exp(-line integral) of the phantom's own attenuation map, each plane
+    reading the voxel slice that holds its z, against the oracle projector on
+    the same plane image."""
+    w, sino, pd, mu, act, ctx, pid = setup(which)
+    try:
+        out = torch.empty((sino.n_plane, sino.n_view, sino.n_rad), dtype=torch.float32, device="cuda")
+        ctx.attenuation_factors(pid, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    finally:
+        ctx.close()
+    mu_img = W.plane_image(pd, mu, w.scanner)
+    ref = np.exp(-O.recon_project(w.scanner, sino, pd, mu_img, tof=False))
+    close(got, ref, rtol=1e-4, atol_frac=1e-6)
+    assert got.min() > 0 and got.max() <= 1.0

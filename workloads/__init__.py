@@ -288,6 +288,26 @@ def serving_phantom(seed: int):
     return desc, mu.astype(np.float32), act.astype(np.float32)
 
 
+def reference_cylinder(desc: PhantomDesc, radius_mm: float):
+    """Uniform water cylinder of the given radius along z, full length, on a
+    phantom grid: the reference object of the smoothing normalisation (the
+    paper uses a 40 cm cylinder)."""
+    z, y, x = voxel_centres(desc)
+    inside = np.broadcast_to(x * x + y * y <= radius_mm ** 2, desc.shape)
+    return (np.where(inside, MU_WATER, 0.0).astype(np.float32), np.where(inside, 1.0, 0.0).astype(np.float32))
+
+
+def plane_image(desc: PhantomDesc, vol: np.ndarray, scanner: Scanner) -> np.ndarray:
+    """A voxel volume on the reconstruction image grid: the phantom's
+    transaxial grid with one slice per sinogram plane, plane p (at z = -L/2 +
+    (p + 1) pitch / 2) taking the voxel slice that holds its z."""
+    n_plane = 2 * scanner.n_rings - 1
+    half_pitch = 0.5 * scanner.length_mm / scanner.n_rings
+    z = -0.5 * scanner.length_mm + (np.arange(n_plane) + 1) * half_pitch
+    iz = np.clip(np.floor((z - desc.lo_mm[2]) / desc.voxel_mm[2]), 0, desc.nz - 1).astype(int)
+    return np.ascontiguousarray(np.asarray(vol).reshape(desc.shape)[iz], np.float32)
+
+
 def scaled_activity(act: np.ndarray, k: int, sigma_vox: float = 15.0) -> np.ndarray:
     """activity_k = activity_0 * max(0, 1 + 0.3 g_k), with g_k a Gaussian-filtered
     N(0, 1) field (sigma in voxels) normalised to max |g| = 1, seed k."""
