@@ -500,7 +500,16 @@ sse_status sse_backproject(sse_ctx* ctx, sse_phantom_id grid, const float* sino,
  * non-positive denominator count 0, and denominators below 1e-20 count as
  * 1e-20; pixels with zero sensitivity in a subset keep their value.  The library holds projection scratch for one subset. */
 sse_status sse_osem(sse_ctx* ctx, sse_phantom_id grid, const float* prompts, const float* mult, const float* additive,
-                    float* image, int n_iter, int n_subsets, void* stream);
+                    const float* sens, float* image, int n_iter, int n_subsets, void* stream);
+
+/* The subset sensitivity images P_s^T m of sse_osem (m broadcast over TOF),
+ * for n_subsets subsets: sens holds n_subsets images back to back (device,
+ * n_subsets * n_plane * ny * nx floats, caller-owned).  Passing them to
+ * sse_osem (sens != NULL) saves one back projection per subset when m stays
+ * the same over many calls, as in the estimation loop; with sens == NULL
+ * sse_osem computes each subset's image itself. */
+sse_status sse_osem_sensitivity(sse_ctx* ctx, sse_phantom_id grid, const float* mult, int n_subsets, float* sens,
+                                void* stream);
 
 /* Attenuation factors of the multiplicative sinogram: out[plane][view][rad]
  * = exp(-line integral of mu511) along each LOR, by the projector above

@@ -135,7 +135,8 @@ SIGNATURES = {
     "sse_finalize_normalised": ([_P, _P, C.c_double, _P, _P, C.c_float, _P, _P], C.c_int),
     "sse_project": ([_P, C.c_uint32, _P, _P, C.c_int, C.c_int, C.c_int, _P], C.c_int),
     "sse_backproject": ([_P, C.c_uint32, _P, _P, C.c_int, C.c_int, C.c_int, _P], C.c_int),
-    "sse_osem": ([_P, C.c_uint32, _P, _P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
+    "sse_osem": ([_P, C.c_uint32, _P, _P, _P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
+    "sse_osem_sensitivity": ([_P, C.c_uint32, _P, C.c_int, _P, _P], C.c_int),
     "sse_image_to_activity": ([_P, C.c_uint32, _P, _P], C.c_int),
     "sse_attenuation_factors": ([_P, C.c_uint32, _P, _P], C.c_int),
     "sse_build_alias_table": ([_P, C.c_uint64, _P, _P], C.c_int),
@@ -403,9 +404,20 @@ class Context:
         _check(lib().sse_backproject(self._h, grid, _ptr(sino), _ptr(image), int(bool(tof)), subset, n_subsets,
                                      _stream_ptr(stream)))
 
-    def osem(self, grid: int, prompts, mult, additive, image, n_iter: int = 1, n_subsets: int = 1, stream=None):
-        _check(lib().sse_osem(self._h, grid, _ptr(prompts), _ptr(mult), _ptr(additive), _ptr(image), n_iter,
-                              n_subsets, _stream_ptr(stream)))
+    def osem(self, grid: int, prompts, mult, additive, image, n_iter: int = 1, n_subsets: int = 1, sens=None,
+             stream=None):
+        """sens: the subset sensitivity images of osem_sensitivity (or None)."""
+        _check(lib().sse_osem(self._h, grid, _ptr(prompts), _ptr(mult), _ptr(additive), _ptr(sens), _ptr(image),
+                              n_iter, n_subsets, _stream_ptr(stream)))
+
+    def osem_sensitivity(self, grid: int, mult, n_subsets: int, stream=None):
+        """The n_subsets subset sensitivity images, a new device tensor."""
+        import torch
+        ny, nx = self.phantom_grid(grid)
+        sens = torch.empty((n_subsets, self.sino.n_plane, ny, nx), dtype=torch.float32,
+                           device=torch.device("cuda", self.device))
+        _check(lib().sse_osem_sensitivity(self._h, grid, _ptr(mult), n_subsets, _ptr(sens), _stream_ptr(stream)))
+        return sens
 
     def attenuation_factors(self, pid: int, out, stream=None):
         """exp(-line integral of the phantom's attenuation) per LOR, [plane][view][rad]."""

@@ -11,8 +11,9 @@ namespace sse {
 
 // Geometry of one projection: the image grid (nx x ny pixels of vx x vy mm
 // from (lox, loy), one slice per sinogram plane), the sinogram, the LOR table
-// lor[view * n_rad + rad] = (midpoint x, y, unit direction x, y towards the
-// TOF-positive crystal; direction 0 where no crystal pair maps) with its
+// lor[view * n_rad + rad] = (midpoint x, y, and the unit direction towards
+// the TOF-positive crystal stored as (1 / u_x, u_y) for an x-major LOR, (u_x,
+// 1 / u_y) for a y-major one; zero where no crystal pair maps) with its
 // major axis decided from the crystal indices (see recon.hip), and the
 // views taken: subset + sv * n_subsets for sv in [0, n_sv).  view_tab[view]
 // = (normal x, y of the view's centre LOR, +-1 so that the radial index
@@ -22,7 +23,7 @@ struct ReconGeom {
   int n_rad, n_view, n_plane, n_tof;
   float tof_bin, tof_sigma, inv_sigma_sqrt2;
   int nx, ny;
-  float vx, vy, lox, loy;
+  float vx, vy, lox, loy, ivx, ivy;
   const float4* lor;
   const uint8_t* major;        // per (view, rad): 1 if x is the LOR's major axis
   const float4* view_tab;
@@ -48,9 +49,13 @@ hipError_t launch_backproject(const ReconGeom& g, const SinoIn& in, float* img, 
 // iz_of[p] (device table), staged in mu_img (image-sized scratch).
 hipError_t launch_attenuation_factors(const ReconGeom& g, const float* mu, const int* iz_of, float* mu_img,
                                       float* out, hipStream_t s);
-// One OSEM subset update of img in place; fp: scratch of n_tof n_plane n_sv
-// n_rad floats; back, sens: scratch images.
+// The subset's sensitivity image P_s^T m (m broadcast over TOF) into sens;
+// fp: scratch of n_tof n_plane n_sv n_rad floats.
+hipError_t launch_subset_sensitivity(const ReconGeom& g, const float* mult, float* fp, float* sens, hipStream_t s);
+// One OSEM subset update of img in place; fp: scratch as above; back:
+// scratch image; sens: the subset's sensitivity image, computed here unless
+// sens_ready.
 hipError_t launch_osem_subset(const ReconGeom& g, const float* prompts, const float* mult, const float* add,
-                              float* img, float* fp, float* back, float* sens, hipStream_t s);
+                              float* img, float* fp, float* back, float* sens, bool sens_ready, hipStream_t s);
 
 }  // namespace sse

@@ -47,23 +47,27 @@ struct Sample {
   float dl;     // path length
 };
 
-// Sample k of the LOR (m, u) along its major axis (x if xmaj).
+// Sample k of the LOR with midpoint (mx, my) along its major axis (x if
+// xmaj); ux, uy hold the table's (1 / u_x, u_y) for an x-major LOR and
+// (u_x, 1 / u_y) for a y-major one.
 __device__ __forceinline__ Sample lor_sample(const ReconGeom& g, float mx, float my, float ux, float uy, bool xmaj,
                                              int k) {
   Sample o;
   float f;
+  // (quotients as products with the reciprocals of the LOR table and the
+  // geometry: forward and back projector take the same binary32 values)
   if (xmaj) {
     const float xc = g.lox + (static_cast<float>(k) + 0.5f) * g.vx;
-    o.s = (xc - mx) / ux;
+    o.s = (xc - mx) * ux;
     const float y = my + o.s * uy;
-    f = (y - g.loy) / g.vy - 0.5f;
-    o.dl = g.vx / fabsf(ux);
+    f = (y - g.loy) * g.ivy - 0.5f;
+    o.dl = g.vx * fabsf(ux);
   } else {
     const float yc = g.loy + (static_cast<float>(k) + 0.5f) * g.vy;
-    o.s = (yc - my) / uy;
+    o.s = (yc - my) * uy;
     const float x = mx + o.s * ux;
-    f = (x - g.lox) / g.vx - 0.5f;
-    o.dl = g.vy / fabsf(uy);
+    f = (x - g.lox) * g.ivx - 0.5f;
+    o.dl = g.vy * fabsf(uy);
   }
   const float fl = floorf(f);
   o.i0 = static_cast<int>(fl);
@@ -317,8 +321,15 @@ hipError_t launch_attenuation_factors(const ReconGeom& g, const float* mu, const
   return hipGetLastError();
 }
 
+hipError_t launch_subset_sensitivity(const ReconGeom& g, const float* mult, float* fp, float* sens, hipStream_t s) {
+  const uint64_t tb = static_cast<uint64_t>(g.n_plane) * g.n_sv * g.n_rad;
+  const SinoIn in{fp, tb, static_cast<uint64_t>(g.n_sv) * g.n_rad, static_cast<uint64_t>(g.n_rad)};
+  hipLaunchKernelGGL(mult_tof_kernel, dim3(grid_for(tb * g.n_tof)), dim3(256), 0, s, g, mult, fp);
+  return launch_backproject(g, in, sens, 1, s);
+}
+
 hipError_t launch_osem_subset(const ReconGeom& g, const float* prompts, const float* mult, const float* add,
-                              float* img, float* fp, float* back, float* sens, hipStream_t s) {
+                              float* img, float* fp, float* back, float* sens, bool sens_ready, hipStream_t s) {
   const uint64_t tb = static_cast<uint64_t>(g.n_plane) * g.n_sv * g.n_rad;  // compact bins per TOF bin
   const SinoOut out{fp, tb, static_cast<uint64_t>(g.n_sv) * g.n_rad, static_cast<uint64_t>(g.n_rad)};
   const SinoIn in{fp, tb, static_cast<uint64_t>(g.n_sv) * g.n_rad, static_cast<uint64_t>(g.n_rad)};
@@ -328,9 +339,10 @@ hipError_t launch_osem_subset(const ReconGeom& g, const float* prompts, const fl
   hipLaunchKernelGGL(ratio_kernel, dim3(grid_for(nb)), dim3(256), 0, s, g, prompts, mult, add, fp);
   e = launch_backproject(g, in, back, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mult_tof_kernel, dim3(grid_for(nb)), dim3(256), 0, s, g, mult, fp);
-  e = launch_backproject(g, in, sens, 1, s);
-  if (e != hipSuccess) return e;
+  if (!sens_ready) {
+    e = launch_subset_sensitivity(g, mult, fp, sens, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(update_kernel, dim3(grid_for(ni)), dim3(256), 0, s, img, back, sens, ni);
   return hipGetLastError();
 }

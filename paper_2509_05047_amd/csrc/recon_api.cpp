@@ -24,6 +24,7 @@ sse_status ensure_lor_tables(sse_ctx* c) {
   const int n = c->sc.n_crystals, n_rad = c->sn.n_rad, n_view = c->sn.n_view, half = (n_rad - 1) / 2;
   const double R = c->sc.radius_mm;
   std::vector<float4> lor(static_cast<size_t>(n_view) * n_rad, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  std::vector<double> ux(lor.size(), 0.0), uy(lor.size(), 0.0), mxs(lor.size(), 0.0), mys(lor.size(), 0.0);
   std::vector<uint8_t> major(static_cast<size_t>(n_view) * n_rad, 1);
   for (int c1 = 0; c1 < n; ++c1)
     for (int c2 = c1 + 1; c2 < n; ++c2) {
@@ -41,23 +42,26 @@ sse_status ensure_lor_tables(sse_ctx* c) {
       const double ax = R * std::cos(pa), ay = R * std::sin(pa), bx = R * std::cos(pb), by = R * std::sin(pb);
       const double dx = ax - bx, dy = ay - by, len = std::sqrt(dx * dx + dy * dy);
       const size_t idx = static_cast<size_t>(k >> 1) * n_rad + (rho + half);
-      lor[idx] = make_float4(static_cast<float>(0.5 * (ax + bx)), static_cast<float>(0.5 * (ay + by)),
-                             static_cast<float>(dx / len), static_cast<float>(dy / len));
       // direction angle pi q / (2 n): x is the major axis within 45 degrees of it
       const int q = (2 * k + n) % (2 * n);
       major[idx] = (2 * q <= n || 2 * q >= 3 * n) ? 1 : 0;
+      ux[idx] = dx / len;
+      uy[idx] = dy / len;
+      mxs[idx] = 0.5 * (ax + bx);
+      mys[idx] = 0.5 * (ay + by);
+      // the sample divides by the major component: stored as its reciprocal
+      lor[idx] = make_float4(static_cast<float>(mxs[idx]), static_cast<float>(mys[idx]),
+                             static_cast<float>(major[idx] ? len / dx : dx / len),
+                             static_cast<float>(major[idx] ? dy / len : len / dy));
     }
   // view table: the centre LOR's normal, and the sign that makes the signed
   // distance along it grow with the radial index
   std::vector<float4> view(n_view);
   for (int v = 0; v < n_view; ++v) {
-    const float4 l0 = lor[static_cast<size_t>(v) * n_rad + half];
-    const double nx = -static_cast<double>(l0.w), ny = static_cast<double>(l0.z);
+    const size_t i0 = static_cast<size_t>(v) * n_rad + half;
+    const double nx = -uy[i0], ny = ux[i0];
     double sg = 1.0;
-    if (n_rad > 1) {
-      const float4 l1 = lor[static_cast<size_t>(v) * n_rad + half + 1];
-      sg = (nx * l1.x + ny * l1.y) >= (nx * l0.x + ny * l0.y) ? 1.0 : -1.0;
-    }
+    if (n_rad > 1) sg = (nx * mxs[i0 + 1] + ny * mys[i0 + 1]) >= (nx * mxs[i0] + ny * mys[i0]) ? 1.0 : -1.0;
     view[v] = make_float4(static_cast<float>(nx), static_cast<float>(ny), static_cast<float>(sg), 0.0f);
   }
   HIP_TRY(hipMalloc(&c->d_lor, lor.size() * sizeof(float4)), "allocate LOR table");
@@ -85,6 +89,8 @@ sse::ReconGeom geom_of(const sse_ctx* c, const Phantom* ph, int subset, int n_su
   g.vy = ph->desc.voxel_mm[1];
   g.lox = ph->desc.lo_mm[0];
   g.loy = ph->desc.lo_mm[1];
+  g.ivx = static_cast<float>(1.0 / ph->desc.voxel_mm[0]);
+  g.ivy = static_cast<float>(1.0 / ph->desc.voxel_mm[1]);
   g.lor = static_cast<const float4*>(c->d_lor);
   g.major = static_cast<const uint8_t*>(c->d_major);
   g.view_tab = static_cast<const float4*>(c->d_view);
@@ -188,8 +194,30 @@ sse_status sse_backproject(sse_ctx* c, sse_phantom_id grid, const float* sino, f
   return SSE_OK;
 }
 
+sse_status sse_osem_sensitivity(sse_ctx* c, sse_phantom_id grid, const float* mult, int n_subsets, float* sens,
+                                void* stream) {
+  if (!c || !mult || !sens) return fail(SSE_EINVAL, "null argument");
+  Phantom* ph = nullptr;
+  if (sse_status st = check_grid(c, grid, ph); st != SSE_OK) return st;
+  if (sse_status st = check_subsets(0, n_subsets, c->sn.n_view); st != SSE_OK) return st;
+  if (sse_status st = check_tof(c, 1); st != SSE_OK) return st;
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (sse_status st = ensure_lor_tables(c); st != SSE_OK) return st;
+  const uint64_t n_sv_max = (static_cast<uint64_t>(c->sn.n_view) + n_subsets - 1) / n_subsets;
+  const uint64_t fp = static_cast<uint64_t>(c->sn.n_tof) * c->sn.n_plane * n_sv_max * c->sn.n_rad;
+  const uint64_t img = static_cast<uint64_t>(ph->desc.nx) * ph->desc.ny * c->sn.n_plane;
+  if (sse_status st = ensure_recon_scratch(c, fp, img); st != SSE_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int sub = 0; sub < n_subsets; ++sub) {
+    const sse::ReconGeom g = geom_of(c, ph, sub, n_subsets);
+    HIP_TRY(sse::launch_subset_sensitivity(g, mult, c->d_recon_fp, sens + static_cast<uint64_t>(sub) * img, s),
+            "subset sensitivity");
+  }
+  return SSE_OK;
+}
+
 sse_status sse_osem(sse_ctx* c, sse_phantom_id grid, const float* prompts, const float* mult, const float* additive,
-                    float* image, int n_iter, int n_subsets, void* stream) {
+                    const float* sens, float* image, int n_iter, int n_subsets, void* stream) {
   if (!c || !prompts || !mult || !additive || !image) return fail(SSE_EINVAL, "null argument");
   if (n_iter < 0) return fail(SSE_EINVAL, "n_iter must be >= 0");
   if (sse_status st = check_tof(c, 1); st != SSE_OK) return st;
@@ -206,8 +234,9 @@ sse_status sse_osem(sse_ctx* c, sse_phantom_id grid, const float* prompts, const
   for (int it = 0; it < n_iter; ++it)
     for (int sub = 0; sub < n_subsets; ++sub) {
       const sse::ReconGeom g = geom_of(c, ph, sub, n_subsets);
-      HIP_TRY(sse::launch_osem_subset(g, prompts, mult, additive, image, c->d_recon_fp, c->d_recon_img[0],
-                                      c->d_recon_img[1], s),
+      float* sub_sens = sens ? const_cast<float*>(sens) + static_cast<uint64_t>(sub) * img : c->d_recon_img[1];
+      HIP_TRY(sse::launch_osem_subset(g, prompts, mult, additive, image, c->d_recon_fp, c->d_recon_img[0], sub_sens,
+                                      sens != nullptr, s),
               "OSEM subset");
     }
   return SSE_OK;

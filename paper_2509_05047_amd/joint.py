@@ -6,7 +6,8 @@ smoothing, and repeat.  The paper runs 10 such iterations with 1 TOF-OSEM
 iteration of 28 subsets each, from an initial reconstruction without scatter
 compensation.
 
-Every step is a call of the C library (sse_osem, sse_image_to_activity,
+Every step is a call of the C library (sse_osem with the subset
+sensitivity images of sse_osem_sensitivity, sse_image_to_activity,
 sse_simulate, sse_finalize_normalised); this module only sequences the calls
 and holds the device buffers.
 """
@@ -50,14 +51,16 @@ def joint_estimation(ctx: Context, pid: int, prompts, mult, norm, sigma_bins, n_
         image = torch.ones((n_plane, pd_ny, pd_nx), dtype=torch.float32, device=dev)
     scatter = torch.zeros_like(prompts)
     out = ctx.new_outputs(trues=False, stats=False)
-    timing = LoopTiming()
+    timing = LoopTiming()   # initial_ms includes the subset sensitivity images
 
     def sync():
         torch.cuda.synchronize(dev)
         return time.perf_counter()
 
     t0 = sync()
-    ctx.osem(pid, prompts, mult, scatter, image, n_iter=initial_iterations, n_subsets=n_subsets, stream=stream)
+    sens = ctx.osem_sensitivity(pid, mult, n_subsets, stream=stream)   # m is the same in every iteration
+    ctx.osem(pid, prompts, mult, scatter, image, n_iter=initial_iterations, n_subsets=n_subsets, sens=sens,
+             stream=stream)
     timing.initial_ms = (sync() - t0) * 1e3
     for k in range(n_iter):
         t0 = sync()
@@ -70,7 +73,7 @@ def joint_estimation(ctx: Context, pid: int, prompts, mult, norm, sigma_bins, n_
         scale = ctx.emission_scale(pid, n_histories, acq_seconds, factor)
         ctx.finalize_normalised(out["scatter_weights"], scale, norm, scatter, sigma_bins, stream=stream)
         t3 = sync()
-        ctx.osem(pid, prompts, mult, scatter, image, n_iter=1, n_subsets=n_subsets, stream=stream)
+        ctx.osem(pid, prompts, mult, scatter, image, n_iter=1, n_subsets=n_subsets, sens=sens, stream=stream)
         t4 = sync()
         timing.iteration_ms.append((t4 - t0) * 1e3)
         timing.activity_ms.append((t1 - t0) * 1e3)

@@ -159,10 +159,15 @@ def test_osem_matches_oracle_tiny():
         prompts = (mult[None] * fwd + add).astype(np.float32)
         x0 = np.full_like(x_true, x_true.mean()).astype(np.float32)
         img = torch.from_numpy(x0).cuda()
-        ctx.osem(pid, torch.from_numpy(prompts).cuda(), torch.from_numpy(mult).cuda(), torch.from_numpy(add).cuda(),
-                 img, n_iter=2, n_subsets=4)
+        dp, dm, da = (torch.from_numpy(a).cuda() for a in (prompts, mult, add))
+        ctx.osem(pid, dp, dm, da, img, n_iter=2, n_subsets=4)
+        # with the subset sensitivity images computed beforehand: the same bits
+        img2 = torch.from_numpy(x0).cuda()
+        sens = ctx.osem_sensitivity(pid, dm, 4)
+        ctx.osem(pid, dp, dm, da, img2, n_iter=2, n_subsets=4, sens=sens)
         torch.cuda.synchronize()
         got = img.cpu().numpy()
+        assert torch.equal(img, img2)
     finally:
         ctx.close()
     ref = O.recon_osem(w.scanner, sino, pd, prompts, mult, add, x0, n_iter=2, n_subsets=4)
