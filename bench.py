@@ -115,9 +115,10 @@ def smoothing_normalisation_timing(ctx, weights, scale, out, stream, reps=3):
     step's weights -- a normalisation sinogram (heavy smoothing of these
     weights standing in for the reference cylinder) and the normalised
     finalize sens * G(S N) / N with the paper's FWHM -- timed with HIP events
-    on the launch stream.  Algorithmic HBM bytes per bin: 40 for the
-    finalize (radial pass reads W and N, writes S N; view pass reads and
-    writes; plane pass reads, N and the sensitivity, writes)."""
+    on the launch stream.  Algorithmic HBM bytes per bin: 28 for the
+    finalize (the fused radial and plane pass reads W and N and writes
+    G_rp(S N), 16; the view pass reads that and N and writes, 12; the
+    sensitivity has no TOF axis and is read once per TOF bin)."""
     import torch
     sigma = tuple(f / 2.35482 for f in PAPER_FWHM_BINS)
     heavy = tuple(3 * s for s in sigma)
@@ -137,7 +138,7 @@ def smoothing_normalisation_timing(ctx, weights, scale, out, stream, reps=3):
     fin_ms = float(np.median(t_fin))
     return {"fwhm_bins": list(PAPER_FWHM_BINS), "normalisation_sigma_bins": list(heavy),
             "normalisation_ms": float(np.median(t_norm)), "finalize_normalised_ms": fin_ms,
-            "finalize_bytes_per_bin": 40, "finalize_hbm_tbps": 40.0 * n_bins / (fin_ms * 1e-3) / 1e12}
+            "finalize_bytes_per_bin": 28, "finalize_hbm_tbps": 28.0 * n_bins / (fin_ms * 1e-3) / 1e12}
 
 
 def log(msg):

@@ -395,8 +395,8 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
   if (!sigma) return fail(SSE_EINVAL, "null sigma");
   if (!in || !out) return fail(SSE_EINVAL, "null buffer");
   if (!(truncate > 0.0f) || !std::isfinite(truncate)) return fail(SSE_EINVAL, "truncate must be positive");
-  sse::Taps taps[3] = {};
-  int axes[3], na = 0;
+  sse::Taps taps[3] = {};  // by axis
+  bool on[3] = {};
   for (int a = 0; a < 3; ++a) {
     const float sg = sigma[a];
     if (!(sg >= 0.0f) || !std::isfinite(sg)) return fail(SSE_EINVAL, "sigma must be finite and >= 0");
@@ -409,30 +409,53 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
       w[k + radius] = std::exp(-0.5 * k * k / (sd * sd));
       tot += w[k + radius];
     }
-    std::memset(&taps[na], 0, sizeof(sse::Taps));
-    taps[na].radius = radius;
-    for (int k = 0; k <= 2 * radius; ++k) taps[na].w[k] = static_cast<float>(w[k] / tot);
-    axes[na++] = a;
+    taps[a].radius = radius;
+    for (int k = 0; k <= 2 * radius; ++k) taps[a].w[k] = static_cast<float>(w[k] / tot);
+    on[a] = true;
   }
   const sse::PostParams g = post_params(c);
-  if (na == 0) {  // elementwise (in place allowed)
+  if (!on[0] && !on[1] && !on[2]) {  // elementwise (in place allowed)
     HIP_TRY(sse::launch_smooth_axis(g, -1, in, in_is_f64, scale, norm, out, taps[0], norm, sens, c->sens_tof, s),
             "pointwise kernel");
     return SSE_OK;
   }
+  // The passes: radial and plane in one launch when both are smoothed and
+  // the tile fits in LDS, then the view pass; otherwise one pass per axis.
+  // The axes commute (each pass is linear along its own axis, and the view
+  // seam's reversal of the radial and TOF indices commutes with the radial
+  // sum, whose taps and reflection are symmetric).
+  constexpr int kFused = 3;
+  sse::FusedPlan plan{};
+  if (on[0] && on[2]) plan = sse::plan_rad_plane(g, taps[0].radius, taps[2].radius);
+  int passes[3], np = 0;
+  if (plan.tl > 0) {
+    passes[np++] = kFused;
+    if (on[1]) passes[np++] = 1;
+  } else {
+    for (int a = 0; a < 3; ++a)
+      if (on[a]) passes[np++] = a;
+  }
   sse_status st = ensure_scratch(c);
   if (st != SSE_OK) return st;
   // A pass never reads and writes the same buffer: with in == out and one
-  // active axis the result goes through scratch.
+  // pass the result goes through scratch.
   const void* src = in;
   bool src_f64 = in_is_f64;
   float* dst = nullptr;
-  for (int i = 0; i < na; ++i) {
-    const bool last = i == na - 1;
-    dst = (last && !(na == 1 && in == out)) ? out : c->d_scratch[i % 2];
-    HIP_TRY(sse::launch_smooth_axis(g, axes[i], src, src_f64, scale, i == 0 ? norm : nullptr, dst, taps[i],
-                                    last ? norm : nullptr, last ? sens : nullptr, c->sens_tof, s),
-            "smoothing kernel");
+  for (int i = 0; i < np; ++i) {
+    const bool last = i == np - 1;
+    dst = (last && !(np == 1 && in == out)) ? out : c->d_scratch[i % 2];
+    const float* n_in = i == 0 ? norm : nullptr;
+    const float* n_out = last ? norm : nullptr;
+    const float* sv = last ? sens : nullptr;
+    if (passes[i] == kFused)
+      HIP_TRY(sse::launch_smooth_rad_plane(g, plan, src, src_f64, scale, n_in, dst, taps[0], taps[2], n_out, sv,
+                                           c->sens_tof, s),
+              "smoothing kernel (radial and plane)");
+    else
+      HIP_TRY(sse::launch_smooth_axis(g, passes[i], src, src_f64, scale, n_in, dst, taps[passes[i]], n_out, sv,
+                                      c->sens_tof, s),
+              "smoothing kernel");
     src = dst;
     src_f64 = false;
   }

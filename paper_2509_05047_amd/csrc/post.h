@@ -29,6 +29,24 @@ struct Taps {
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
                               const float* norm_in, float* out, const Taps& taps, const float* norm_out,
                               const float* sens, int sens_tof, hipStream_t stream);
+// The radial and plane passes in one launch (both axes smoothed): tiles of
+// tl radial positions by all planes of one (TOF, view) row, staged in LDS by
+// a persistent block per CU.  plan_rad_plane picks the tile for the radii
+// (tl == 0: the tile does not fit in fused_lds_limit() bytes of LDS -- the
+// device's per-block LDS, at most kFusedLdsBytes -- or its staging slots, or
+// would be mostly halo; use the one-axis passes).  Same input and output
+// treatment as launch_smooth_axis.
+constexpr size_t kFusedLdsBytes = 128 * 1024;
+size_t fused_lds_limit();
+struct FusedPlan {
+  int tl, n_tiles, sx, sy;
+  size_t lds_bytes;
+};
+FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radius);
+hipError_t launch_smooth_rad_plane(const PostParams& g, const FusedPlan& plan, const void* in, bool in_is_f64,
+                                   double scale, const float* norm_in, float* out, const Taps& radial,
+                                   const Taps& plane, const float* norm_out, const float* sens, int sens_tof,
+                                   hipStream_t stream);
 // total[0] = sum over bins of (scale * W) * sens in binary64, in a fixed
 // order (partial: device scratch of kTotalPartials doubles).
 constexpr int kTotalPartials = 1024;

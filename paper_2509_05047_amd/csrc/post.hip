@@ -15,6 +15,8 @@
 // and the structures re-applied after).
 #include "post.h"
 
+#include <type_traits>
+
 namespace sse {
 namespace {
 
@@ -138,9 +140,10 @@ __device__ __forceinline__ float finish_out(const SmoothArgs& a, float acc, uint
 // loads are in flight meanwhile; finish() then applies them as finish_out.
 struct OutFactors {
   float nrm, sv;
-  __device__ __forceinline__ void load(const SmoothArgs& a, uint64_t o, uint64_t inner) {
+  // o: the bin; o_inner: the same bin without its TOF offset
+  __device__ __forceinline__ void load(const SmoothArgs& a, uint64_t o, uint64_t o_inner) {
     nrm = a.norm_out ? a.norm_out[o] : 1.0f;
-    sv = a.sens ? a.sens[a.sens_tof ? o : o % inner] : 1.0f;
+    sv = a.sens ? a.sens[a.sens_tof ? o : o_inner] : 1.0f;
   }
   __device__ __forceinline__ float finish(const SmoothArgs& a, float acc) const {
     if (a.norm_out) acc = nrm > 0.0f ? acc / nrm : acc;
@@ -149,17 +152,60 @@ struct OutFactors {
   }
 };
 
-// Outputs per thread in the sums: each tap (a scalar load) and, along the
-// view and plane axes, each staged value then serves four outputs.  The sums
-// are fused multiply-adds (each product enters unrounded): one instruction
-// per tap and output, and no less accurate than a product and a sum.
+// Outputs per lane in the radial pass of the one-axis route (each tap, a
+// scalar load, serves four).  All sums are fused multiply-adds (each product
+// enters unrounded): one instruction per tap and output, and no less accurate
+// than a product and a sum.
 constexpr int kOuts = 4;
-static_assert(kOuts == 4, "the sliding window of the column passes holds four values");
 
 // Loads issued back to back before their LDS stores in the view and plane
 // passes, so that each thread has this many in flight instead of one (a
 // clinical tile takes two or three such rounds).
 constexpr int kLoadBatch = 16;
+
+// Outputs per thread and item in the view, plane and fused passes.  Along
+// the sum each staged value serves kWin outputs and each block of four taps
+// (one 16-byte LDS read) 4 kWin fused multiply-adds, which keeps the LDS
+// traffic well under its bandwidth.
+constexpr int kWin = 8;
+
+// s[j] += sum over k = 0 .. n - 1 (in that order) of w[k] x[(j + k) stride],
+// j < kO: a window of staged values slides along the sum, four taps per
+// step.  w (the taps, 16-byte aligned) and x are in LDS, so the loop waits
+// only on LDS reads, which return in order.
+template <int kO>
+__device__ __forceinline__ void window_sums(const float* x, int stride, const float* w, int n, float (&s)[kO]) {
+  float win[kO + 3];  // x[k .. k + kO + 2]
+#pragma unroll
+  for (int i = 0; i < kO - 1; ++i) win[i] = x[i * stride];
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    const float4 w4 = *reinterpret_cast<const float4*>(w + k);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) win[kO - 1 + i] = x[(k + kO - 1 + i) * stride];
+    const float wt[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < kO; ++j) s[j] = __builtin_fmaf(wt[t], win[j + t], s[j]);
+#pragma unroll
+    for (int i = 0; i < kO - 1; ++i) win[i] = win[i + 4];
+  }
+  for (; k < n; ++k) {
+    const float wk = w[k];
+    win[kO - 1] = x[(k + kO - 1) * stride];
+#pragma unroll
+    for (int j = 0; j < kO; ++j) s[j] = __builtin_fmaf(wk, win[j], s[j]);
+#pragma unroll
+    for (int i = 0; i < kO - 1; ++i) win[i] = win[i + 1];
+  }
+}
+
+// The taps of a pass copied into LDS (block-wide; a barrier must follow
+// before they are read).
+__device__ __forceinline__ void stage_taps(const Taps& t, float* dst) {
+  for (int k = static_cast<int>(threadIdx.x); k < 2 * t.radius + 1; k += static_cast<int>(blockDim.x)) dst[k] = t.w[k];
+}
 
 // Passes along the view (kAxis 1) or plane (kAxis 2) axis.  A block stages
 // a tile of a.tile_len positions along the axis (plus the kernel's halo) by
@@ -167,105 +213,167 @@ constexpr int kLoadBatch = 16;
 // 256-byte rows, one wavefront per row -- and computes the tile's outputs
 // from LDS.  The tile (dynamic LDS) is sized by the radius: the launch
 // picks the longest tile_len <= 128 whose tile fits kColTileBytes (three
-// blocks per CU at least; four or more for the finalize's radii).  Views
+// 512-thread blocks per CU at least).  Views
 // are periodic over 180 degrees, and past the seam the same LOR is seen
 // from the other end (radial and TOF indices reversed); planes reflect at
 // the ends.
+//
+// Block b serves tile (b / 8) % T of slab 8 (b / 8T) + b % 8 (a slab: one
+// TOF bin and one position on the other axis; T tiles: column tiles times
+// axis tiles): workgroups go round-robin over the eight XCDs, so the tiles
+// of one slab run on one XCD one after another, and a tile's halo rows and
+// the cache lines it shares with the neighbouring column tiles (rows are not
+// line-aligned) are the neighbours' data in that L2.  With kFinish (the last
+// pass) every thread reads the normalisation and sensitivity factors of all
+// its outputs before it stages the tile, so that their latency overlaps the
+// staging loads instead of stalling each block of outputs.  (A persistent,
+// pipelined form of this pass, like the fused radial and plane pass, measured
+// no faster: its tiles are short sums over few taps.)
 constexpr int kTC = 64;
 constexpr int kMaxTileLen = 128;
 constexpr size_t kColTileBytes = 48 * 1024;
+constexpr int kColThreads = 512;
+constexpr int kColMinBlocks = 3;  // resident blocks per CU the register budget allows for
+constexpr int kColRowsPerSweep = kColThreads / kTC;
+constexpr int kColGroups = kMaxTileLen / (kWin * kColRowsPerSweep);  // output blocks per thread
 
 // LDS bytes of a column-pass tile: tile_len positions (at most n), the halo,
-// and kOuts - 1 rows read (unused) by the last thread's block of outputs.
+// and kWin - 1 rows read (unused) by the last thread's block of outputs.
 size_t col_tile_bytes(int tile_len, int n, int radius) {
   const int len = tile_len < n ? tile_len : n;
-  return static_cast<size_t>(len + 2 * radius + kOuts - 1) * kTC * sizeof(float);
+  return static_cast<size_t>(len + 2 * radius + kWin - 1) * kTC * sizeof(float);
 }
 
-template <int kAxis, bool kFromF64>
-__global__ void __launch_bounds__(256) smooth_cols(SmoothArgs a) {
+__device__ __forceinline__ bool xcd_tile(uint32_t b, uint32_t T, uint32_t n_groups, uint32_t& group, uint32_t& tile) {
+  group = (b / (8u * T)) * 8u + (b & 7u);
+  tile = (b >> 3) % T;
+  return group < n_groups;
+}
+
+// Position i (any integer) folded into [0, 2n) by whole periods: the halos
+// reach at most kMaxSmoothRadius past an end, so this takes one step or
+// none unless the axis is shorter than the radius.
+__device__ __forceinline__ int fold(int i, int n) {
+  const int period = 2 * n;
+  while (i < 0) i += period;
+  while (i >= period) i -= period;
+  return i;
+}
+
+// Binary32 input value at element offset o of a row that starts at element
+// `row` (the scaled and rounded binary64 weight, or the binary32 input).
+template <bool kFromF64>
+__device__ __forceinline__ float raw_at(const SmoothArgs& a, uint64_t row, uint32_t o) {
+  if (kFromF64) return static_cast<float>(a.scale * (static_cast<const double*>(a.in) + row)[o]);
+  return (static_cast<const float*>(a.in) + row)[o];
+}
+
+template <int kAxis, bool kFromF64, bool kFinish>
+__global__ void __launch_bounds__(kColThreads, kColMinBlocks) smooth_cols(SmoothArgs a, int n_col_tiles, int n_axis_tiles) {
   extern __shared__ float tile[];
+  __shared__ __align__(16) float tw[2 * kMaxSmoothRadius + 4];
   const PostParams& g = a.g;
   const int R = a.taps.radius;
   const int n = kAxis == 1 ? g.n_view : g.n_plane;
   const int n_other = kAxis == 1 ? g.n_plane : g.n_view;
-  const int r0 = blockIdx.x * kTC;
-  const int p0 = blockIdx.y * a.tile_len;
+  uint32_t group, tile_id;
+  if (!xcd_tile(blockIdx.x, static_cast<uint32_t>(n_col_tiles * n_axis_tiles),
+                static_cast<uint32_t>(n_other * g.n_tof), group, tile_id))
+    return;
+  // block-uniform geometry
+  const int xt = static_cast<int>(tile_id % static_cast<uint32_t>(n_col_tiles));
+  const uint32_t ytile = tile_id / static_cast<uint32_t>(n_col_tiles);
+  const int z = static_cast<int>(group);
+  const int r0 = xt * kTC;
+  const int p0 = static_cast<int>(ytile) * a.tile_len;
   const int tl = n - p0 < a.tile_len ? n - p0 : a.tile_len;
-  const int t = blockIdx.z / n_other;
-  const int other = blockIdx.z - t * n_other;
+  const int t = z / n_other;
+  const int other = z - t * n_other;
   const uint64_t vs = static_cast<uint64_t>(g.n_rad);
   const uint64_t ps = vs * g.n_view;
   const uint64_t ts = ps * g.n_plane;
-  const int col = threadIdx.x & (kTC - 1);
-  const int sub = threadIdx.x / kTC;
-  constexpr int kRowsPerSweep = 256 / kTC;
+  const uint64_t ax = kAxis == 1 ? vs : ps;                     // stride along the axis
+  const uint64_t other_off = kAxis == 1 ? other * ps : other * vs;
+  const uint64_t out0 = static_cast<uint64_t>(t) * ts + other_off + static_cast<uint64_t>(p0) * ax;
+  // per lane: the radial column (clamped into the row for lanes past its end)
+  const int col = static_cast<int>(threadIdx.x & (kTC - 1));
+  const int sub = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kTC));  // the wave
   const int r = r0 + col;
+  const bool live = r < g.n_rad;
+  const uint32_t rc = static_cast<uint32_t>(live ? r : g.n_rad - 1);
+  const uint32_t rflip = static_cast<uint32_t>(g.n_rad - 1) - rc;
   const int rows = tl + 2 * R;
-  // input index of tile row i (row p0 - R + i along the axis)
-  auto in_index = [&](int i) -> uint64_t {
-    const int pos = p0 - R + i;
-    if (kAxis == 2)
-      return static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(reflect(pos, g.n_plane)) * ps +
-             static_cast<uint64_t>(other) * vs + static_cast<uint64_t>(r);
-    const int period = 2 * g.n_view;
-    int m = pos % period;
-    if (m < 0) m += period;
-    return m < g.n_view ? static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(other) * ps +
-                              static_cast<uint64_t>(m) * vs + static_cast<uint64_t>(r)
-                        : static_cast<uint64_t>(g.n_tof - 1 - t) * ts + static_cast<uint64_t>(other) * ps +
-                              static_cast<uint64_t>(m - g.n_view) * vs + static_cast<uint64_t>(g.n_rad - 1 - r);
-  };
-  for (int i0 = sub; i0 < rows; i0 += kLoadBatch * kRowsPerSweep) {
-    uint64_t idx[kLoadBatch];
-    bool ok[kLoadBatch];
+  stage_taps(a.taps, tw);
+  // outputs i0 .. i0 + kWin - 1 of block q: i0 = kWin (sub + kColRowsPerSweep q)
+  OutFactors f[kFinish ? kColGroups : 1][kWin];
+  if (kFinish && live) {
+#pragma unroll
+    for (int q = 0; q < kColGroups; ++q) {
+      const int i0 = kWin * (sub + kColRowsPerSweep * q);
+      if (i0 < tl) {
+#pragma unroll
+        for (int j = 0; j < kWin; ++j) {
+          const uint64_t o = out0 + static_cast<uint64_t>(i0 + j < tl ? i0 + j : i0) * ax + rc;
+          f[q][j].load(a, o, o - static_cast<uint64_t>(t) * ts);
+        }
+      }
+    }
+  }
+  // Stage: the wave's rows i = sub + 4 k (tile row i is position p0 - R + i
+  // along the axis); row offsets are wave-uniform, only the column varies.
+  for (int i0 = sub; i0 < rows; i0 += kLoadBatch * kColRowsPerSweep) {
+    uint64_t roff[kLoadBatch];
+    uint32_t c[kLoadBatch];
+#pragma unroll
+    for (int b = 0; b < kLoadBatch; ++b) {
+      const int i = i0 + b * kColRowsPerSweep;
+      const int pos = p0 - R + (i < rows ? i : rows - 1);
+      if (kAxis == 2) {
+        const int m = fold(pos, g.n_plane);
+        const int pl = m < g.n_plane ? m : 2 * g.n_plane - 1 - m;
+        roff[b] = static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(pl) * ps + other_off;
+        c[b] = rc;
+      } else {
+        const int m = fold(pos, g.n_view);  // past the seam: the other end of the LOR
+        const bool flip = m >= g.n_view;
+        roff[b] = static_cast<uint64_t>(flip ? g.n_tof - 1 - t : t) * ts + other_off +
+                  static_cast<uint64_t>(flip ? m - g.n_view : m) * vs;
+        c[b] = flip ? rflip : rc;
+      }
+    }
     float v[kLoadBatch];
 #pragma unroll
-    for (int b = 0; b < kLoadBatch; ++b) {
-      const int i = i0 + b * kRowsPerSweep;
-      ok[b] = i < rows && r < g.n_rad;
-      idx[b] = ok[b] ? in_index(i) : 0;
+    for (int b = 0; b < kLoadBatch; ++b)
+      if (i0 + b * kColRowsPerSweep < rows) v[b] = raw_at<kFromF64>(a, roff[b], c[b]);
+    if (a.norm_in) {
+      float nv[kLoadBatch];
+#pragma unroll
+      for (int b = 0; b < kLoadBatch; ++b)
+        if (i0 + b * kColRowsPerSweep < rows) nv[b] = (a.norm_in + roff[b])[c[b]];
+#pragma unroll
+      for (int b = 0; b < kLoadBatch; ++b) v[b] = v[b] * nv[b];
     }
-    load_batch<kFromF64, kLoadBatch>(a, idx, ok, v);
 #pragma unroll
     for (int b = 0; b < kLoadBatch; ++b) {
-      const int i = i0 + b * kRowsPerSweep;
+      const int i = i0 + b * kColRowsPerSweep;
       if (i < rows) tile[i * kTC + col] = v[b];
     }
   }
   __syncthreads();
-  if (r >= g.n_rad) return;
-  // outputs i0 .. i0 + kOuts - 1 (those below tl are stored): a window of
-  // kOuts staged values slides down the tile, each output summing its taps
-  // in order k = 0 .. 2R as a one-output loop would
-  for (int i0 = kOuts * sub; i0 < tl; i0 += kOuts * kRowsPerSweep) {
-    uint64_t o[kOuts];
-    OutFactors f[kOuts];
+  if (!live) return;
+  // a window of staged values slides down the tile, each output summing its
+  // taps in order k = 0 .. 2R as a one-output loop would
 #pragma unroll
-    for (int j = 0; j < kOuts; ++j) {
-      const int pos = p0 + (i0 + j < tl ? i0 + j : i0);
-      o[j] = kAxis == 2 ? static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(pos) * ps +
-                              static_cast<uint64_t>(other) * vs + static_cast<uint64_t>(r)
-                        : static_cast<uint64_t>(t) * ts + static_cast<uint64_t>(other) * ps +
-                              static_cast<uint64_t>(pos) * vs + static_cast<uint64_t>(r);
-      f[j].load(a, o[j], ts);
-    }
-    float acc[kOuts] = {};
-    float x0 = tile[i0 * kTC + col], x1 = tile[(i0 + 1) * kTC + col], x2 = tile[(i0 + 2) * kTC + col];
-    for (int k = 0; k <= 2 * R; ++k) {
-      const float w = a.taps.w[k];
-      const float x3 = tile[(i0 + k + 3) * kTC + col];
-      acc[0] = __builtin_fmaf(w, x0, acc[0]);
-      acc[1] = __builtin_fmaf(w, x1, acc[1]);
-      acc[2] = __builtin_fmaf(w, x2, acc[2]);
-      acc[3] = __builtin_fmaf(w, x3, acc[3]);
-      x0 = x1;
-      x1 = x2;
-      x2 = x3;
-    }
+  for (int q = 0; q < kColGroups; ++q) {
+    const int i0 = kWin * (sub + kColRowsPerSweep * q);
+    if (i0 >= tl) break;
+    float acc[kWin] = {};
+    window_sums<kWin>(tile + i0 * kTC + col, kTC, tw, 2 * R + 1, acc);
 #pragma unroll
-    for (int j = 0; j < kOuts; ++j)
-      if (i0 + j < tl) a.out[o[j]] = f[j].finish(a, acc[j]);
+    for (int j = 0; j < kWin; ++j)
+      if (i0 + j < tl)
+        (a.out + out0 + static_cast<uint64_t>(i0 + j) * ax)[rc] =
+            kFinish ? f[kFinish ? q : 0][j].finish(a, acc[j]) : acc[j];
   }
 }
 
@@ -310,6 +418,7 @@ __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint64_t inner = static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane;
+  const uint64_t tof_off = row / (static_cast<uint64_t>(g.n_view) * g.n_plane) * inner;
   // outputs lane + 64 j (kSeg = 64 kOuts: the whole segment), each tap
   // read once for all of them; reads for outputs past len stay inside buf
   const int i = static_cast<int>(lane);
@@ -318,7 +427,7 @@ __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows
 #pragma unroll
   for (int j = 0; j < kOuts; ++j) {
     o[j] = base + static_cast<uint64_t>(s0 + (i + 64 * j < len ? i + 64 * j : 0));
-    f[j].load(a, o[j], inner);
+    f[j].load(a, o[j], o[j] - tof_off);
   }
   float acc[kOuts] = {};
   for (int k = 0; k <= 2 * R; ++k) {
@@ -329,6 +438,260 @@ __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows
 #pragma unroll
   for (int j = 0; j < kOuts; ++j)
     if (i + 64 * j < len) a.out[o[j]] = f[j].finish(a, acc[j]);
+}
+
+// Radial and plane passes fused over one (TOF, view) row: a tile of f.tl
+// radial positions by every plane, plus the radial halo (reflected at the
+// row ends), is staged in LDS; the rows are smoothed radially into
+// registers and written back over the staged input, each plane also into
+// the rows of the plane halo that reflect it, and the columns are smoothed
+// along the planes from there.  HBM sees the input once (plus the radial
+// halo, which the tile's neighbours on the same XCD read at about the same
+// time) and the output once: the intermediate never leaves the CU.
+//
+// The kernel is persistent, one 1024-thread block per CU, and pipelined:
+// while a block smooths one tile, the loads of its next tile are in flight
+// into registers, so the CU's memory traffic overlaps its arithmetic instead
+// of alternating with it.
+//
+// Radial outputs come in blocks of kFusedWin per thread (sliding window,
+// lanes on consecutive planes: the row stride is odd, so the lanes hit
+// distinct banks); plane outputs likewise, lanes on consecutive radial
+// positions.  Both sums run their taps in the order k = 0 .. 2R as the
+// one-axis passes do.
+struct FusedArgs {
+  SmoothArgs a;   // a.taps: the radial taps
+  Taps plane;     // the plane taps
+  int tl;         // radial outputs per tile (<= kFusedMaxTile)
+  int n_tiles;    // tiles per (TOF, view) row
+  int sx;         // LDS row stride of the staged input (odd, >= tl + 2 R + kFusedWin - 1)
+  int sy;         // LDS row stride of the radially smoothed rows (odd, >= tl)
+  uint32_t n_units;  // tile slots of the XCD mapping (8 ceil(rows / 8) n_tiles)
+};
+constexpr int kFusedThreads = 1024;
+constexpr int kFusedWaves = kFusedThreads / 64;
+constexpr int kFusedPrefetch = 16;                          // staged elements per thread
+constexpr int kFusedStage = kFusedThreads * kFusedPrefetch;  // staged elements per tile
+constexpr int kFusedWin = kWin;  // outputs per thread and item
+constexpr int kFusedItems = 2;   // radial output blocks per thread
+constexpr int kFusedMaxTile = 128;
+
+// One tile's geometry.
+struct FusedTile {
+  int t, r0, tl, wx;
+  uint64_t row0;  // element offset of (t, plane 0, view, column 0)
+};
+
+__device__ __forceinline__ bool fused_tile(const FusedArgs& f, uint32_t u, FusedTile& ft) {
+  const PostParams& g = f.a.g;
+  uint32_t row, tile;
+  if (!xcd_tile(u, static_cast<uint32_t>(f.n_tiles), static_cast<uint32_t>(g.n_view) * static_cast<uint32_t>(g.n_tof),
+                row, tile))
+    return false;
+  ft.t = static_cast<int>(row / static_cast<uint32_t>(g.n_view));
+  const int v = static_cast<int>(row) - ft.t * g.n_view;
+  ft.r0 = static_cast<int>(tile) * f.tl;
+  ft.tl = g.n_rad - ft.r0 < f.tl ? g.n_rad - ft.r0 : f.tl;
+  ft.wx = ft.tl + 2 * f.a.taps.radius;
+  const uint64_t vs = static_cast<uint64_t>(g.n_rad);
+  ft.row0 = static_cast<uint64_t>(ft.t) * vs * g.n_view * g.n_plane + static_cast<uint64_t>(v) * vs;
+  return true;
+}
+
+// The next unit of this block at or after u that holds a tile (n_units if none).
+__device__ __forceinline__ uint32_t fused_next(const FusedArgs& f, uint32_t u, FusedTile& ft) {
+  for (; u < f.n_units; u += gridDim.x)
+    if (fused_tile(f, u, ft)) return u;
+  return f.n_units;
+}
+
+// Prefetch registers of one staged tile: element e = threadIdx.x + 1024 i
+// is plane e / wx, staged column e % wx (stepped without division).  Every
+// element slot is loaded (slots past the tile from a clamped, valid index,
+// never stored), so that the loads are straight-line code and nothing waits
+// between them.
+template <bool kFromF64, bool kNormIn>
+struct FusedPrefetch {
+  using Raw = typename std::conditional<kFromF64, double, float>::type;
+  Raw w[kFusedPrefetch];
+  float nrm[kNormIn ? kFusedPrefetch : 1];
+
+  __device__ __forceinline__ void issue(const SmoothArgs& a, const FusedTile& ft, int np, uint64_t ps) {
+    const int dp = kFusedThreads / ft.wx, dc = kFusedThreads % ft.wx;
+    int p = static_cast<int>(threadIdx.x) / ft.wx, c = static_cast<int>(threadIdx.x) % ft.wx;
+    const Raw* in = static_cast<const Raw*>(a.in) + ft.row0;
+    const float* nin = a.norm_in + ft.row0;
+    const int n_rad = a.g.n_rad;
+#pragma unroll
+    for (int i = 0; i < kFusedPrefetch; ++i) {
+      // one reflection at most: the planner keeps the radius <= n_rad
+      int col = ft.r0 - a.taps.radius + c;
+      col = col < 0 ? -col - 1 : col;
+      col = col >= n_rad ? 2 * n_rad - 1 - col : col;
+      const int pc = p < np ? p : np - 1;
+      const uint64_t o = static_cast<uint64_t>(pc) * ps + static_cast<uint64_t>(col);
+      w[i] = in[o];
+      if (kNormIn) nrm[kNormIn ? i : 0] = nin[o];
+      p += dp;
+      c += dc;
+      if (c >= ft.wx) {
+        c -= ft.wx;
+        ++p;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(const SmoothArgs& a, const FusedTile& ft, int np, int sx, float* lds) const {
+    const int n = np * ft.wx;
+    const int dp = kFusedThreads / ft.wx, dc = kFusedThreads % ft.wx;
+    int p = static_cast<int>(threadIdx.x) / ft.wx, c = static_cast<int>(threadIdx.x) % ft.wx;
+#pragma unroll
+    for (int i = 0; i < kFusedPrefetch; ++i) {
+      const int e = static_cast<int>(threadIdx.x) + kFusedThreads * i;
+      float x = kFromF64 ? static_cast<float>(a.scale * static_cast<double>(w[i])) : static_cast<float>(w[i]);
+      if (kNormIn) x = x * nrm[kNormIn ? i : 0];
+      if (e < n) lds[p * sx + c] = x;
+      p += dp;
+      c += dc;
+      if (c >= ft.wx) {
+        c -= ft.wx;
+        ++p;
+      }
+    }
+  }
+};
+
+template <bool kFromF64, bool kNormIn, bool kFinish>
+__global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f) {
+  extern __shared__ float lds[];
+  __shared__ __align__(16) float tw_r[2 * kMaxSmoothRadius + 4];
+  __shared__ __align__(16) float tw_p[2 * kMaxSmoothRadius + 4];
+  const SmoothArgs& a = f.a;
+  const PostParams& g = a.g;
+  const int Rr = a.taps.radius, Rp = f.plane.radius;
+  const int np = g.n_plane;
+  stage_taps(a.taps, tw_r);  // read after the first barrier below
+  stage_taps(f.plane, tw_p);
+  const uint64_t ps = static_cast<uint64_t>(g.n_rad) * g.n_view;
+  const uint64_t ts = ps * g.n_plane;
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int y_rows = np + 2 * Rp + kFusedWin - 1;  // smoothed planes and plane halo
+  // the halo rows are written with the planes they reflect when one
+  // reflection reaches them all, else copied in a pass of their own
+  const bool direct_halo = Rp + kFusedWin - 1 <= np;
+
+  FusedTile cur, nxt;
+  uint32_t u = fused_next(f, blockIdx.x, cur);
+  if (u >= f.n_units) return;
+  FusedPrefetch<kFromF64, kNormIn> pre;
+  pre.issue(a, cur, np, ps);
+  while (true) {
+    pre.store(a, cur, np, f.sx, lds);
+    __syncthreads();
+    const uint32_t un = fused_next(f, u + gridDim.x, nxt);
+    if (un < f.n_units) pre.issue(a, nxt, np, ps);  // in flight while this tile is smoothed
+    const int tl = cur.tl;
+
+    // Radial sums: item i = threadIdx.x + 1024 m is plane i % np, outputs
+    // kFusedWin (i / np) .. + kFusedWin - 1 of the tile.
+    const int n_ch = (tl + kFusedWin - 1) / kFusedWin;
+    const int dp = kFusedThreads % np, dch = kFusedThreads / np;
+    float acc[kFusedItems][kFusedWin];
+    {
+      int p = static_cast<int>(threadIdx.x) % np, ch = static_cast<int>(threadIdx.x) / np;
+#pragma unroll
+      for (int m = 0; m < kFusedItems; ++m) {
+#pragma unroll
+        for (int j = 0; j < kFusedWin; ++j) acc[m][j] = 0.0f;
+        if (ch < n_ch) window_sums<kFusedWin>(lds + p * f.sx + kFusedWin * ch, 1, tw_r, 2 * Rr + 1, acc[m]);
+        p += dp;
+        ch += dch;
+        if (p >= np) {
+          p -= np;
+          ++ch;
+        }
+      }
+    }
+    __syncthreads();  // every staged value read: the rows below overwrite them
+
+    // Radially smoothed plane p goes to row Rp + p and, with direct_halo,
+    // to the halo rows that reflect it: Rp - 1 - p (p < Rp) and
+    // Rp + 2 np - 1 - p (when below y_rows; the last kFusedWin - 1 halo rows
+    // are read only by outputs past the final plane).
+    {
+      int p = static_cast<int>(threadIdx.x) % np, ch = static_cast<int>(threadIdx.x) / np;
+#pragma unroll
+      for (int m = 0; m < kFusedItems; ++m) {
+        if (ch < n_ch) {
+          const int c0 = kFusedWin * ch;
+          float* yr = lds + (Rp + p) * f.sy + c0;
+          float* ytop = lds + (Rp - 1 - p) * f.sy + c0;
+          float* ybot = lds + (Rp + 2 * np - 1 - p) * f.sy + c0;
+          const bool top = direct_halo && p < Rp;
+          const bool bot = direct_halo && Rp + 2 * np - 1 - p < y_rows;
+#pragma unroll
+          for (int j = 0; j < kFusedWin; ++j)
+            if (c0 + j < tl) {
+              yr[j] = acc[m][j];
+              if (top) ytop[j] = acc[m][j];
+              if (bot) ybot[j] = acc[m][j];
+            }
+        }
+        p += dp;
+        ch += dch;
+        if (p >= np) {
+          p -= np;
+          ++ch;
+        }
+      }
+    }
+    __syncthreads();
+    if (!direct_halo) {  // halo rows by folding (radius near the plane count)
+      for (int h = wave; h < 2 * Rp + kFusedWin - 1; h += kFusedWaves) {
+        const int e = h < Rp ? h : np + h;
+        const int m = fold(e - Rp, np);
+        const int src = Rp + (m < np ? m : 2 * np - 1 - m);
+        for (int c = lane; c < tl; c += 64) lds[e * f.sy + c] = lds[src * f.sy + c];
+      }
+      __syncthreads();
+    }
+
+    // Plane sums: item i is radial position i % tl, planes kFusedWin (i / tl)
+    // .. + kFusedWin - 1.
+    const int n_pg = (np + kFusedWin - 1) / kFusedWin;
+    float* out_row = a.out + cur.row0 + static_cast<uint64_t>(cur.r0);  // plane 0 of the tile
+    const int dc = kFusedThreads % tl, dpg = kFusedThreads / tl;
+    int c = static_cast<int>(threadIdx.x) % tl, pg = static_cast<int>(threadIdx.x) / tl;
+    while (pg < n_pg) {
+      OutFactors fo[kFinish ? kFusedWin : 1];
+      if (kFinish) {
+#pragma unroll
+        for (int j = 0; j < kFusedWin; ++j) {
+          const int p = kFusedWin * pg + j < np ? kFusedWin * pg + j : kFusedWin * pg;
+          const uint64_t o = cur.row0 + static_cast<uint64_t>(p) * ps + static_cast<uint64_t>(cur.r0 + c);
+          fo[kFinish ? j : 0].load(a, o, o - static_cast<uint64_t>(cur.t) * ts);
+        }
+      }
+      float sm[kFusedWin] = {};
+      window_sums<kFusedWin>(lds + kFusedWin * pg * f.sy + c, f.sy, tw_p, 2 * Rp + 1, sm);
+#pragma unroll
+      for (int j = 0; j < kFusedWin; ++j)
+        if (kFusedWin * pg + j < np)
+          (out_row + static_cast<uint64_t>(kFusedWin * pg + j) * ps)[c] =
+              kFinish ? fo[kFinish ? j : 0].finish(a, sm[j]) : sm[j];
+      c += dc;
+      pg += dpg;
+      if (c >= tl) {
+        c -= tl;
+        ++pg;
+      }
+    }
+    if (un >= f.n_units) break;
+    __syncthreads();  // the plane sums have read the rows the next staging overwrites
+    u = un;
+    cur = nxt;
+  }
 }
 
 // No axis smoothed: out = ((float)(scale W) or in) * norm_in / norm_out * sens.
@@ -384,6 +747,93 @@ hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale,
   return hipGetLastError();
 }
 
+namespace {
+// Compute units and LDS bytes per block of the current device (the
+// persistent kernels run one block per CU), cached per device.
+struct DeviceShape {
+  int cus;
+  size_t lds;
+};
+DeviceShape device_shape() {
+  static DeviceShape cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DeviceShape{256, 64 * 1024};
+  if (!cached[dev].cus) {
+    int cus = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0)
+      lds = 64 * 1024;
+    cached[dev] = DeviceShape{cus, static_cast<size_t>(lds)};
+  }
+  return cached[dev];
+}
+int device_cus() { return device_shape().cus; }
+}  // namespace
+
+size_t fused_lds_limit() {
+  const size_t dev = device_shape().lds;
+  const size_t static_lds = 2 * (2 * kMaxSmoothRadius + 4) * sizeof(float);  // the two tap arrays
+  const size_t avail = dev > static_lds ? dev - static_lds : 0;
+  return avail < kFusedLdsBytes ? avail : kFusedLdsBytes;
+}
+
+FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radius) {
+  FusedPlan pl{};
+  if (g.n_plane <= 0 || g.n_rad <= 0 || radial_radius > g.n_rad) return pl;
+  const size_t lds_max = fused_lds_limit();
+  for (int k = (g.n_rad + kFusedMaxTile - 1) / kFusedMaxTile;; ++k) {  // k tiles of about equal length
+    const int tl = (g.n_rad + k - 1) / k;
+    const int n_tiles = (g.n_rad + tl - 1) / tl;
+    if (tl < 16 && tl < g.n_rad) break;  // halo-dominated: the one-axis passes do better
+    const int64_t radial_items = static_cast<int64_t>(g.n_plane) * ((tl + kFusedWin - 1) / kFusedWin);
+    if (radial_items > static_cast<int64_t>(kFusedThreads) * kFusedItems) continue;
+    if (static_cast<int64_t>(g.n_plane) * (tl + 2 * radial_radius) > kFusedStage) continue;
+    const int sx = (tl + 2 * radial_radius + kFusedWin - 1) | 1;
+    const int sy = tl | 1;
+    const size_t x_floats = static_cast<size_t>(g.n_plane) * sx;
+    const size_t y_floats = static_cast<size_t>(g.n_plane + 2 * plane_radius + kFusedWin - 1) * sy;
+    const size_t lds = (x_floats > y_floats ? x_floats : y_floats) * sizeof(float);
+    if (lds <= lds_max) {
+      pl.tl = tl;
+      pl.n_tiles = n_tiles;
+      pl.sx = sx;
+      pl.sy = sy;
+      pl.lds_bytes = lds;
+      return pl;
+    }
+    if (tl == 1) break;
+  }
+  return pl;
+}
+
+hipError_t launch_smooth_rad_plane(const PostParams& g, const FusedPlan& pl, const void* in, bool in_is_f64,
+                                   double scale, const float* norm_in, float* out, const Taps& radial,
+                                   const Taps& plane, const float* norm_out, const float* sens, int sens_tof,
+                                   hipStream_t stream) {
+  if (pl.tl <= 0) return hipErrorInvalidValue;
+  const uint64_t rows = static_cast<uint64_t>(g.n_view) * g.n_tof;
+  const uint64_t units = (rows + 7) / 8 * 8 * static_cast<uint64_t>(pl.n_tiles);
+  if (units == 0) return hipSuccess;
+  if (units > 0xffffffffull) return hipErrorInvalidValue;
+  FusedArgs f{SmoothArgs{g, in, scale, norm_in, out, norm_out, sens, sens_tof, radial, 0}, plane, pl.tl,
+              pl.n_tiles, pl.sx, pl.sy, static_cast<uint32_t>(units)};
+  // one block per CU (a multiple of 8: a block's units stay on its XCD)
+  uint64_t blocks = static_cast<uint64_t>(device_cus() + 7) / 8 * 8;
+  if (blocks > units) blocks = (units + 7) / 8 * 8;
+  const bool fin = norm_out != nullptr || sens != nullptr;
+  const bool nin = norm_in != nullptr;
+  const dim3 grid(static_cast<unsigned>(blocks));
+#define SSE_FUSED(F64, NIN, FIN) \
+  hipLaunchKernelGGL((smooth_rad_plane<F64, NIN, FIN>), grid, dim3(kFusedThreads), pl.lds_bytes, stream, f)
+#define SSE_FUSED_FIN(F64, NIN) \
+  do { if (fin) SSE_FUSED(F64, NIN, true); else SSE_FUSED(F64, NIN, false); } while (0)
+  if (in_is_f64) { if (nin) SSE_FUSED_FIN(true, true); else SSE_FUSED_FIN(true, false); }
+  else { if (nin) SSE_FUSED_FIN(false, true); else SSE_FUSED_FIN(false, false); }
+#undef SSE_FUSED_FIN
+#undef SSE_FUSED
+  return hipGetLastError();
+}
+
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
                               const float* norm_in, float* out, const Taps& taps, const float* norm_out,
                               const float* sens, int sens_tof, hipStream_t stream) {
@@ -408,14 +858,21 @@ hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, boo
   while (tile_len > 16 && col_tile_bytes(tile_len, n, taps.radius) > kColTileBytes) tile_len /= 2;
   a.tile_len = tile_len;
   const size_t lds = col_tile_bytes(tile_len, n, taps.radius);  // <= kColTileBytes up to radius 63
-  const dim3 grid((g.n_rad + kTC - 1) / kTC, (n + tile_len - 1) / tile_len, static_cast<unsigned>(n_other * g.n_tof));
+  const int n_col_tiles = (g.n_rad + kTC - 1) / kTC;
+  const int n_axis_tiles = (n + tile_len - 1) / tile_len;
+  const uint64_t groups = static_cast<uint64_t>(n_other) * g.n_tof;
+  const dim3 grid(static_cast<unsigned>((groups + 7) / 8 * 8 * static_cast<uint64_t>(n_col_tiles * n_axis_tiles)));
+  const bool fin = norm_out != nullptr || sens != nullptr;
+#define SSE_COLS(AX, F64, FIN) \
+  hipLaunchKernelGGL((smooth_cols<AX, F64, FIN>), grid, dim3(kColThreads), lds, stream, a, n_col_tiles, n_axis_tiles)
   if (axis == 1) {
-    if (in_is_f64) hipLaunchKernelGGL((smooth_cols<1, true>), grid, dim3(256), lds, stream, a);
-    else hipLaunchKernelGGL((smooth_cols<1, false>), grid, dim3(256), lds, stream, a);
+    if (in_is_f64) { if (fin) SSE_COLS(1, true, true); else SSE_COLS(1, true, false); }
+    else { if (fin) SSE_COLS(1, false, true); else SSE_COLS(1, false, false); }
   } else {
-    if (in_is_f64) hipLaunchKernelGGL((smooth_cols<2, true>), grid, dim3(256), lds, stream, a);
-    else hipLaunchKernelGGL((smooth_cols<2, false>), grid, dim3(256), lds, stream, a);
+    if (in_is_f64) { if (fin) SSE_COLS(2, true, true); else SSE_COLS(2, true, false); }
+    else { if (fin) SSE_COLS(2, false, true); else SSE_COLS(2, false, false); }
   }
+#undef SSE_COLS
   return hipGetLastError();
 }
 

@@ -1,0 +1,50 @@
+"""Smoothing parity on sinogram shapes other than the workloads': the whole
+sinogram against the oracle's separable Gaussian (Methods, smoothing of the
+scatter estimate along the radial, angular and planar axes).  One shape has
+several radial tiles of the fused radial-and-plane pass with a ragged last
+tile; the other has so many planes that a tile of all of them does not fit
+in LDS and the library takes one pass per axis."""
+import numpy as np
+import pytest
+
+import oracle.post as post
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PAPER_SIGMA = tuple(f / 2.35482 for f in (9.0, 6.0, 10.5))
+HEAVY = tuple(3 * s for s in PAPER_SIGMA)
+
+SHAPES = {
+    # n_rad 257 over tiles of 86, 86, 85 radial positions; 23 planes
+    "wide": (W.Scanner(n_crystals=320, n_rings=12, radius_mm=300.0, length_mm=150.0, crystals_per_module=8,
+                       rings_per_block=4),
+             W.Sinogram(n_rad=257, n_view=160, n_plane=23, n_tof=3, tof_bin_mm=200.0, tof_sigma_mm=0.0)),
+    # 335 planes: the fused tile exceeds its LDS budget at these radii
+    "tall": (W.Scanner(n_crystals=64, n_rings=168, radius_mm=150.0, length_mm=600.0, crystals_per_module=4,
+                       rings_per_block=8),
+             W.Sinogram(n_rad=63, n_view=32, n_plane=335, n_tof=2, tof_bin_mm=150.0, tof_sigma_mm=0.0)),
+}
+
+
+@pytest.mark.parametrize("shape", sorted(SHAPES))
+@pytest.mark.parametrize("sigma", [PAPER_SIGMA, HEAVY, (2.0, 0.0, 3.0)], ids=["paper", "heavy", "no_view"])
+def test_smoothing_matches_oracle_on_whole_sinogram(shape, sigma):
+    import paper_2509_05047_amd as sse
+    scanner, sino = SHAPES[shape]
+    x = np.random.default_rng(11).uniform(0.1, 1.0, sino.shape).astype(np.float32)
+    ref = post.gaussian_smooth(x, sigma).reshape(sino.shape)
+    ctx = sse.Context(scanner, sino, dict(W.PHYSICS_DEFAULT))
+    try:
+        dx = torch.from_numpy(x.ravel()).cuda()
+        out = torch.empty_like(dx)
+        ctx.gaussian_smooth(dx, out, sigma)
+        ctx.gaussian_smooth(dx, dx, sigma)  # in place
+        torch.cuda.synchronize()
+        got, inplace = out.cpu().numpy().reshape(sino.shape), dx.cpu().numpy().reshape(sino.shape)
+    finally:
+        ctx.close()
+    assert np.array_equal(got, inplace)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert rel.max() < 1e-5, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
