@@ -100,7 +100,7 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
 // converged.  Reading a word is one LDS load: no register shuffling and no
 // dynamically indexed registers.
 typedef __attribute__((address_space(3))) uint32_t LdsWord;
-constexpr uint32_t kRngSlots = 16;
+constexpr uint32_t kRngSlots = 8;
 
 __device__ __forceinline__ float to_uniform(uint32_t x) {
   // uniform in (0, 1): 24 bits with the last forced odd, times 2^-24
@@ -349,12 +349,22 @@ __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct
 // Distance along d from p to the exit of the voxel box: the least of the
 // per-axis quotients, all three computed (no branches) and those of axes
 // the direction does not move along left out.
+// The box's bounds are read as wave-uniform values before the per-lane
+// select: a select between two parameter fields otherwise becomes a select
+// of their addresses and a vector load, whose latency the few lanes that
+// scatter in an iteration wait out.
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 __device__ __forceinline__ float box_exit(const TransportParams& p, float px, float py, float pz, float dx,
                                           float dy, float dz) {
+  const float lox = uniform_f(p.lox), loy = uniform_f(p.loy), loz = uniform_f(p.loz);
+  const float hix = uniform_f(p.hix), hiy = uniform_f(p.hiy), hiz = uniform_f(p.hiz);
   // a quotient by a zero component is not used (its value does not matter)
-  const float qx = fdiv(dx > 0.0f ? p.hix - px : p.lox - px, dx);
-  const float qy = fdiv(dy > 0.0f ? p.hiy - py : p.loy - py, dy);
-  const float qz = fdiv(dz > 0.0f ? p.hiz - pz : p.loz - pz, dz);
+  const float qx = fdiv(dx > 0.0f ? hix - px : lox - px, dx);
+  const float qy = fdiv(dy > 0.0f ? hiy - py : loy - py, dy);
+  const float qz = fdiv(dz > 0.0f ? hiz - pz : loz - pz, dz);
   float t = __builtin_huge_valf();
   t = dx != 0.0f ? fminf(t, qx) : t;
   t = dy != 0.0f ? fminf(t, qy) : t;
@@ -559,8 +569,16 @@ constexpr int kStepTail = 10;
 // Rejection rounds per iteration for the Compton sampler; a lane still
 // rejecting goes on in the next iteration with its try count.
 constexpr int kRounds = 2;
-// Waves per SIMD the transport kernels are compiled for (registers).
-constexpr int kTransportWavesPerEu = 3;
+// Waves per SIMD the transport kernels are compiled for (registers, at most
+// 102 each).  With eight random-word slots per lane the work-list kernel's
+// LDS (about 31 KB per block) also admits five 256-thread blocks per CU:
+// the loop waits on its gathers and LDS reads, and a fifth wave per SIMD
+// hides more of that than the deeper word buffer of sixteen slots saved in
+// refills (measured: 68.4 against 72.2 ms for 1e9 clinical histories).
+constexpr int kTransportWavesPerEu = 5;
+// The instrumented instantiation (statistics and records) keeps more state
+// live; it is compiled for three.
+constexpr int kInstrWavesPerEu = 3;
 
 // ---------------------------------------------------------------------------
 // coincidences
@@ -964,10 +982,10 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
       }
     }
     if (__all(phase == kDone)) break;
-    // Converged top-up: three rounds in which every live lane with room
-    // generates a block (a new history gets twelve words).
+    // Converged top-up: two rounds in which every live lane with room
+    // generates a block (a new history gets eight words, the whole buffer).
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 2; ++k) {
       if (__any(phase != kDone && r.room())) {
         if (phase != kDone && r.room()) r.refill(k0, k1);
       }
@@ -1279,7 +1297,7 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
 // per-history records); false: the production path, with neither.  Every
 // wavefront owns a contiguous share of [h0, h0 + n).
 template <bool kInstr>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTransportWavesPerEu)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kInstr ? kInstrWavesPerEu : kTransportWavesPerEu)))
 transport_kernel(TransportParams p) {
   const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
