@@ -190,9 +190,11 @@ sse_status sse_destroy(sse_ctx* ctx);
  * (`mem`).  The emission sampler (an integer alias table over voxels) is
  * built on the host.  The activity and attenuation images are the
  * simulator's inputs (Fig. 3 caption).  *out receives the phantom id.
- * Synchronous with respect to the host inputs.  Errors: SSE_EINVAL (bad
- * descriptor, negative or non-finite values, all-zero activity, box outside
- * the cylinder), SSE_ENOMEM. */
+ * Synchronous with respect to the host inputs.  Allowed while a server runs
+ * on the context (thread-safe against its scheduler; the new phantom's
+ * device memory counts against the server's HBM budget).  Errors:
+ * SSE_EINVAL (bad descriptor, negative or non-finite values, all-zero
+ * activity, box outside the cylinder), SSE_ENOMEM. */
 sse_status sse_load_phantom(sse_ctx* ctx, const sse_phantom_desc* desc, const float* mu511_per_mm,
                             const float* activity, int mem, void* stream, sse_phantom_id* out);
 
@@ -557,7 +559,8 @@ typedef struct sse_server sse_server;
 typedef struct {
   int32_t max_active;          /* requests simulated concurrently, 1..256 */
   int32_t reserved;
-  uint64_t hbm_budget_bytes;   /* cap on library-allocated output buffers; 0 = 90 % of free device memory */
+  uint64_t hbm_budget_bytes;   /* cap on library-allocated output buffers, with the device memory of phantoms
+                                  loaded after the start; 0 = 90 % of the device memory free at the start */
   uint64_t tick_histories;     /* histories per tick over all active requests; 0 = 32 Mi */
   uint64_t chunk_histories;    /* histories per work-list sub-chunk (<= 2^31; the kernel balances its launches by
                                   claiming 256 histories at a time); 0 = a sixteenth of a tick, at least 256 */

@@ -50,8 +50,10 @@ bool lut_fits_gaps(const sse_scanner_desc& sc, const sse_lut_desc& d) {
 }
 
 Phantom* get_phantom(sse_ctx* c, sse_phantom_id id) {
-  if (!c || id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1].used) return nullptr;
-  return &c->phantoms[id - 1];
+  if (!c) return nullptr;
+  std::lock_guard<std::mutex> lk(c->phantoms_mu);
+  if (id == 0 || id > c->phantoms.size() || !c->phantoms[id - 1]->used) return nullptr;
+  return c->phantoms[id - 1].get();
 }
 
 void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, uint64_t h0, uint64_t n,
@@ -522,10 +524,10 @@ sse_status sse_destroy(sse_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (auto& p : c->phantoms) {
-    release(p.d_mu);
-    release(p.d_alias);
-    release(p.d_mu8);
-    release(p.d_mu_table);
+    release(p->d_mu);
+    release(p->d_alias);
+    release(p->d_mu8);
+    release(p->d_mu_table);
   }
   if (c->d_lut) release(c->d_lut);
   if (c->d_sens) release(c->d_sens);
@@ -605,13 +607,16 @@ sse_status sse_load_phantom(sse_ctx* c, const sse_phantom_desc* d, const float* 
     release(p.d_mu_table);
     return st;
   }
+  p.device_bytes = n * (sizeof(float) + sizeof(uint2)) + (p.d_mu8 ? n + 256 * sizeof(float) : 0);
+  std::lock_guard<std::mutex> lk(c->phantoms_mu);
+  c->phantom_bytes += p.device_bytes;
   for (size_t i = 0; i < c->phantoms.size(); ++i)
-    if (!c->phantoms[i].used) {
-      c->phantoms[i] = p;
+    if (!c->phantoms[i]->used) {
+      *c->phantoms[i] = p;
       *out = static_cast<sse_phantom_id>(i + 1);
       return SSE_OK;
     }
-  c->phantoms.push_back(p);
+  c->phantoms.push_back(std::make_unique<Phantom>(p));
   *out = static_cast<sse_phantom_id>(c->phantoms.size());
   return SSE_OK;
 }
@@ -647,6 +652,8 @@ sse_status sse_unload_phantom(sse_ctx* c, sse_phantom_id id) {
   release(p->d_alias);
   release(p->d_mu8);
   release(p->d_mu_table);
+  std::lock_guard<std::mutex> lk(c->phantoms_mu);
+  c->phantom_bytes -= p->device_bytes;
   *p = Phantom();
   return SSE_OK;
 }

@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct Phantom {
   uint2* d_alias = nullptr;
   uint8_t* d_mu8 = nullptr;      // palette indices when the map has <= 256 distinct values
   float* d_mu_table = nullptr;   // the 256-entry palette (exact values)
+  uint64_t device_bytes = 0;     // of the four device arrays above
   std::shared_ptr<AliasWork> alias_work;
 };
 
@@ -48,7 +50,13 @@ struct sse_ctx {
   sse_sino_desc sn{};
   sse_physics_desc ph{};
   uint64_t n_bins = 0;
-  std::vector<Phantom> phantoms;
+  // phantom slots (id = index + 1); each phantom has a fixed address, and
+  // the list is changed and searched under phantoms_mu, since a server's
+  // scheduler thread looks phantoms up while the caller may load more;
+  // phantom_bytes is the device memory of the loaded ones
+  std::vector<std::unique_ptr<Phantom>> phantoms;
+  std::mutex phantoms_mu;
+  std::atomic<uint64_t> phantom_bytes{0};
   void* d_lut = nullptr;
   int lut_type = -1;
   sse_lut_desc lut{};

@@ -72,6 +72,7 @@ struct sse_server {
   bool stopping = false;
   sse_server_stats st{};
   uint64_t footprint = 0;                   // bytes of one output pair
+  uint64_t phantom_bytes0 = 0;              // the context's phantom memory when the budget was taken
   sse::TransportParams* d_items = nullptr;  // one per slot
   sse::TransportParams* h_items = nullptr;  // pinned staging
   sse::WorkChunk* d_chunks[2] = {nullptr, nullptr};
@@ -152,8 +153,17 @@ bool fail_if_starved(sse_server* s) {
   return true;
 }
 
+// Device memory of phantoms loaded since the budget was taken: it counts
+// against the budget as the outputs do (phantoms cannot be unloaded while
+// the server runs, so it only grows).
+uint64_t phantom_growth(const sse_server* s) {
+  const uint64_t now = s->ctx->phantom_bytes.load();
+  return now > s->phantom_bytes0 ? now - s->phantom_bytes0 : 0;
+}
+
 // Admit queued requests first-in first-out while a slot is free and their
-// output buffers fit the budget.  Called with the lock held.
+// output buffers, with the phantoms loaded since the start, fit the budget.
+// Called with the lock held.
 void admit(sse_server* s) {
   while (!s->pending.empty()) {
     Req& q = s->pending.front();
@@ -180,7 +190,8 @@ void admit(sse_server* s) {
       if (!s->pool.empty()) {
         b = s->pool.back();
         s->pool.pop_back();
-      } else if (s->st.bytes_allocated + s->footprint <= s->st.budget_bytes && !s->alloc_blocked) {
+      } else if (s->st.bytes_allocated + s->footprint + phantom_growth(s) <= s->st.budget_bytes &&
+                 !s->alloc_blocked) {
         const uint64_t nb = s->ctx->n_bins;
         hipError_t ea = hipMalloc(&b.counts, nb * sizeof(uint32_t));
         if (ea == hipSuccess) {
@@ -415,6 +426,7 @@ sse_status sse_server_start(sse_ctx* c, const sse_server_cfg* cfg, sse_server** 
     return hip_fail(e, "server resources");
   }
   // the default budget: what is free once the server's own buffers exist
+  s->phantom_bytes0 = c->phantom_bytes.load();
   if (cfg->hbm_budget_bytes) {
     s->st.budget_bytes = cfg->hbm_budget_bytes;
   } else {
@@ -448,8 +460,8 @@ sse_status sse_server_submit(sse_server* s, const sse_request* req, uint64_t* id
     return fail(SSE_EINVAL, "give both output buffers or neither");
   if (reinterpret_cast<uintptr_t>(req->scatter_counts) % 4 || reinterpret_cast<uintptr_t>(req->scatter_weights) % 8)
     return fail(SSE_EINVAL, "misaligned output buffer");
-  if (!req->scatter_counts && s->footprint > s->st.budget_bytes)
-    return fail(SSE_EBUSY, "one request's outputs exceed the HBM budget");
+  if (!req->scatter_counts && s->footprint + phantom_growth(s) > s->st.budget_bytes)
+    return fail(SSE_EBUSY, "one request's outputs (with the phantoms loaded since the start) exceed the HBM budget");
   Req q;
   q.id = s->next_id++;
   q.r = *req;

@@ -217,6 +217,36 @@ def test_admission_by_hbm_budget():
     ctx.close()
 
 
+def test_phantom_loaded_while_serving_counts_against_the_budget():
+    """A phantom loaded after the server started (the scheduler thread looks
+    phantoms up meanwhile) is served, and its device memory counts against
+    the HBM budget: a request whose outputs the budget held before no longer
+    fits, while one with caller-owned outputs runs."""
+    ctx, pids = tiny_ctx()
+    footprint = ctx.n_bins * 12
+    srv = sse.Server(ctx, max_active=2, hbm_budget_bytes=footprint + footprint // 2, tick_histories=50_000,
+                     chunk_histories=4096)
+    try:
+        # 64 x 64 x 48 voxels of 2 mm: 13 bytes per voxel on the device (map,
+        # alias column, palette index), about 1.4 footprints
+        pd, mu, act = W.uniform_box(n=(64, 64, 48), voxel_mm=(2.0, 2.0, 2.0))
+        pid = ctx.load_phantom(pd, mu, act)
+        assert 64 * 64 * 48 * 13 > footprint // 2
+        with pytest.raises(sse.SseError) as e:
+            srv.submit(pid, 20_000, 7)
+        assert e.value.status == sse.EBUSY
+        out = ctx.new_outputs(stats=False)
+        rid = srv.submit(pid, 20_000, 7, counts=out["scatter_counts"], weights=out["scatter_weights"])
+        got = drain(srv, 1, lambda c: None)
+        assert got[rid]["status"] == sse.REQ_DONE
+        torch.cuda.synchronize()
+        served = (out["scatter_counts"].clone(), out["scatter_weights"].clone())
+    finally:
+        srv.stop()
+    same(served, alone(ctx, pid, 20_000, 7))
+    ctx.close()
+
+
 def test_cancel_and_errors():
     ctx, pids = tiny_ctx()
     srv = sse.Server(ctx, max_active=2, tick_histories=100_000, chunk_histories=8192)
