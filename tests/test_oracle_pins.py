@@ -294,6 +294,25 @@ def test_rayleigh_angles_follow_model_pdf():
     assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-5, chi2
 
 
+@pytest.mark.parametrize("variant", ["f32", "f64"])
+def test_rayleigh_sampler_reduces_to_thomson_without_form_factor(variant):
+    """With the form factor switched off (beta -> 0) the Rayleigh sampler must
+    draw the classical Thomson distribution, pdf (3/8)(1 + cos^2) on [-1, 1]
+    (CDF (3c + c^3 + 4) / 8): a textbook law that the sampler's inversion and
+    rejection steps only reach together, so a wrong rejection test, a wrong
+    inversion or a lost sign fails it.  Pinned by Kolmogorov-Smirnov and by
+    the first three moments (E c = 0, E c^2 = 2/5, E c^3 = 0)."""
+    n = 200_000
+    ct = O.sample_rayleigh(29, 480.0, 1e-6, n, variant=variant)
+    assert np.all((ct >= -1.0) & (ct <= 1.0))
+    cdf = lambda c: (3.0 * c + c ** 3 + 4.0) / 8.0
+    assert stats.kstest(ct, cdf).pvalue > 1e-5
+    se = 1.0 / math.sqrt(n)
+    assert abs(ct.mean()) < 5 * se * math.sqrt(0.4)
+    assert abs((ct ** 2).mean() - 0.4) < 5 * se * 0.35
+    assert abs((ct ** 3).mean()) < 5 * se * 0.55
+
+
 # ---------------------------------------------------------------------------
 # Woodcock transport: Beer-Lambert survival
 # ---------------------------------------------------------------------------
