@@ -391,9 +391,12 @@ sse_status ensure_scratch(sse_ctx* c) {
 }
 
 // Separable smoothing of `in` (binary32, or binary64 weights times `scale`
-// rounded on load) into `out`, optionally multiplied by the sensitivity.
+// rounded on load) into `out`, optionally multiplied by the sensitivity;
+// with ratio_w the last pass writes G / float(scale ratio_w) instead of the
+// smoothed G (1 where either is not positive).
 sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, float* out, const float* sigma,
-                  float truncate, const float* sens, hipStream_t s, const float* norm = nullptr) {
+                  float truncate, const float* sens, hipStream_t s, const float* norm = nullptr,
+                  const double* ratio_w = nullptr) {
   if (!sigma) return fail(SSE_EINVAL, "null sigma");
   if (!in || !out) return fail(SSE_EINVAL, "null buffer");
   if (!(truncate > 0.0f) || !std::isfinite(truncate)) return fail(SSE_EINVAL, "truncate must be positive");
@@ -417,7 +420,8 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
   }
   const sse::PostParams g = post_params(c);
   if (!on[0] && !on[1] && !on[2]) {  // elementwise (in place allowed)
-    HIP_TRY(sse::launch_smooth_axis(g, -1, in, in_is_f64, scale, norm, out, taps[0], norm, sens, c->sens_tof, s),
+    HIP_TRY(sse::launch_smooth_axis(g, -1, in, in_is_f64, scale, norm, out, taps[0], norm, sens, c->sens_tof, ratio_w,
+                                    s),
             "pointwise kernel");
     return SSE_OK;
   }
@@ -450,13 +454,14 @@ sse_status smooth(sse_ctx* c, const void* in, bool in_is_f64, double scale, floa
     const float* n_in = i == 0 ? norm : nullptr;
     const float* n_out = last ? norm : nullptr;
     const float* sv = last ? sens : nullptr;
+    const double* rw = last ? ratio_w : nullptr;
     if (passes[i] == kFused)
       HIP_TRY(sse::launch_smooth_rad_plane(g, plan, src, src_f64, scale, n_in, dst, taps[0], taps[2], n_out, sv,
-                                           c->sens_tof, s),
+                                           c->sens_tof, rw, s),
               "smoothing kernel (radial and plane)");
     else
       HIP_TRY(sse::launch_smooth_axis(g, passes[i], src, src_f64, scale, n_in, dst, taps[passes[i]], n_out, sv,
-                                      c->sens_tof, s),
+                                      c->sens_tof, rw, s),
               "smoothing kernel");
     src = dst;
     src_f64 = false;
@@ -1049,10 +1054,8 @@ sse_status sse_smoothing_normalisation(sse_ctx* c, const double* W, double scale
   if (!std::isfinite(scale)) return fail(SSE_EINVAL, "scale must be finite");
   HIP_TRY(hipSetDevice(c->device), "set device");
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const sse_status st = smooth(c, W, true, scale, norm_out, sigma_bins, truncate, nullptr, s);
-  if (st != SSE_OK) return st;
-  HIP_TRY(sse::launch_norm_ratio(post_params(c), W, scale, norm_out, s), "normalisation kernel");
-  return SSE_OK;
+  // the ratio to the unsmoothed estimate is taken in the last pass
+  return smooth(c, W, true, scale, norm_out, sigma_bins, truncate, nullptr, s, nullptr, W);
 }
 
 sse_status sse_finalize_normalised(sse_ctx* c, const double* W, double scale, const float* norm,

@@ -25,10 +25,12 @@ struct Taps {
 // smoothing, pointwise only).  The input is binary32, or binary64 weights
 // scaled by `scale` and rounded on load (in_is_f64); norm_in (if not NULL)
 // multiplies the input on load; norm_out (if not NULL) divides the output
-// (entries <= 0 count as 1) and sens (if not NULL) multiplies it.
+// (entries <= 0 count as 1) and sens (if not NULL) multiplies it; ratio_w
+// (if not NULL) then replaces the output G by G / S, S = float(scale ratio_w),
+// or by 1 where S or G is not positive.
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
                               const float* norm_in, float* out, const Taps& taps, const float* norm_out,
-                              const float* sens, int sens_tof, hipStream_t stream);
+                              const float* sens, int sens_tof, const double* ratio_w, hipStream_t stream);
 // The radial and plane passes in one launch (both axes smoothed): tiles of
 // tl radial positions by all planes of one (TOF, view) row, staged in LDS by
 // a persistent block per CU.  plan_rad_plane picks the tile for the radii
@@ -46,14 +48,11 @@ FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radiu
 hipError_t launch_smooth_rad_plane(const PostParams& g, const FusedPlan& plan, const void* in, bool in_is_f64,
                                    double scale, const float* norm_in, float* out, const Taps& radial,
                                    const Taps& plane, const float* norm_out, const float* sens, int sens_tof,
-                                   hipStream_t stream);
+                                   const double* ratio_w, hipStream_t stream);
 // total[0] = sum over bins of (scale * W) * sens in binary64, in a fixed
 // order (partial: device scratch of kTotalPartials doubles).
 constexpr int kTotalPartials = 1024;
 hipError_t launch_total_scatter(const PostParams& g, const double* W, double scale, const float* sens, int sens_tof,
                                 double* partial, double* total, hipStream_t stream);
-// norm[b] = G[b] / S[b] with S = float(scale * W[b]), or 1 where S or G is
-// not positive (norm holds G on entry).
-hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale, float* norm, hipStream_t stream);
 
 }  // namespace sse

@@ -93,6 +93,8 @@ struct SmoothArgs {
   int sens_tof;
   Taps taps;
   int tile_len;           // positions per tile of the view and plane passes
+  const double* ratio_w;  // the output becomes out / float(scale ratio_w), 1 where
+                          // either is not positive (or NULL: no ratio)
 };
 
 template <bool kFromF64>
@@ -127,18 +129,34 @@ __device__ __forceinline__ void load_batch(const SmoothArgs& a, const uint64_t* 
   for (int b = 0; b < n; ++b) v[b] = ok[b] ? v[b] : 0.0f;
 }
 
+// The ratio G / S of a smoothed value G and S = float(scale w), or 1 where
+// either is not positive.
+__device__ __forceinline__ float smoothing_ratio(float g, float s) { return (s > 0.0f && g > 0.0f) ? g / s : 1.0f; }
+
 __device__ __forceinline__ float finish_out(const SmoothArgs& a, float acc, uint64_t o, uint64_t inner) {
   if (a.norm_out) {
     const float nrm = a.norm_out[o];
     acc = nrm > 0.0f ? acc / nrm : acc;
   }
   if (a.sens) acc = acc * a.sens[a.sens_tof ? o : o % inner];
+  if (a.ratio_w) acc = smoothing_ratio(acc, static_cast<float>(a.scale * a.ratio_w[o]));
   return acc;
 }
 
+// What a pass does to its outputs (a template argument, so that each kernel
+// holds only the factors it applies): nothing, the normalisation and
+// sensitivity factors, or the ratio to float(scale ratio_w).
+constexpr int kOutPlain = 0, kOutFinish = 1, kOutRatio = 2;
+
 // The output factors of bin o, read before the taps are summed so that the
 // loads are in flight meanwhile; finish() then applies them as finish_out.
+template <int kOut>
 struct OutFactors {
+  __device__ __forceinline__ void load(const SmoothArgs&, uint64_t, uint64_t) {}
+  __device__ __forceinline__ float finish(const SmoothArgs&, float acc) const { return acc; }
+};
+template <>
+struct OutFactors<kOutFinish> {
   float nrm, sv;
   // o: the bin; o_inner: the same bin without its TOF offset
   __device__ __forceinline__ void load(const SmoothArgs& a, uint64_t o, uint64_t o_inner) {
@@ -149,6 +167,14 @@ struct OutFactors {
     if (a.norm_out) acc = nrm > 0.0f ? acc / nrm : acc;
     if (a.sens) acc = acc * sv;
     return acc;
+  }
+};
+template <>
+struct OutFactors<kOutRatio> {
+  double rw;
+  __device__ __forceinline__ void load(const SmoothArgs& a, uint64_t o, uint64_t) { rw = a.ratio_w[o]; }
+  __device__ __forceinline__ float finish(const SmoothArgs& a, float acc) const {
+    return smoothing_ratio(acc, static_cast<float>(a.scale * rw));
   }
 };
 
@@ -223,17 +249,17 @@ __device__ __forceinline__ void stage_taps(const Taps& t, float* dst) {
 // axis tiles): workgroups go round-robin over the eight XCDs, so the tiles
 // of one slab run on one XCD one after another, and a tile's halo rows and
 // the cache lines it shares with the neighbouring column tiles (rows are not
-// line-aligned) are the neighbours' data in that L2.  With kFinish (the last
-// pass) every thread reads the normalisation and sensitivity factors of all
-// its outputs before it stages the tile, so that their latency overlaps the
-// staging loads instead of stalling each block of outputs.  (A persistent,
+// line-aligned) are the neighbours' data in that L2.  With output factors
+// (the last pass) every thread reads the factors of all its outputs before
+// it stages the tile, so that their latency overlaps the staging loads
+// instead of stalling each block of outputs.  (A persistent,
 // pipelined form of this pass, like the fused radial and plane pass, measured
 // no faster: its tiles are short sums over few taps.)
 constexpr int kTC = 64;
 constexpr int kMaxTileLen = 128;
 constexpr size_t kColTileBytes = 48 * 1024;
 constexpr int kColThreads = 512;
-constexpr int kColMinBlocks = 3;  // resident blocks per CU the register budget allows for
+constexpr int kColMinBlocks = 3;  // minimum waves per SIMD the register budget allows for
 constexpr int kColRowsPerSweep = kColThreads / kTC;
 constexpr int kColGroups = kMaxTileLen / (kWin * kColRowsPerSweep);  // output blocks per thread
 
@@ -268,7 +294,7 @@ __device__ __forceinline__ float raw_at(const SmoothArgs& a, uint64_t row, uint3
   return (static_cast<const float*>(a.in) + row)[o];
 }
 
-template <int kAxis, bool kFromF64, bool kFinish>
+template <int kAxis, bool kFromF64, int kOut>
 __global__ void __launch_bounds__(kColThreads, kColMinBlocks) smooth_cols(SmoothArgs a, int n_col_tiles, int n_axis_tiles) {
   extern __shared__ float tile[];
   __shared__ __align__(16) float tw[2 * kMaxSmoothRadius + 4];
@@ -305,8 +331,8 @@ __global__ void __launch_bounds__(kColThreads, kColMinBlocks) smooth_cols(Smooth
   const int rows = tl + 2 * R;
   stage_taps(a.taps, tw);
   // outputs i0 .. i0 + kWin - 1 of block q: i0 = kWin (sub + kColRowsPerSweep q)
-  OutFactors f[kFinish ? kColGroups : 1][kWin];
-  if (kFinish && live) {
+  OutFactors<kOut> f[kOut ? kColGroups : 1][kWin];
+  if (kOut && live) {
 #pragma unroll
     for (int q = 0; q < kColGroups; ++q) {
       const int i0 = kWin * (sub + kColRowsPerSweep * q);
@@ -373,7 +399,7 @@ __global__ void __launch_bounds__(kColThreads, kColMinBlocks) smooth_cols(Smooth
     for (int j = 0; j < kWin; ++j)
       if (i0 + j < tl)
         (a.out + out0 + static_cast<uint64_t>(i0 + j) * ax)[rc] =
-            kFinish ? f[kFinish ? q : 0][j].finish(a, acc[j]) : acc[j];
+            f[kOut ? q : 0][j].finish(a, acc[j]);
   }
 }
 
@@ -382,7 +408,7 @@ __global__ void __launch_bounds__(kColThreads, kColMinBlocks) smooth_cols(Smooth
 constexpr int kSeg = 256;
 static_assert(kSeg == 64 * kOuts, "one block of outputs per lane covers a segment");
 
-template <bool kFromF64>
+template <bool kFromF64, int kOut>
 __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows) {
   __shared__ float seg[4][kSeg + 2 * kMaxSmoothRadius];
   const PostParams& g = a.g;
@@ -423,7 +449,7 @@ __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows
   // read once for all of them; reads for outputs past len stay inside buf
   const int i = static_cast<int>(lane);
   uint64_t o[kOuts];
-  OutFactors f[kOuts];
+  OutFactors<kOut> f[kOuts];
 #pragma unroll
   for (int j = 0; j < kOuts; ++j) {
     o[j] = base + static_cast<uint64_t>(s0 + (i + 64 * j < len ? i + 64 * j : 0));
@@ -561,7 +587,7 @@ struct FusedPrefetch {
   }
 };
 
-template <bool kFromF64, bool kNormIn, bool kFinish>
+template <bool kFromF64, bool kNormIn, int kOut>
 __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f) {
   extern __shared__ float lds[];
   __shared__ __align__(16) float tw_r[2 * kMaxSmoothRadius + 4];
@@ -664,13 +690,13 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
     const int dc = kFusedThreads % tl, dpg = kFusedThreads / tl;
     int c = static_cast<int>(threadIdx.x) % tl, pg = static_cast<int>(threadIdx.x) / tl;
     while (pg < n_pg) {
-      OutFactors fo[kFinish ? kFusedWin : 1];
-      if (kFinish) {
+      OutFactors<kOut> fo[kOut ? kFusedWin : 1];
+      if (kOut) {
 #pragma unroll
         for (int j = 0; j < kFusedWin; ++j) {
           const int p = kFusedWin * pg + j < np ? kFusedWin * pg + j : kFusedWin * pg;
           const uint64_t o = cur.row0 + static_cast<uint64_t>(p) * ps + static_cast<uint64_t>(cur.r0 + c);
-          fo[kFinish ? j : 0].load(a, o, o - static_cast<uint64_t>(cur.t) * ts);
+          fo[kOut ? j : 0].load(a, o, o - static_cast<uint64_t>(cur.t) * ts);
         }
       }
       float sm[kFusedWin] = {};
@@ -679,7 +705,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
       for (int j = 0; j < kFusedWin; ++j)
         if (kFusedWin * pg + j < np)
           (out_row + static_cast<uint64_t>(kFusedWin * pg + j) * ps)[c] =
-              kFinish ? fo[kFinish ? j : 0].finish(a, sm[j]) : sm[j];
+              fo[kOut ? j : 0].finish(a, sm[j]);
       c += dc;
       pg += dpg;
       if (c >= tl) {
@@ -701,17 +727,6 @@ __global__ void __launch_bounds__(256) pointwise_kernel(SmoothArgs a, uint64_t n
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     a.out[i] = finish_out(a, load_in<kFromF64>(a, i), i, inner);
-}
-
-// norm = G / S (S = float(scale W)), 1 where S or G is not positive.
-__global__ void __launch_bounds__(256) norm_ratio_kernel(const double* __restrict__ W, double scale,
-                                                          float* __restrict__ norm, uint64_t n) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float s = static_cast<float>(scale * W[i]);
-    const float gs = norm[i];
-    norm[i] = (s > 0.0f && gs > 0.0f) ? gs / s : 1.0f;
-  }
 }
 
 uint64_t inner_bins(const PostParams& g) { return static_cast<uint64_t>(g.n_rad) * g.n_view * g.n_plane; }
@@ -738,12 +753,6 @@ hipError_t launch_total_scatter(const PostParams& g, const double* W, double sca
   hipLaunchKernelGGL(total_partial_kernel, dim3(kTotalBlocks), dim3(256), 0, stream, W, scale, sens, n, inner,
                      sens_tof, partial);
   hipLaunchKernelGGL(total_final_kernel, dim3(1), dim3(kTotalBlocks), 0, stream, partial, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_norm_ratio(const PostParams& g, const double* W, double scale, float* norm, hipStream_t stream) {
-  const uint64_t n = inner_bins(g) * static_cast<uint64_t>(g.n_tof);
-  hipLaunchKernelGGL(norm_ratio_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, W, scale, norm, n);
   return hipGetLastError();
 }
 
@@ -806,38 +815,79 @@ FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radiu
   return pl;
 }
 
+namespace {
+// The output mode of a pass (kOut*), or -1 for a ratio combined with the
+// other factors, which no caller needs.
+int out_mode(const float* norm_out, const float* sens, const double* ratio_w) {
+  if (ratio_w) return (norm_out || sens) ? -1 : kOutRatio;
+  return (norm_out || sens) ? kOutFinish : kOutPlain;
+}
+
+template <bool kF64, bool kNin>
+void launch_fused(int mode, dim3 grid, size_t lds, hipStream_t stream, const FusedArgs& f) {
+  if (mode == kOutRatio)
+    hipLaunchKernelGGL((smooth_rad_plane<kF64, kNin, kOutRatio>), grid, dim3(kFusedThreads), lds, stream, f);
+  else if (mode == kOutFinish)
+    hipLaunchKernelGGL((smooth_rad_plane<kF64, kNin, kOutFinish>), grid, dim3(kFusedThreads), lds, stream, f);
+  else
+    hipLaunchKernelGGL((smooth_rad_plane<kF64, kNin, kOutPlain>), grid, dim3(kFusedThreads), lds, stream, f);
+}
+
+template <int kAxis, bool kF64>
+void launch_cols(int mode, dim3 grid, size_t lds, hipStream_t stream, const SmoothArgs& a, int n_col_tiles,
+                 int n_axis_tiles) {
+  if (mode == kOutRatio)
+    hipLaunchKernelGGL((smooth_cols<kAxis, kF64, kOutRatio>), grid, dim3(kColThreads), lds, stream, a, n_col_tiles,
+                       n_axis_tiles);
+  else if (mode == kOutFinish)
+    hipLaunchKernelGGL((smooth_cols<kAxis, kF64, kOutFinish>), grid, dim3(kColThreads), lds, stream, a, n_col_tiles,
+                       n_axis_tiles);
+  else
+    hipLaunchKernelGGL((smooth_cols<kAxis, kF64, kOutPlain>), grid, dim3(kColThreads), lds, stream, a, n_col_tiles,
+                       n_axis_tiles);
+}
+
+template <bool kF64>
+void launch_rows(int mode, dim3 grid, hipStream_t stream, const SmoothArgs& a, uint64_t rows) {
+  if (mode == kOutRatio) hipLaunchKernelGGL((smooth_rows<kF64, kOutRatio>), grid, dim3(256), 0, stream, a, rows);
+  else if (mode == kOutFinish) hipLaunchKernelGGL((smooth_rows<kF64, kOutFinish>), grid, dim3(256), 0, stream, a, rows);
+  else hipLaunchKernelGGL((smooth_rows<kF64, kOutPlain>), grid, dim3(256), 0, stream, a, rows);
+}
+}  // namespace
+
 hipError_t launch_smooth_rad_plane(const PostParams& g, const FusedPlan& pl, const void* in, bool in_is_f64,
                                    double scale, const float* norm_in, float* out, const Taps& radial,
                                    const Taps& plane, const float* norm_out, const float* sens, int sens_tof,
-                                   hipStream_t stream) {
-  if (pl.tl <= 0) return hipErrorInvalidValue;
+                                   const double* ratio_w, hipStream_t stream) {
+  const int mode = out_mode(norm_out, sens, ratio_w);
+  if (pl.tl <= 0 || mode < 0) return hipErrorInvalidValue;
   const uint64_t rows = static_cast<uint64_t>(g.n_view) * g.n_tof;
   const uint64_t units = (rows + 7) / 8 * 8 * static_cast<uint64_t>(pl.n_tiles);
   if (units == 0) return hipSuccess;
   if (units > 0xffffffffull) return hipErrorInvalidValue;
-  FusedArgs f{SmoothArgs{g, in, scale, norm_in, out, norm_out, sens, sens_tof, radial, 0}, plane, pl.tl,
+  FusedArgs f{SmoothArgs{g, in, scale, norm_in, out, norm_out, sens, sens_tof, radial, 0, ratio_w}, plane, pl.tl,
               pl.n_tiles, pl.sx, pl.sy, static_cast<uint32_t>(units)};
   // one block per CU (a multiple of 8: a block's units stay on its XCD)
   uint64_t blocks = static_cast<uint64_t>(device_cus() + 7) / 8 * 8;
   if (blocks > units) blocks = (units + 7) / 8 * 8;
-  const bool fin = norm_out != nullptr || sens != nullptr;
   const bool nin = norm_in != nullptr;
   const dim3 grid(static_cast<unsigned>(blocks));
-#define SSE_FUSED(F64, NIN, FIN) \
-  hipLaunchKernelGGL((smooth_rad_plane<F64, NIN, FIN>), grid, dim3(kFusedThreads), pl.lds_bytes, stream, f)
-#define SSE_FUSED_FIN(F64, NIN) \
-  do { if (fin) SSE_FUSED(F64, NIN, true); else SSE_FUSED(F64, NIN, false); } while (0)
-  if (in_is_f64) { if (nin) SSE_FUSED_FIN(true, true); else SSE_FUSED_FIN(true, false); }
-  else { if (nin) SSE_FUSED_FIN(false, true); else SSE_FUSED_FIN(false, false); }
-#undef SSE_FUSED_FIN
-#undef SSE_FUSED
+  if (in_is_f64) {
+    if (nin) launch_fused<true, true>(mode, grid, pl.lds_bytes, stream, f);
+    else launch_fused<true, false>(mode, grid, pl.lds_bytes, stream, f);
+  } else {
+    if (nin) launch_fused<false, true>(mode, grid, pl.lds_bytes, stream, f);
+    else launch_fused<false, false>(mode, grid, pl.lds_bytes, stream, f);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, bool in_is_f64, double scale,
                               const float* norm_in, float* out, const Taps& taps, const float* norm_out,
-                              const float* sens, int sens_tof, hipStream_t stream) {
-  SmoothArgs a{g, in, scale, norm_in, out, norm_out, sens, sens_tof, taps, 0};
+                              const float* sens, int sens_tof, const double* ratio_w, hipStream_t stream) {
+  SmoothArgs a{g, in, scale, norm_in, out, norm_out, sens, sens_tof, taps, 0, ratio_w};
+  const int mode = out_mode(norm_out, sens, ratio_w);
+  if (mode < 0) return hipErrorInvalidValue;
   const uint64_t n_bins = inner_bins(g) * static_cast<uint64_t>(g.n_tof);
   if (axis < 0) {
     if (in_is_f64) hipLaunchKernelGGL(pointwise_kernel<true>, dim3(blocks_for(n_bins)), dim3(256), 0, stream, a, n_bins);
@@ -848,8 +898,8 @@ hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, boo
     const uint64_t rows = static_cast<uint64_t>(g.n_view) * g.n_plane * g.n_tof;
     const uint64_t jobs = rows * static_cast<uint64_t>((g.n_rad + kSeg - 1) / kSeg);
     const dim3 grid(static_cast<unsigned>((jobs + 3) / 4));
-    if (in_is_f64) hipLaunchKernelGGL(smooth_rows<true>, grid, dim3(256), 0, stream, a, rows);
-    else hipLaunchKernelGGL(smooth_rows<false>, grid, dim3(256), 0, stream, a, rows);
+    if (in_is_f64) launch_rows<true>(mode, grid, stream, a, rows);
+    else launch_rows<false>(mode, grid, stream, a, rows);
     return hipGetLastError();
   }
   const int n = axis == 1 ? g.n_view : g.n_plane;
@@ -862,17 +912,13 @@ hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, boo
   const int n_axis_tiles = (n + tile_len - 1) / tile_len;
   const uint64_t groups = static_cast<uint64_t>(n_other) * g.n_tof;
   const dim3 grid(static_cast<unsigned>((groups + 7) / 8 * 8 * static_cast<uint64_t>(n_col_tiles * n_axis_tiles)));
-  const bool fin = norm_out != nullptr || sens != nullptr;
-#define SSE_COLS(AX, F64, FIN) \
-  hipLaunchKernelGGL((smooth_cols<AX, F64, FIN>), grid, dim3(kColThreads), lds, stream, a, n_col_tiles, n_axis_tiles)
   if (axis == 1) {
-    if (in_is_f64) { if (fin) SSE_COLS(1, true, true); else SSE_COLS(1, true, false); }
-    else { if (fin) SSE_COLS(1, false, true); else SSE_COLS(1, false, false); }
+    if (in_is_f64) launch_cols<1, true>(mode, grid, lds, stream, a, n_col_tiles, n_axis_tiles);
+    else launch_cols<1, false>(mode, grid, lds, stream, a, n_col_tiles, n_axis_tiles);
   } else {
-    if (in_is_f64) { if (fin) SSE_COLS(2, true, true); else SSE_COLS(2, true, false); }
-    else { if (fin) SSE_COLS(2, false, true); else SSE_COLS(2, false, false); }
+    if (in_is_f64) launch_cols<2, true>(mode, grid, lds, stream, a, n_col_tiles, n_axis_tiles);
+    else launch_cols<2, false>(mode, grid, lds, stream, a, n_col_tiles, n_axis_tiles);
   }
-#undef SSE_COLS
   return hipGetLastError();
 }
 
