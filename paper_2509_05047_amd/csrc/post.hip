@@ -531,6 +531,15 @@ __device__ __forceinline__ uint32_t fused_next(const FusedArgs& f, uint32_t u, F
   return f.n_units;
 }
 
+// The value of type T at element offset o past base, the byte offset taken
+// in 32 bits (the planner keeps every offset within a (TOF, view) row's
+// planes below 2^32 bytes), so that the address is a uniform base plus a
+// 32-bit lane offset.
+template <class T>
+__device__ __forceinline__ T load_at(const T* base, uint32_t o) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o * static_cast<uint32_t>(sizeof(T)));
+}
+
 // Prefetch registers of one staged tile: element e = threadIdx.x + 1024 i
 // is plane e / wx, staged column e % wx (stepped without division).  Every
 // element slot is loaded (slots past the tile from a clamped, valid index,
@@ -542,22 +551,24 @@ struct FusedPrefetch {
   Raw w[kFusedPrefetch];
   float nrm[kNormIn ? kFusedPrefetch : 1];
 
-  __device__ __forceinline__ void issue(const SmoothArgs& a, const FusedTile& ft, int np, uint64_t ps) {
+  // ps: the plane stride in elements (below 2^24, by the planner)
+  __device__ __forceinline__ void issue(const SmoothArgs& a, const FusedTile& ft, int np, uint32_t ps) {
     const int dp = kFusedThreads / ft.wx, dc = kFusedThreads % ft.wx;
     int p = static_cast<int>(threadIdx.x) / ft.wx, c = static_cast<int>(threadIdx.x) % ft.wx;
     const Raw* in = static_cast<const Raw*>(a.in) + ft.row0;
     const float* nin = a.norm_in + ft.row0;
     const int n_rad = a.g.n_rad;
+    const int c0 = ft.r0 - a.taps.radius;
 #pragma unroll
     for (int i = 0; i < kFusedPrefetch; ++i) {
       // one reflection at most: the planner keeps the radius <= n_rad
-      int col = ft.r0 - a.taps.radius + c;
+      int col = c0 + c;
       col = col < 0 ? -col - 1 : col;
       col = col >= n_rad ? 2 * n_rad - 1 - col : col;
       const int pc = p < np ? p : np - 1;
-      const uint64_t o = static_cast<uint64_t>(pc) * ps + static_cast<uint64_t>(col);
-      w[i] = in[o];
-      if (kNormIn) nrm[kNormIn ? i : 0] = nin[o];
+      const uint32_t o = __umul24(static_cast<uint32_t>(pc), ps) + static_cast<uint32_t>(col);
+      w[i] = load_at(in, o);
+      if (kNormIn) nrm[kNormIn ? i : 0] = load_at(nin, o);
       p += dp;
       c += dc;
       if (c >= ft.wx) {
@@ -598,8 +609,8 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
   const int np = g.n_plane;
   stage_taps(a.taps, tw_r);  // read after the first barrier below
   stage_taps(f.plane, tw_p);
-  const uint64_t ps = static_cast<uint64_t>(g.n_rad) * g.n_view;
-  const uint64_t ts = ps * g.n_plane;
+  const uint32_t ps = static_cast<uint32_t>(g.n_rad) * static_cast<uint32_t>(g.n_view);
+  const uint64_t ts = static_cast<uint64_t>(ps) * g.n_plane;
   const int lane = static_cast<int>(threadIdx.x & 63u);
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int y_rows = np + 2 * Rp + kFusedWin - 1;  // smoothed planes and plane halo
@@ -704,8 +715,9 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
 #pragma unroll
       for (int j = 0; j < kFusedWin; ++j)
         if (kFusedWin * pg + j < np)
-          (out_row + static_cast<uint64_t>(kFusedWin * pg + j) * ps)[c] =
-              fo[kOut ? j : 0].finish(a, sm[j]);
+          *reinterpret_cast<float*>(reinterpret_cast<char*>(out_row) +
+                                    (__umul24(static_cast<uint32_t>(kFusedWin * pg + j), ps) +
+                                     static_cast<uint32_t>(c)) * 4u) = fo[kOut ? j : 0].finish(a, sm[j]);
       c += dc;
       pg += dpg;
       if (c >= tl) {
@@ -789,6 +801,11 @@ size_t fused_lds_limit() {
 FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radius) {
   FusedPlan pl{};
   if (g.n_plane <= 0 || g.n_rad <= 0 || radial_radius > g.n_rad) return pl;
+  // offsets within a (TOF, view) row's planes: 24-bit plane strides and
+  // 32-bit byte offsets of binary64 elements
+  const uint64_t plane_stride = static_cast<uint64_t>(g.n_rad) * static_cast<uint64_t>(g.n_view);
+  if (plane_stride >= (1ull << 24) || plane_stride * static_cast<uint64_t>(g.n_plane) * sizeof(double) >= (1ull << 32))
+    return pl;
   const size_t lds_max = fused_lds_limit();
   for (int k = (g.n_rad + kFusedMaxTile - 1) / kFusedMaxTile;; ++k) {  // k tiles of about equal length
     const int tl = (g.n_rad + k - 1) / k;
