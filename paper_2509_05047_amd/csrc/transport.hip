@@ -88,6 +88,16 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
     }                                                                                 \
   } while (0)
 
+// Wave votes over the active lanes.  A vote on a conjunction is taken as
+// the AND of the two comparisons' lane masks: a ballot of a combined
+// predicate is compiled as a value that is compared back into a mask (two
+// more vector instructions, one of them a 4-cycle select).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ bool wave_any(bool p, bool q) {
+  return (__builtin_amdgcn_ballot_w64(p) & __builtin_amdgcn_ballot_w64(q)) != 0;
+}
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
+
 // A history's random stream: the 32-bit words of Philox blocks 0, 1, 2, ...
 // with counter (block, h_lo, h_hi, 0), consumed in order.
 //
@@ -282,7 +292,7 @@ struct RegRng {
 // short, all active lanes with room generate one block together.
 #define RNG_NEED(k)                                  \
   do {                                               \
-    if (__any(r.left < (k))) {                       \
+    if (wave_any(r.left < (k))) {                       \
       if (r.room()) r.refill(k0, k1);                \
     }                                                \
   } while (0)
@@ -600,7 +610,7 @@ template <class Q>
 __device__ __forceinline__ float std_normal(Q& q, const TransportParams& p) {
   const uint32_t k0 = static_cast<uint32_t>(p.seed), k1 = static_cast<uint32_t>(p.seed >> 32);
   for (int i = 0; i < kMaxTries; ++i) {
-    if (__any(q.left < 2u)) {
+    if (wave_any(q.left < 2u)) {
       if (q.room()) q.refill(k0, k1);
     }
     const float a = 2.0f * q.uniform() - 1.0f;
@@ -981,12 +991,12 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
         if (phase == kEmit) phase = kDone;  // no history left for this lane
       }
     }
-    if (__all(phase == kDone)) break;
+    if (wave_all(phase == kDone)) break;
     // Converged top-up: two rounds in which every live lane with room
     // generates a block (a new history gets eight words, the whole buffer).
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (__any(phase != kDone && r.room())) {
+      if (wave_any(phase != kDone, r.room())) {
         if (phase != kDone && r.room()) r.refill(k0, k1);
       }
     }
@@ -1004,11 +1014,11 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     auto keep_stepping = [&]() -> bool {
       const uint64_t trk_m = __ballot(phase == kTrack);
       if (!trk_m) return false;
-      return __popcll(trk_m) > kStepTail || !__any(phase != kTrack && phase != kDone);
+      return __popcll(trk_m) > kStepTail || !wave_any(phase != kTrack, phase != kDone);
     };
     bool stepping = keep_stepping();
     while (stepping) {
-      if (__any(phase == kTrack && r.left < 2u)) {
+      if (wave_any(phase == kTrack, r.left < 2u)) {
         if (phase != kDone && r.room()) r.refill(k0, k1);
       }
       // One tentative step per tracking lane, written with selects rather
@@ -1089,11 +1099,11 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
 
     // ---------------- Compton: Klein-Nishina by Kahn's method --------------
     // x = E / E'; at most kMaxTries tries in all, kRounds per iteration.
-    if (__any(phase == kCompton)) {
+    if (wave_any(phase == kCompton)) {
       bool acc = false;
       float x = 0.0f;
       for (int k = 0; k < kRounds; ++k) {
-        if (!__any(phase == kCompton && !acc)) break;
+        if (!wave_any(phase == kCompton, !acc)) break;
         if (phase == kCompton && !acc) {
           if (tries >= kMaxTries) {
             fate = kAbsorbed;
@@ -1151,7 +1161,9 @@ __device__ __forceinline__ void run_histories(const TransportParams& p, uint64_t
     // block reserved.  res_next and res_end change only here and at the end
     // of the iteration, so they stay wave-uniform.
     {
-      const uint64_t need = static_cast<uint64_t>(__popcll(__ballot(phase == kFinish && side == 1 && a_win)));
+      const uint64_t need = static_cast<uint64_t>(__popcll(__builtin_amdgcn_ballot_w64(phase == kFinish) &
+                                                            __builtin_amdgcn_ballot_w64(side == 1) &
+                                                            __builtin_amdgcn_ballot_w64(a_win)));
       if (res_end - res_next < need) {
         pad_pairs(p, res_next, res_end);
         uint32_t b0 = 0u;
