@@ -79,6 +79,10 @@ void build_transport_params(const sse_ctx* c, const Phantom* ph, uint64_t seed, 
   p.fz_max = static_cast<float>(d.nz - 1);
   // (iz ny + iy) < ny nz and each factor below 2^24: exact 24-bit products
   p.vox24 = static_cast<uint64_t>(d.ny) * static_cast<uint64_t>(d.nz) <= (1ull << 24) && d.nx < (1 << 24);
+  // every index below 2^24: the binary32 sums iz nx ny + iy nx + ix are exact
+  p.voxf = static_cast<uint64_t>(d.nx) * static_cast<uint64_t>(d.ny) * static_cast<uint64_t>(d.nz) <= (1ull << 24);
+  p.fnx = static_cast<float>(d.nx);
+  p.fnxy = static_cast<float>(static_cast<uint64_t>(d.nx) * static_cast<uint64_t>(d.ny));
   p.mu_maj = c->ph.mu_majorant > 0.0f ? c->ph.mu_majorant : ph->mu_max;
   p.n_crystals = c->sc.n_crystals;
   p.n_rings = c->sc.n_rings;

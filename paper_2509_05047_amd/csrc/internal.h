@@ -68,6 +68,8 @@ struct TransportParams {
   float ivx, ivy, ivz, vx, vy, vz;
   float fx_max, fy_max, fz_max;   // nx - 1, ny - 1, nz - 1
   int vox24;                      // ny nz <= 2^24: voxel indices by 24-bit multiplies
+  int voxf;                       // nx ny nz <= 2^24: voxel indices by exact binary32 multiply-adds
+  float fnx, fnxy;                // nx, nx ny
   float mu_maj;             // Woodcock majorant at 511 keV
   // scanner and sinogram
   int n_crystals, n_rings, cmod, rblk, max_ring_diff;

@@ -389,12 +389,16 @@ __device__ __forceinline__ int clamp_floor(float f, int n) {
 
 // Voxel of a point, clamped to the grid (a valid index for any finite
 // point): the clamp is one median-of-three before the floor, which equals
-// flooring first and clamping to [0, n - 1] after; the index takes 24-bit
-// multiplies when the grid's sizes allow them (vox24).
+// flooring first and clamping to [0, n - 1] after.  The index is formed from
+// the floored coordinates by two binary32 multiply-adds when the grid has at
+// most 2^24 voxels (every partial sum is then an integer below 2^24, exact),
+// else by 24-bit multiplies when the grid's sizes allow them (vox24).
 __device__ __forceinline__ uint32_t voxel_at(const TransportParams& p, float x, float y, float z) {
-  const uint32_t ix = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((x - p.lox) * p.ivx, 0.0f, p.fx_max)));
-  const uint32_t iy = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((y - p.loy) * p.ivy, 0.0f, p.fy_max)));
-  const uint32_t iz = static_cast<uint32_t>(floorf(__builtin_amdgcn_fmed3f((z - p.loz) * p.ivz, 0.0f, p.fz_max)));
+  const float fx = floorf(__builtin_amdgcn_fmed3f((x - p.lox) * p.ivx, 0.0f, p.fx_max));
+  const float fy = floorf(__builtin_amdgcn_fmed3f((y - p.loy) * p.ivy, 0.0f, p.fy_max));
+  const float fz = floorf(__builtin_amdgcn_fmed3f((z - p.loz) * p.ivz, 0.0f, p.fz_max));
+  if (p.voxf) return static_cast<uint32_t>(__builtin_fmaf(fz, p.fnxy, __builtin_fmaf(fy, p.fnx, fx)));
+  const uint32_t ix = static_cast<uint32_t>(fx), iy = static_cast<uint32_t>(fy), iz = static_cast<uint32_t>(fz);
   const uint32_t nx = static_cast<uint32_t>(p.nx), ny = static_cast<uint32_t>(p.ny);
   if (p.vox24) return __umul24(__umul24(iz, ny) + iy, nx) + ix;
   return (iz * ny + iy) * nx + ix;
