@@ -362,6 +362,19 @@ sse_status sse_simulate_noalloc(sse_ctx* ctx, sse_phantom_id id, uint64_t n_hist
  * the context. */
 sse_status sse_set_pair_pruning(sse_ctx* ctx, int enable);
 
+/* Size limit of the context's pair buffer, in records of 80 bytes (default
+ * 2^27, 10.7 GB).  The buffer carries the in-window pairs from the transport
+ * kernel to the coincidence kernel; sse_simulate allocates it on first use,
+ * at most max_records and no more than a run needs.  A run whose pairs do not
+ * fit goes through several launches, each of which stops taking histories
+ * when the buffer is nearly full, so a smaller buffer costs launches, not
+ * results: counts are the same bit for bit and weights up to the order of
+ * their binary64 sums.  The current buffer is freed (after the device is
+ * idle) and the next sse_simulate allocates one under the new limit.
+ * Errors: SSE_EINVAL (max_records outside 2^22 .. 2^31), SSE_EBUSY while a
+ * server runs on the context. */
+sse_status sse_set_pair_buffer(sse_ctx* ctx, uint64_t max_records);
+
 /* Per-kernel timing of the production launches, for measurement.  With
  * enable = 1, every later sse_simulate on its production path (no
  * statistics, no records) records HIP events on its stream before and after

@@ -120,6 +120,7 @@ SIGNATURES = {
     "sse_load_sensitivity": ([_P, _P, C.c_int, C.c_int, _P], C.c_int),
     "sse_set_gaps": ([_P, _P, _P, _P, C.c_int, _P], C.c_int),
     "sse_set_pair_pruning": ([_P, C.c_int], C.c_int),
+    "sse_set_pair_buffer": ([_P, C.c_uint64], C.c_int),
     "sse_build_edge_lut": ([_P, _P], C.c_int),
     "sse_check_division": ([_P, C.c_uint64, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], C.c_int),
     "sse_simulate": ([_P, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
@@ -308,6 +309,10 @@ class Context:
         et = None if edge_t is None else np.ascontiguousarray(edge_t, np.float32)
         ea = None if edge_a is None else np.ascontiguousarray(edge_a, np.float32)
         _check(lib().sse_set_gaps(self._h, C.byref(d), _ptr(et), _ptr(ea), MEM_HOST, None))
+
+    def set_pair_buffer(self, max_records: int):
+        """Most records of the pair buffer (see sse_set_pair_buffer)."""
+        _check(lib().sse_set_pair_buffer(self._h, int(max_records)))
 
     def set_pair_pruning(self, enable: bool):
         """Do not track photon B when photon A ended outside the energy

@@ -353,14 +353,16 @@ sse::PostParams post_params(const sse_ctx* c) {
   return sse::PostParams{c->sn.n_rad, c->sn.n_view, c->sn.n_plane, c->sn.n_tof};
 }
 
-// Pair buffer for runs of n histories: the records one launch of n needs
-// (in either launch form), at most 2^27 (10.7 GB: longer runs are split into
-// launches, and fewer, longer launches lose less to each launch's end),
-// rounded up to 2^16 and grown when needed (halved down to 2^22 while
-// allocation fails); and the work-list scratch of the production path.
+// Pair buffer for runs of n histories: the records one launch of n needs in
+// the worst case (in either launch form), at most pair_cap_max (2^27 = 10.7
+// GB unless set: a run beyond it goes through fill launches, which end when
+// the buffer is nearly full), rounded up to 2^16 and grown when needed
+// (halved down to 2^22 while allocation fails); and the work-list scratch of
+// the production path.
+constexpr uint64_t kMinPairCap = 1ull << 22;
 sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
-  constexpr uint64_t kDefaultCap = 1ull << 27;
-  constexpr uint64_t kMinCap = 1ull << 22;
+  const uint64_t kDefaultCap = c->pair_cap_max;
+  constexpr uint64_t kMinCap = kMinPairCap;
   if (!c->d_item) HIP_TRY(hipMalloc(&c->d_item, sizeof(sse::TransportParams)), "allocate work-list scratch");
   if (!c->d_chunk) HIP_TRY(hipMalloc(&c->d_chunk, sizeof(sse::WorkChunk)), "allocate work-list scratch");
   if (!c->d_cursor) HIP_TRY(hipMalloc(&c->d_cursor, sizeof(uint32_t)), "allocate work-list scratch");
@@ -753,6 +755,21 @@ sse_status sse_load_sensitivity(sse_ctx* c, const float* sens, int has_tof_axis,
   }
   c->d_sens = d;
   c->sens_tof = has_tof_axis ? 1 : 0;
+  return SSE_OK;
+}
+
+sse_status sse_set_pair_buffer(sse_ctx* c, uint64_t max_records) {
+  if (!c) return fail(SSE_EINVAL, "null context");
+  if (max_records < kMinPairCap || max_records > sse::kMaxPairCap)
+    return fail(SSE_EINVAL, "max_records must be 2^22 .. 2^31");
+  if (sse_status st = refuse_while_serving(c, "cannot change the pair buffer"); st != SSE_OK) return st;
+  HIP_TRY(hipSetDevice(c->device), "set device");
+  if (c->d_pairs) {  // the freeing waits for the device; the next simulate allocates anew
+    release(c->d_pairs);
+    c->d_pairs = nullptr;
+    c->pair_cap = 0;
+  }
+  c->pair_cap_max = max_records;
   return SSE_OK;
 }
 

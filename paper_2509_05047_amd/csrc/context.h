@@ -86,6 +86,7 @@ struct sse_ctx {
   uint32_t* d_pairs = nullptr;
   uint32_t* d_pair_count = nullptr;
   uint64_t pair_cap = 0;
+  uint64_t pair_cap_max = 1ull << 27;  // most records the buffer may hold (sse_set_pair_buffer)
   // the production simulate's work-list scratch: one parameter set, one
   // chunk and the claim cursor (ordered like the pair buffer)
   sse::TransportParams* d_item = nullptr;

@@ -234,6 +234,10 @@ struct BatchParams {
   uint32_t* pair_count;
   uint64_t pair_cap;
   int gap_on;                    // the items' gap model is on (they share one context)
+  // No slice is claimed once the pair counter exceeds stop_at (a fill
+  // launch: the launch ends early and the next one goes on from the claim
+  // cursor); ~0 never stops.
+  uint64_t stop_at = ~0ull;
 };
 
 // HIP events recorded around the kernels of work-list launches (for

@@ -1385,7 +1385,15 @@ transport_batch_kernel(BatchParams b) {
   const ConstParams* items = (const ConstParams*)(b.items);
   auto claim = [&](WorkChunk& ch) -> bool {
     uint32_t pos = 0;
-    if (lane == 0) pos = atomicAdd(b.counter, kBatchSlice);
+    if (lane == 0) {
+      // a fill launch stops claiming once the buffer holds what every
+      // resident wavefront may still add to it (the pair counter is read at
+      // device scope, past this CU's cache)
+      const bool full = b.stop_at != ~0ull &&
+                        static_cast<uint64_t>(__hip_atomic_load(b.pair_count, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)) > b.stop_at;
+      pos = full ? 0xffffffffu : atomicAdd(b.counter, kBatchSlice);
+    }
     pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));
     if (pos >= b.n_positions) return false;
     for (;;) {
@@ -1622,14 +1630,56 @@ hipError_t launch_transport(const TransportParams& p, hipStream_t stream) {
   return hipSuccess;
 }
 
+namespace {
+hipError_t launch_batch_pass(const BatchParams& b, hipStream_t stream, KernelTiming* kt, bool reset_cursor);
+// Histories of one fill run: its claim positions fit 32 bits.
+constexpr uint64_t kFillRun = 1ull << 31;
+}  // namespace
+
 hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
                                  uint32_t* d_cursor, hipStream_t stream, KernelTiming* kt) {
   if (!p.pairs || !p.pair_count || p.pair_cap == 0 || p.pair_cap > kMaxPairCap || !d_item || !d_chunk || !d_cursor)
     return hipErrorInvalidValue;
-  const uint64_t most = transport_batch_max_histories(p.pair_cap);
-  if (most == 0) return hipErrorInvalidValue;
   TransportParams q = p;
   q.item = 0;
+  // Fill launches: the work list spans the whole run (up to kFillRun
+  // histories) and each launch takes slices from the common cursor until
+  // the pair buffer holds stop_at records -- in practice one launch, as a
+  // pair is queued for a few per cent of histories -- and as many launches
+  // are queued as the worst case (a pair for every history) needs; those
+  // that find the cursor at the end exit at once.  After its last claim a
+  // wavefront adds at most the pairs of its slice and of its lanes still in
+  // flight (kBatchSlice + 64), with the padding of the blocks it leaves:
+  // three blocks.
+  const uint64_t rw = resident_blocks(transport_batch_kernel) * (kBlock / 64);
+  const uint64_t headroom = rw * 3u * kPairBlock;
+  if (rw > 0 && p.pair_cap > headroom + 2u * rw * kPairBlock) {
+    const uint64_t stop_at = p.pair_cap - headroom;
+    // histories a launch takes at least before it stops: past stop_at the
+    // counter holds a partly used block per wavefront, and every block
+    // is padded by at most 63 records
+    const uint64_t per_launch = (stop_at - rw * kPairBlock) / kPairBlock * (kPairBlock - 64);
+    for (uint64_t done = 0; done < p.n;) {
+      const uint64_t n = p.n - done < kFillRun ? p.n - done : kFillRun;
+      const WorkChunk ch{p.h0 + done, static_cast<uint32_t>(n), 0u};
+      hipLaunchKernelGGL(store_item_kernel, dim3(1), dim3(1), 0, stream, q, ch, d_item, d_chunk);
+      hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, d_cursor);
+      const uint64_t positions = (n + kBatchSlice - 1) / kBatchSlice * kBatchSlice;
+      BatchParams b{d_item, d_chunk, 1u, static_cast<uint32_t>(positions), d_cursor, n,
+                    p.pairs, p.pair_count, p.pair_cap, p.gap_on};
+      b.stop_at = stop_at;
+      const uint64_t launches = (n + per_launch - 1) / per_launch;
+      for (uint64_t k = 0; k < launches; ++k) {
+        const hipError_t e = launch_batch_pass(b, stream, kt, false);
+        if (e != hipSuccess) return e;
+      }
+      done += n;
+    }
+    return hipSuccess;
+  }
+  // a small buffer: launches sized for the worst case
+  const uint64_t most = transport_batch_max_histories(p.pair_cap);
+  if (most == 0) return hipErrorInvalidValue;
   for (uint64_t done = 0; done < p.n;) {
     const uint64_t n = p.n - done < most ? p.n - done : most;
     const WorkChunk ch{p.h0 + done, static_cast<uint32_t>(n), 0u};
@@ -1729,9 +1779,17 @@ hipError_t launch_transport_noalloc(int device, const TransportParams& p0, hipSt
 
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, KernelTiming* kt) {
   if (b.n_chunks == 0) return hipSuccess;
-  if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap ||
+  if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap || b.stop_at != ~0ull ||
       b.n_histories > transport_batch_max_histories(b.pair_cap))
     return hipErrorInvalidValue;
+  return launch_batch_pass(b, stream, kt, true);
+}
+
+namespace {
+// One pass of a work list: the claim cursor reset (reset_cursor) or left
+// where the last pass stopped, the pair counter reset, the transport kernel,
+// then the coincidence kernel over the records it queued.
+hipError_t launch_batch_pass(const BatchParams& b, hipStream_t stream, KernelTiming* kt, bool reset_cursor) {
   if (b.n_positions < b.n_histories ||
       b.n_positions > b.n_histories + static_cast<uint64_t>(b.n_chunks) * kBatchSlice)
     return hipErrorInvalidValue;
@@ -1747,12 +1805,13 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, Kern
     if (kt->n < kt->cap) ev = kt->ev + 4u * kt->n++;
     else ++kt->dropped;
   }
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
+  if (reset_cursor) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.pair_count);
   if (ev) (void)hipEventRecord(ev[0], stream);
   hipLaunchKernelGGL(transport_batch_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  const dim3 cgrid(stride_grid(pair_records_needed(b.n_histories, 4ull * grid), cus));
+  const uint64_t most_records = pair_records_needed(b.n_histories, 4ull * grid);
+  const dim3 cgrid(stride_grid(most_records < b.pair_cap ? most_records : b.pair_cap, cus));
   if (ev) (void)hipEventRecord(ev[2], stream);
   if (b.gap_on)
     hipLaunchKernelGGL(coincidence_batch_kernel<true>, cgrid, dim3(kBlock), 0, stream, b);
@@ -1761,5 +1820,6 @@ hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, Kern
   if (ev) (void)hipEventRecord(ev[3], stream);
   return hipGetLastError();
 }
+}  // namespace
 
 }  // namespace sse

@@ -137,3 +137,4 @@ def test_edge_lut_rejects_bad_geometry(bad):
 
 def test_pair_pruning_rejects_null_context():
     assert sse.lib().sse_set_pair_pruning(None, 1) == sse.EINVAL
+    assert sse.lib().sse_set_pair_buffer(None, 1 << 27) == sse.EINVAL
