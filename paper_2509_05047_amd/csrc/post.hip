@@ -238,8 +238,9 @@ __device__ __forceinline__ void stage_taps(const Taps& t, float* dst) {
 // kTC consecutive radial columns in LDS -- every input read once, in
 // 256-byte rows, one wavefront per row -- and computes the tile's outputs
 // from LDS.  The tile (dynamic LDS) is sized by the radius: the launch
-// picks the longest tile_len <= 128 whose tile fits kColTileBytes (three
-// 512-thread blocks per CU at least).  Views
+// picks the longest tile_len <= 128 whose tile fits col_tile_limit() (two
+// 512-thread blocks per CU, the register budget's limit, or one tile of
+// kColTileBytesSmall on a device with less LDS).  Views
 // are periodic over 180 degrees, and past the seam the same LOR is seen
 // from the other end (radial and TOF indices reversed); planes reflect at
 // the ends.
@@ -257,7 +258,8 @@ __device__ __forceinline__ void stage_taps(const Taps& t, float* dst) {
 // no faster: its tiles are short sums over few taps.)
 constexpr int kTC = 64;
 constexpr int kMaxTileLen = 128;
-constexpr size_t kColTileBytes = 48 * 1024;
+constexpr size_t kColTileBytes = 78 * 1024;
+constexpr size_t kColTileBytesSmall = 48 * 1024;
 constexpr int kColThreads = 512;
 constexpr int kColMinBlocks = 3;  // minimum waves per SIMD the register budget allows for
 constexpr int kColRowsPerSweep = kColThreads / kTC;
@@ -791,6 +793,16 @@ DeviceShape device_shape() {
 int device_cus() { return device_shape().cus; }
 }  // namespace
 
+namespace {
+// LDS bytes of one column-pass tile: two tiles of kColTileBytes per CU when
+// the device's LDS holds them, else kColTileBytesSmall.
+size_t col_tile_limit() {
+  const size_t dev = device_shape().lds;
+  const size_t static_lds = (2 * kMaxSmoothRadius + 4) * sizeof(float);  // the tap array
+  return dev >= 2 * (kColTileBytes + static_lds) ? kColTileBytes : kColTileBytesSmall;
+}
+}  // namespace
+
 size_t fused_lds_limit() {
   const size_t dev = device_shape().lds;
   const size_t static_lds = 2 * (2 * kMaxSmoothRadius + 4) * sizeof(float);  // the two tap arrays
@@ -921,10 +933,11 @@ hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, boo
   }
   const int n = axis == 1 ? g.n_view : g.n_plane;
   const int n_other = axis == 1 ? g.n_plane : g.n_view;
+  const size_t limit = col_tile_limit();
   int tile_len = kMaxTileLen;
-  while (tile_len > 16 && col_tile_bytes(tile_len, n, taps.radius) > kColTileBytes) tile_len /= 2;
+  while (tile_len > 16 && col_tile_bytes(tile_len, n, taps.radius) > limit) tile_len /= 2;
   a.tile_len = tile_len;
-  const size_t lds = col_tile_bytes(tile_len, n, taps.radius);  // <= kColTileBytes up to radius 63
+  const size_t lds = col_tile_bytes(tile_len, n, taps.radius);  // <= 38 KB at tile_len 16 and radius 63
   const int n_col_tiles = (g.n_rad + kTC - 1) / kTC;
   const int n_axis_tiles = (n + tile_len - 1) / tile_len;
   const uint64_t groups = static_cast<uint64_t>(n_other) * g.n_tof;
