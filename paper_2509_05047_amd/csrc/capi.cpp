@@ -365,7 +365,8 @@ sse_status ensure_pairs(sse_ctx* c, uint64_t n) {
   constexpr uint64_t kMinCap = kMinPairCap;
   if (!c->d_item) HIP_TRY(hipMalloc(&c->d_item, sizeof(sse::TransportParams)), "allocate work-list scratch");
   if (!c->d_chunk) HIP_TRY(hipMalloc(&c->d_chunk, sizeof(sse::WorkChunk)), "allocate work-list scratch");
-  if (!c->d_cursor) HIP_TRY(hipMalloc(&c->d_cursor, sizeof(uint32_t)), "allocate work-list scratch");
+  if (!c->d_cursor)
+    HIP_TRY(hipMalloc(&c->d_cursor, sse::kCursorWords * sizeof(uint32_t)), "allocate work-list scratch");
   const uint64_t want = std::max(sse::transport_pairs_needed(n), sse::transport_batch_pairs_needed(n));
   uint64_t cap = want < kDefaultCap ? want : kDefaultCap;
   cap = (cap + 0xffffull) & ~0xffffull;

@@ -238,7 +238,17 @@ struct BatchParams {
   // launch: the launch ends early and the next one goes on from the claim
   // cursor); ~0 never stops.
   uint64_t stop_at = ~0ull;
+  // Fill launches: a flag, in a cache line of its own, that the wavefront
+  // finding the cursor at the end sets; while it is set no slice is claimed
+  // (or NULL: not kept).
+  uint32_t* done = nullptr;
 };
+
+// Words from the claim cursor to the fill launches' end flag (128 bytes: the
+// flag lies in another cache line than the cursor's atomic adds); d_cursor of
+// launch_transport_item holds at least kCursorWords words.
+constexpr uint32_t kDoneOffsetWords = 32;
+constexpr uint32_t kCursorWords = 64;
 
 // HIP events recorded around the kernels of work-list launches (for
 // measurement): launch i records ev[4i] / ev[4i + 1] before and after its
@@ -255,10 +265,11 @@ struct KernelTiming {
 // in all): pair-counter reset, transport, coincidences (timed if kt).
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, KernelTiming* kt = nullptr);
 // Histories [p.h0, p.h0 + p.n) of one request through the work-list kernels
-// (the production path of a simulate call: no statistics, no records), in
-// launches of at most transport_batch_max_histories(p.pair_cap) histories;
-// d_item, d_chunk and d_cursor are device scratch of one parameter set, one
-// chunk and one claim cursor.
+// (the production path of a simulate call: no statistics, no records):
+// fill launches when the pair buffer is large enough, else launches of at
+// most transport_batch_max_histories(p.pair_cap) histories; d_item, d_chunk
+// and d_cursor are device scratch of one parameter set, one chunk and the
+// claim cursor with the fill launches' end flag (kCursorWords words).
 hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_item, WorkChunk* d_chunk,
                                  uint32_t* d_cursor, hipStream_t stream, KernelTiming* kt = nullptr);
 

@@ -1386,13 +1386,21 @@ transport_batch_kernel(BatchParams b) {
   auto claim = [&](WorkChunk& ch) -> bool {
     uint32_t pos = 0;
     if (lane == 0) {
-      // a fill launch stops claiming once the buffer holds what every
-      // resident wavefront may still add to it (the pair counter is read at
-      // device scope, past this CU's cache)
-      const bool full = b.stop_at != ~0ull &&
-                        static_cast<uint64_t>(__hip_atomic_load(b.pair_count, __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT)) > b.stop_at;
-      pos = full ? 0xffffffffu : atomicAdd(b.counter, kBatchSlice);
+      // A fill launch stops claiming once the buffer holds what every
+      // resident wavefront may still add to it, or once the end flag is set:
+      // in the empty launches that follow a fill run, every wavefront's
+      // atomic add on the one cursor would serialise.  (The flag is read
+      // rather than the cursor, whose line the atomic adds keep busy; both
+      // words are read at device scope, past this CU's cache.)
+      bool stop = false;
+      if (b.done) {  // a fill launch (both words are loaded before either is tested)
+        const uint32_t done = __hip_atomic_load(b.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t count = __hip_atomic_load(b.pair_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stop = done != 0u || static_cast<uint64_t>(count) > b.stop_at;
+      }
+      pos = stop ? 0xffffffffu : atomicAdd(b.counter, kBatchSlice);
+      if (b.done && !stop && pos >= b.n_positions)
+        __hip_atomic_store(b.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     pos = __builtin_amdgcn_readfirstlane(__shfl(pos, 0, 64));
     if (pos >= b.n_positions) return false;
@@ -1664,10 +1672,12 @@ hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_it
       const WorkChunk ch{p.h0 + done, static_cast<uint32_t>(n), 0u};
       hipLaunchKernelGGL(store_item_kernel, dim3(1), dim3(1), 0, stream, q, ch, d_item, d_chunk);
       hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, d_cursor);
+      hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, d_cursor + kDoneOffsetWords);
       const uint64_t positions = (n + kBatchSlice - 1) / kBatchSlice * kBatchSlice;
       BatchParams b{d_item, d_chunk, 1u, static_cast<uint32_t>(positions), d_cursor, n,
                     p.pairs, p.pair_count, p.pair_cap, p.gap_on};
       b.stop_at = stop_at;
+      b.done = d_cursor + kDoneOffsetWords;
       const uint64_t launches = (n + per_launch - 1) / per_launch;
       for (uint64_t k = 0; k < launches; ++k) {
         const hipError_t e = launch_batch_pass(b, stream, kt, false);
@@ -1731,6 +1741,7 @@ constexpr uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
 constexpr uint64_t kNoAllocChunkAt = align256(sizeof(TransportParams));
 constexpr uint64_t kNoAllocCursorAt = kNoAllocChunkAt + align256(sizeof(WorkChunk));
 constexpr uint64_t kNoAllocCountAt = kNoAllocCursorAt + 256;
+static_assert(kNoAllocCountAt - kNoAllocCursorAt >= kCursorWords * sizeof(uint32_t), "cursor slot too small");
 constexpr uint64_t kNoAllocHeader = kNoAllocCountAt + 256;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
@@ -1779,7 +1790,7 @@ hipError_t launch_transport_noalloc(int device, const TransportParams& p0, hipSt
 
 hipError_t launch_transport_batch(const BatchParams& b, hipStream_t stream, KernelTiming* kt) {
   if (b.n_chunks == 0) return hipSuccess;
-  if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap || b.stop_at != ~0ull ||
+  if (!b.pairs || !b.pair_count || b.pair_cap > kMaxPairCap || b.stop_at != ~0ull || b.done ||
       b.n_histories > transport_batch_max_histories(b.pair_cap))
     return hipErrorInvalidValue;
   return launch_batch_pass(b, stream, kt, true);
