@@ -661,7 +661,9 @@ def main():
                      "traffic": (measured_traffic() if args.workload == "clinical" and n == w.n_histories
                                  and args.lut == "f32" and args.lut_mode == "lut5d" and gaps is None
                                  and args.lut_shape == "workload" else None),
-                     "kernel": "transport_batch_kernel (transport, detection; 97 % of the step)",
+                     "kernel": "transport_batch_kernel (transport, detection; 97 % of the step); a step is one "
+                               "fill launch that takes every history and empty launches after it, and kernel_ms "
+                               "averages all of them, as histories_per_launch does",
                      "kernel_ms": t_launch_ms, "launches_per_step": launches_per_step,
                      "histories_per_launch": hist_per_launch,
                      "ops_per_history": ops_transport,
