@@ -1661,12 +1661,14 @@ hipError_t launch_transport_item(const TransportParams& p, TransportParams* d_it
   // three blocks.
   const uint64_t rw = resident_blocks(transport_batch_kernel) * (kBlock / 64);
   const uint64_t headroom = rw * 3u * kPairBlock;
-  if (rw > 0 && p.pair_cap > headroom + 2u * rw * kPairBlock) {
-    const uint64_t stop_at = p.pair_cap - headroom;
-    // histories a launch takes at least before it stops: past stop_at the
-    // counter holds a partly used block per wavefront, and every block
-    // is padded by at most 63 records
-    const uint64_t per_launch = (stop_at - rw * kPairBlock) / kPairBlock * (kPairBlock - 64);
+  const uint64_t stop_at = p.pair_cap > headroom ? p.pair_cap - headroom : 0;
+  // Histories a launch takes at least before it stops: it stops with more
+  // than stop_at records reserved, of which every block gave at most 63 to
+  // padding and every wavefront at most a block to its unused tail, and a
+  // history queues at most one pair.
+  const uint64_t records_min = stop_at / kPairBlock * (kPairBlock - 63);
+  const uint64_t per_launch = records_min > 2u * rw * kPairBlock ? records_min - rw * kPairBlock : 0;
+  if (rw > 0 && per_launch > 0) {
     for (uint64_t done = 0; done < p.n;) {
       const uint64_t n = p.n - done < kFillRun ? p.n - done : kFillRun;
       const WorkChunk ch{p.h0 + done, static_cast<uint32_t>(n), 0u};

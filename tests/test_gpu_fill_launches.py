@@ -29,7 +29,7 @@ def test_fill_launches_resume_where_the_buffer_filled():
     case = H.case_from("clinical")
     ctx, pid = H.open_context(case)
     n, seed = 1_200_000_000, 4242
-    small = 14 << 20  # fill launches: above the fill threshold of an MI355X (13.1 M records)
+    small = 14 << 20  # fill launches: above the fill threshold of an MI355X (13.8 M records)
     try:
         print(f"[fill] clinical, {n} histories, default buffer", flush=True)
         a = run(ctx, pid, n, seed)
