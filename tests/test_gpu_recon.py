@@ -39,9 +39,12 @@ def close(got, ref, rtol=1e-4, atol_frac=2e-5):
     assert not bad.any(), (int(bad.sum()), float(np.abs(got - ref).max()), float(np.abs(ref).max()))
 
 
-def setup(which, tof_sigma=None):
+def setup(which, tof_sigma=None, n_tof=None):
     w = W.WORKLOADS[which]
     sino = w.sino if tof_sigma is None else W.Sinogram(**{**w.sino.__dict__, "tof_sigma_mm": tof_sigma})
+    if n_tof is not None:  # the same TOF range in n_tof bins
+        span = sino.n_tof * sino.tof_bin_mm
+        sino = W.Sinogram(**{**sino.__dict__, "n_tof": n_tof, "tof_bin_mm": span / n_tof})
     pd, mu, act = W.make_phantom(w)
     ctx = sse.Context(w.scanner, sino, w.physics)
     pid = ctx.load_phantom(pd, mu, act)
@@ -148,8 +151,11 @@ def test_gpu_projector_pair_is_adjoint(which):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
 
 
-def test_osem_matches_oracle_tiny():
-    w, sino, pd, mu, act, ctx, pid = setup("tiny", 20.0)
+# TOF bins per LOR in the compact subset layout: 8 (5 bins), 16 (11, the tiny
+# workload's own) and 32 (29, the clinical workload's count)
+@pytest.mark.parametrize("n_tof", [5, 11, 29])
+def test_osem_matches_oracle_tiny(n_tof):
+    w, sino, pd, mu, act, ctx, pid = setup("tiny", 20.0, n_tof)
     try:
         x_true = smooth_image(pd, sino.n_plane, 6).astype(np.float64)
         att = np.exp(-O.recon_project(w.scanner, sino, pd, 0.0096 * (x_true > 0.05), tof=False))
