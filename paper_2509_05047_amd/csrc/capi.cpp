@@ -549,6 +549,7 @@ sse_status sse_destroy(sse_ctx* c) {
   if (c->d_partials) release(c->d_partials);
   release(c->d_lor);
   release(c->d_view);
+  release(c->d_qtab);
   release(c->d_major);
   release(c->d_recon_fp);
   release(c->d_recon_img[0]);

@@ -75,6 +75,7 @@ struct sse_ctx {
   // reconstruction: LOR and view tables of the projector, OSEM scratch
   void* d_lor = nullptr;
   void* d_view = nullptr;
+  void* d_qtab = nullptr;
   void* d_major = nullptr;
   float* d_recon_fp = nullptr;
   uint64_t recon_fp_cap = 0;

@@ -21,7 +21,9 @@ namespace sse {
 // parameters of the back projector's search (see recon.hip).
 struct ReconGeom {
   int n_rad, n_view, n_plane, n_tof;
-  float tof_bin, tof_sigma, inv_sigma_sqrt2;
+  float tof_bin, tof_sigma;
+  float q_scale;        // 1 / (sigma h): TOF distance to table intervals
+  const float4* q_tab;  // the normal tail Q by intervals (see kQIntervals)
   int nx, ny;
   float vx, vy, lox, loy, ivx, ivy;
   const float4* lor;
@@ -30,6 +32,14 @@ struct ReconGeom {
   int subset, n_subsets, n_sv;
   float radius, rho_scale, rho_max, win_num, win_extra;
 };
+
+// The TOF weights' normal tail Q(v) = erfc(v / sqrt 2) / 2 by cubic
+// Hermite interpolation on kQIntervals intervals of [-kQRange, kQRange]:
+// q_tab[k] holds the binary64 coefficients, rounded, of Q(v_k + f h) =
+// a0 + f (a1 + f (a2 + f a3)), f in [0, 1], h = 2 kQRange / kQIntervals
+// (interpolation error below 1e-10; Q is held at its end values outside).
+constexpr int kQIntervals = 1024;
+constexpr double kQRange = 6.5;
 
 // A sinogram as the kernels address it: bin (t, plane, sv, rad) at
 // p[t ts + plane ps + sv vs + rad].

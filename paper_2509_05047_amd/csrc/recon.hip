@@ -91,10 +91,22 @@ __device__ __forceinline__ void tof_range(const ReconGeom& g, float s, int& jlo,
   jhi = jhi > g.n_tof - 1 ? g.n_tof - 1 : jhi;
 }
 
-// Phi((e_j - s) / sigma) for the lower edge e_j of bin j.
+// Phi((e_j - s) / sigma) = Q((s - e_j) / sigma) for the lower edge e_j of
+// bin j, from the interpolation table (three multiply-adds and one 16-byte
+// read instead of an erfc).
 __device__ __forceinline__ float edge_cdf(const ReconGeom& g, int j, float s) {
   const float e = (static_cast<float>(j) - 0.5f * static_cast<float>(g.n_tof)) * g.tof_bin;
-  return 0.5f * erfcf((s - e) * g.inv_sigma_sqrt2);
+  // w = v / h counts intervals from v = 0, so that the fraction f keeps its
+  // precision where Q varies fastest (the table's origin is interval
+  // kQIntervals / 2)
+  const float w = (s - e) * g.q_scale;
+  const float fl = floorf(w);
+  const float kf = fl + static_cast<float>(kQIntervals / 2);
+  const bool below = !(kf >= 0.0f), above = kf > static_cast<float>(kQIntervals - 1);
+  const int k = below ? 0 : (above ? kQIntervals - 1 : static_cast<int>(kf));
+  const float f = below ? 0.0f : (above ? 1.0f : w - fl);
+  const float4 c = g.q_tab[k];
+  return __builtin_fmaf(f, __builtin_fmaf(f, __builtin_fmaf(f, c.w, c.z), c.y), c.x);
 }
 
 __device__ __forceinline__ float4 lor_at(const ReconGeom& g, int view, int rad) {

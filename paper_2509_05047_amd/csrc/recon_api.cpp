@@ -20,7 +20,11 @@ constexpr double kPiD = 3.141592653589793;
 // (the sinogram mapping of the coincidence evaluation), TOF-positive end
 // first, and from it the LOR table and the view table of the projector.
 sse_status ensure_lor_tables(sse_ctx* c) {
-  if (c->d_lor) return SSE_OK;
+  if (c->d_lor && c->d_view && c->d_major && c->d_qtab) return SSE_OK;
+  for (void** t : {&c->d_lor, &c->d_view, &c->d_major, &c->d_qtab}) {  // after a failed build
+    release(*t);
+    *t = nullptr;
+  }
   const int n = c->sc.n_crystals, n_rad = c->sn.n_rad, n_view = c->sn.n_view, half = (n_rad - 1) / 2;
   const double R = c->sc.radius_mm;
   std::vector<float4> lor(static_cast<size_t>(n_view) * n_rad, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
@@ -71,6 +75,21 @@ sse_status ensure_lor_tables(sse_ctx* c) {
   HIP_TRY(hipMemcpy(c->d_lor, lor.data(), lor.size() * sizeof(float4), hipMemcpyHostToDevice), "upload LOR table");
   HIP_TRY(hipMemcpy(c->d_view, view.data(), view.size() * sizeof(float4), hipMemcpyHostToDevice),
           "upload view table");
+  // the TOF weights' normal tail Q(v) = erfc(v / sqrt 2) / 2, cubic Hermite
+  // coefficients (values and slopes -phi at the interval ends) per interval
+  std::vector<float4> q(sse::kQIntervals);
+  const double h = 2.0 * sse::kQRange / sse::kQIntervals;
+  auto tail = [](double v) { return 0.5 * std::erfc(v / std::sqrt(2.0)); };
+  auto slope = [h](double v) { return -h * std::exp(-0.5 * v * v) / std::sqrt(2.0 * kPiD); };
+  for (int k = 0; k < sse::kQIntervals; ++k) {
+    const double v0 = -sse::kQRange + k * h, v1 = v0 + h;
+    const double q0 = tail(v0), q1 = tail(v1), d0 = slope(v0), d1 = slope(v1);
+    q[k] = make_float4(static_cast<float>(q0), static_cast<float>(d0), static_cast<float>(3.0 * (q1 - q0) - 2.0 * d0 - d1),
+                       static_cast<float>(2.0 * (q0 - q1) + d0 + d1));
+  }
+  HIP_TRY(hipMalloc(&c->d_qtab, q.size() * sizeof(float4)), "allocate TOF weight table");
+  HIP_TRY(hipMemcpy(c->d_qtab, q.data(), q.size() * sizeof(float4), hipMemcpyHostToDevice),
+          "upload TOF weight table");
   return SSE_OK;
 }
 
@@ -82,7 +101,8 @@ sse::ReconGeom geom_of(const sse_ctx* c, const Phantom* ph, int subset, int n_su
   g.n_tof = c->sn.n_tof;
   g.tof_bin = c->sn.tof_bin_mm;
   g.tof_sigma = c->sn.tof_sigma_mm;
-  g.inv_sigma_sqrt2 = g.tof_sigma > 0.0f ? static_cast<float>(1.0 / (g.tof_sigma * std::sqrt(2.0))) : 0.0f;
+  g.q_scale = g.tof_sigma > 0.0f ? static_cast<float>(sse::kQIntervals / (2.0 * sse::kQRange * g.tof_sigma)) : 0.0f;
+  g.q_tab = static_cast<const float4*>(c->d_qtab);
   g.nx = ph->desc.nx;
   g.ny = ph->desc.ny;
   g.vx = ph->desc.voxel_mm[0];
