@@ -326,8 +326,11 @@ sse_status sse_load_sensitivity(sse_ctx* ctx, const float* sens, int has_tof_axi
  * Introduction, footnote on scatter).  Random numbers: Philox4x32-10 keyed
  * by the seed, counter (block, h, substream); history results do not depend
  * on the launch, so runs split over calls or GPUs sum to the same result.
- * Asynchronous on `stream`.  Errors: SSE_EINVAL (unknown phantom, null or
- * misaligned outputs, record stride 0), SSE_ESTATE (no LUT loaded). */
+ * Device memory: the context's pair buffer (sse_set_pair_buffer) and a few
+ * words of work-list scratch, allocated on first use and grown for longer
+ * runs up to the buffer's limit.  Asynchronous on `stream`.  Errors:
+ * SSE_EINVAL (unknown phantom, null or misaligned outputs, record stride 0),
+ * SSE_ESTATE (no LUT loaded), SSE_ENOMEM (no pair buffer of 2^22 records). */
 sse_status sse_simulate(sse_ctx* ctx, sse_phantom_id id, uint64_t n_histories, uint64_t seed,
                         uint64_t h_offset, const sse_outputs* out, void* stream);
 
