@@ -21,8 +21,9 @@
 // Phi((lo_j - s)/sigma) for the bins within 5 sigma of s (the bin holding s
 // with sigma = 0).
 //
-// Forward: one thread per LOR of the requested views, its TOF bins
-// accumulated in a private LDS column.  Back: one thread per pixel, which
+// Forward: four threads per LOR of the requested views, each over a share
+// of its samples, their TOF bins accumulated in private LDS columns and
+// added in a fixed order.  Back: one thread per pixel, which
 // finds the LORs of each view whose samples read it (a window of radial
 // indices around the pixel's distance from the view's centre LOR) and takes
 // exactly the weights the forward sample computes, so the pair is a transpose
@@ -113,28 +114,36 @@ __device__ __forceinline__ float4 lor_at(const ReconGeom& g, int view, int rad) 
   return g.lor[static_cast<uint64_t>(view) * g.n_rad + rad];
 }
 
-// Forward projection: thread per (plane, sv, rad) LOR, views subset + sv n_subsets.
+// Forward projection: kProjSplit threads per (plane, sv, rad) LOR (views
+// subset + sv n_subsets), each over an equal share of the LOR's samples: a
+// block takes 64 LORs, wavefront w the w-th share of each, so the launch
+// has four times as many wavefronts as LORs need and its long sample loops
+// overlap.  Each thread accumulates its TOF bins in its own LDS column; the
+// shares are then added in share order (deterministic) and written.
+constexpr int kProjSplit = kReconThreads / 64;
 __global__ void __launch_bounds__(kReconThreads) project_kernel(ReconGeom g, const float* __restrict__ img,
                                                                 SinoOut out, int tof) {
-  extern __shared__ float acc_lds[];  // [n_tof][kReconThreads] when tof
-  const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  extern __shared__ float acc_lds[];  // [nt][kReconThreads]
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  const int share = static_cast<int>(threadIdx.x >> 6);
+  const uint64_t id = static_cast<uint64_t>(blockIdx.x) * 64u + lane;
   const uint64_t n_lor = static_cast<uint64_t>(g.n_plane) * g.n_sv * g.n_rad;
-  if (id >= n_lor) return;
-  const int rad = static_cast<int>(id % g.n_rad);
-  const int sv = static_cast<int>((id / g.n_rad) % g.n_sv);
-  const int plane = static_cast<int>(id / (static_cast<uint64_t>(g.n_rad) * g.n_sv));
+  const bool live = id < n_lor;
+  const uint64_t idc = live ? id : 0;
+  const int rad = static_cast<int>(idc % g.n_rad);
+  const int sv = static_cast<int>((idc / g.n_rad) % g.n_sv);
+  const int plane = static_cast<int>(idc / (static_cast<uint64_t>(g.n_rad) * g.n_sv));
   const int view = g.subset + sv * g.n_subsets;
   const int nt = tof ? g.n_tof : 1;
   float* acc = acc_lds + threadIdx.x;
-  float acc1 = 0.0f;
-  if (tof)
-    for (int j = 0; j < nt; ++j) acc[j * kReconThreads] = 0.0f;
+  for (int j = 0; j < nt; ++j) acc[j * kReconThreads] = 0.0f;
   const float4 l = lor_at(g, view, rad);
-  if (l.z != 0.0f || l.w != 0.0f) {
+  if (live && (l.z != 0.0f || l.w != 0.0f)) {
     const float* im = img + static_cast<uint64_t>(plane) * g.nx * g.ny;
     const bool mx = g.major[static_cast<uint64_t>(view) * g.n_rad + rad] != 0;
     const int ns = mx ? g.nx : g.ny, n_minor = mx ? g.ny : g.nx;
-    for (int k = 0; k < ns; ++k) {
+    const int k0 = ns * share / kProjSplit, k1 = ns * (share + 1) / kProjSplit;
+    for (int k = k0; k < k1; ++k) {
       const Sample o = lor_sample(g, l.x, l.y, l.z, l.w, mx, k);
       if (o.i0 < -1 || o.i0 >= n_minor) continue;
       const float v0 = o.i0 >= 0 ? im[mx ? o.i0 * g.nx + k : k * g.nx + o.i0] : 0.0f;
@@ -143,7 +152,7 @@ __global__ void __launch_bounds__(kReconThreads) project_kernel(ReconGeom g, con
       if (val == 0.0f) continue;
       const float c = o.dl * val;
       if (!tof) {
-        acc1 += c;
+        acc[0] += c;
         continue;
       }
       int jlo, jhi;
@@ -160,12 +169,17 @@ __global__ void __launch_bounds__(kReconThreads) project_kernel(ReconGeom g, con
       }
     }
   }
+  __syncthreads();
+  if (!live) return;
+  // bins j = share, share + kProjSplit, ... of the block's LOR `lane`
   const uint64_t base = static_cast<uint64_t>(plane) * out.ps + static_cast<uint64_t>(sv) * out.vs + rad;
-  if (!tof) {
-    out.p[base] = acc1;
-    return;
+  const float* col = acc_lds + lane;
+  for (int j = share; j < nt; j += kProjSplit) {
+    float v = col[j * kReconThreads];
+#pragma unroll
+    for (int q = 1; q < kProjSplit; ++q) v += col[j * kReconThreads + 64 * q];
+    out.p[base + static_cast<uint64_t>(j) * (tof ? out.ts : 0)] = v;
   }
-  for (int j = 0; j < nt; ++j) out.p[base + static_cast<uint64_t>(j) * out.ts] = acc[j * kReconThreads];
 }
 
 // Back projection: thread per (plane, iy, ix) pixel.
@@ -306,9 +320,9 @@ int grid_for(uint64_t n) {
 
 hipError_t launch_project(const ReconGeom& g, const float* img, const SinoOut& out, int tof, hipStream_t s) {
   const uint64_t n = static_cast<uint64_t>(g.n_plane) * g.n_sv * g.n_rad;
-  const size_t lds = tof ? static_cast<size_t>(g.n_tof) * kReconThreads * sizeof(float) : 0;
-  hipLaunchKernelGGL(project_kernel, dim3(static_cast<unsigned>((n + kReconThreads - 1) / kReconThreads)),
-                     dim3(kReconThreads), lds, s, g, img, out, tof);
+  const size_t lds = static_cast<size_t>(tof ? g.n_tof : 1) * kReconThreads * sizeof(float);
+  hipLaunchKernelGGL(project_kernel, dim3(static_cast<unsigned>((n + 63) / 64)), dim3(kReconThreads), lds, s, g, img,
+                     out, tof);
   return hipGetLastError();
 }
 
