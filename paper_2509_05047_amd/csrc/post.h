@@ -38,7 +38,7 @@ hipError_t launch_smooth_axis(const PostParams& g, int axis, const void* in, boo
 // device's per-block LDS, at most kFusedLdsBytes -- or its staging slots, or
 // would be mostly halo; use the one-axis passes).  Same input and output
 // treatment as launch_smooth_axis.
-constexpr size_t kFusedLdsBytes = 128 * 1024;
+constexpr size_t kFusedLdsBytes = 160 * 1024;
 size_t fused_lds_limit();
 struct FusedPlan {
   int tl, n_tiles, sx, sy;

@@ -205,6 +205,7 @@ __device__ __forceinline__ void window_sums(const float* x, int stride, const fl
 #pragma unroll
   for (int i = 0; i < kO - 1; ++i) win[i] = x[i * stride];
   int k = 0;
+#pragma unroll 2
   for (; k + 4 <= n; k += 4) {
     const float4 w4 = *reinterpret_cast<const float4*>(w + k);
 #pragma unroll
@@ -470,30 +471,35 @@ __global__ void __launch_bounds__(256) smooth_rows(SmoothArgs a, uint64_t n_rows
 
 // Radial and plane passes fused over one (TOF, view) row: a tile of f.tl
 // radial positions by every plane, plus the radial halo (reflected at the
-// row ends), is staged in LDS; the rows are smoothed radially into
-// registers and written back over the staged input, each plane also into
-// the rows of the plane halo that reflect it, and the columns are smoothed
-// along the planes from there.  HBM sees the input once (plus the radial
-// halo, which the tile's neighbours on the same XCD read at about the same
-// time) and the output once: the intermediate never leaves the CU.
+// row ends), is staged in LDS; the rows are smoothed radially and stored in
+// a second LDS region, each plane also into the slots of the plane halo
+// that reflect it, and the columns are smoothed along the planes from
+// there.  HBM sees the input once (plus the radial halo, which the tile's
+// neighbours on the same XCD read at about the same time) and the output
+// once: the intermediate never leaves the CU.
 //
 // The kernel is persistent, one 1024-thread block per CU, and pipelined:
 // while a block smooths one tile, the loads of its next tile are in flight
 // into registers, so the CU's memory traffic overlaps its arithmetic instead
-// of alternating with it.
+// of alternating with it.  With the two regions apart a tile takes two
+// barriers: the next staging writes only the first region, so it does not
+// wait for the plane sums, and no radial sum is held across a barrier.
 //
 // Radial outputs come in blocks of kFusedWin per thread (sliding window,
 // lanes on consecutive planes: the row stride is odd, so the lanes hit
 // distinct banks); plane outputs likewise, lanes on consecutive radial
-// positions.  Both sums run their taps in the order k = 0 .. 2R as the
-// one-axis passes do.
+// positions, from the radially smoothed values stored one radial position's
+// planes after another, so that both sums read LDS at unit stride and the
+// window loads take immediate offsets.  Both sums run their taps in the
+// order k = 0 .. 2R as the one-axis passes do.
 struct FusedArgs {
   SmoothArgs a;   // a.taps: the radial taps
   Taps plane;     // the plane taps
   int tl;         // radial outputs per tile (<= kFusedMaxTile)
   int n_tiles;    // tiles per (TOF, view) row
   int sx;         // LDS row stride of the staged input (odd, >= tl + 2 R + kFusedWin - 1)
-  int sy;         // LDS row stride of the radially smoothed rows (odd, >= tl)
+  int sy;         // LDS stride between radial positions of the radially smoothed columns (odd, >= np + 2 Rp + kFusedWin - 1)
+  int y0;         // LDS float offset of the smoothed columns (after the np sx staged floats)
   uint32_t n_units;  // tile slots of the XCD mapping (8 ceil(rows / 8) n_tiles)
 };
 constexpr int kFusedThreads = 1024;
@@ -625,56 +631,52 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
   if (u >= f.n_units) return;
   FusedPrefetch<kFromF64, kNormIn> pre;
   pre.issue(a, cur, np, ps);
+  float* const ys = lds + f.y0;  // the radially smoothed values, after the staged input
   while (true) {
+    // The staged input was last read by the previous tile's radial sums,
+    // before the barrier that preceded its plane sums: it may be
+    // overwritten while other waves still sum planes.
     pre.store(a, cur, np, f.sx, lds);
-    __syncthreads();
+    __syncthreads();  // staged; and the previous tile's plane sums are done with ys
     const uint32_t un = fused_next(f, u + gridDim.x, nxt);
     if (un < f.n_units) pre.issue(a, nxt, np, ps);  // in flight while this tile is smoothed
     const int tl = cur.tl;
 
     // Radial sums: item i = threadIdx.x + 1024 m is plane i % np, outputs
-    // kFusedWin (i / np) .. + kFusedWin - 1 of the tile.
+    // kFusedWin (i / np) .. + kFusedWin - 1 of the tile, stored as soon as
+    // they are summed.  The radially smoothed values are kept by radial
+    // position: column c holds y_rows consecutive floats, plane p at Rp + p
+    // and, with direct_halo, also at the halo slots that reflect it:
+    // Rp - 1 - p (p < Rp) and Rp + 2 np - 1 - p (when below y_rows; the last
+    // kFusedWin - 1 halo slots are read only by outputs past the final
+    // plane).  Lanes on consecutive planes write consecutive floats.
     const int n_ch = (tl + kFusedWin - 1) / kFusedWin;
     const int dp = kFusedThreads % np, dch = kFusedThreads / np;
-    float acc[kFusedItems][kFusedWin];
-    {
-      int p = static_cast<int>(threadIdx.x) % np, ch = static_cast<int>(threadIdx.x) / np;
-#pragma unroll
-      for (int m = 0; m < kFusedItems; ++m) {
-#pragma unroll
-        for (int j = 0; j < kFusedWin; ++j) acc[m][j] = 0.0f;
-        if (ch < n_ch) window_sums<kFusedWin>(lds + p * f.sx + kFusedWin * ch, 1, tw_r, 2 * Rr + 1, acc[m]);
-        p += dp;
-        ch += dch;
-        if (p >= np) {
-          p -= np;
-          ++ch;
-        }
-      }
-    }
-    __syncthreads();  // every staged value read: the rows below overwrite them
-
-    // Radially smoothed plane p goes to row Rp + p and, with direct_halo,
-    // to the halo rows that reflect it: Rp - 1 - p (p < Rp) and
-    // Rp + 2 np - 1 - p (when below y_rows; the last kFusedWin - 1 halo rows
-    // are read only by outputs past the final plane).
     {
       int p = static_cast<int>(threadIdx.x) % np, ch = static_cast<int>(threadIdx.x) / np;
 #pragma unroll
       for (int m = 0; m < kFusedItems; ++m) {
         if (ch < n_ch) {
+          float acc[kFusedWin] = {};
+          window_sums<kFusedWin>(lds + p * f.sx + kFusedWin * ch, 1, tw_r, 2 * Rr + 1, acc);
           const int c0 = kFusedWin * ch;
-          float* yr = lds + (Rp + p) * f.sy + c0;
-          float* ytop = lds + (Rp - 1 - p) * f.sy + c0;
-          float* ybot = lds + (Rp + 2 * np - 1 - p) * f.sy + c0;
+          // The store addresses do not change from tile to tile; computed
+          // here (the empty asm hides that) rather than hoisted out of the
+          // tile loop, where 48 of them would take registers the prefetch
+          // needs and spill.
+          int col = c0 * f.sy;
+          asm volatile("" : "+v"(col));
+          float* yr = ys + col + (Rp + p);
+          float* ytop = ys + col + (Rp - 1 - p);
+          float* ybot = ys + col + (Rp + 2 * np - 1 - p);
           const bool top = direct_halo && p < Rp;
           const bool bot = direct_halo && Rp + 2 * np - 1 - p < y_rows;
 #pragma unroll
           for (int j = 0; j < kFusedWin; ++j)
             if (c0 + j < tl) {
-              yr[j] = acc[m][j];
-              if (top) ytop[j] = acc[m][j];
-              if (bot) ybot[j] = acc[m][j];
+              yr[j * f.sy] = acc[j];
+              if (top) ytop[j * f.sy] = acc[j];
+              if (bot) ybot[j * f.sy] = acc[j];
             }
         }
         p += dp;
@@ -685,19 +687,20 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
         }
       }
     }
-    __syncthreads();
-    if (!direct_halo) {  // halo rows by folding (radius near the plane count)
+    __syncthreads();  // the staged input is read: the next staging may overwrite it
+    if (!direct_halo) {  // halo slots by folding (radius near the plane count)
       for (int h = wave; h < 2 * Rp + kFusedWin - 1; h += kFusedWaves) {
         const int e = h < Rp ? h : np + h;
         const int m = fold(e - Rp, np);
         const int src = Rp + (m < np ? m : 2 * np - 1 - m);
-        for (int c = lane; c < tl; c += 64) lds[e * f.sy + c] = lds[src * f.sy + c];
+        for (int c = lane; c < tl; c += 64) ys[c * f.sy + e] = ys[c * f.sy + src];
       }
       __syncthreads();
     }
 
     // Plane sums: item i is radial position i % tl, planes kFusedWin (i / tl)
-    // .. + kFusedWin - 1.
+    // .. + kFusedWin - 1, summed along its column (unit stride, as the radial
+    // sums; the lanes' columns lie an odd stride apart, in distinct banks).
     const int n_pg = (np + kFusedWin - 1) / kFusedWin;
     float* out_row = a.out + cur.row0 + static_cast<uint64_t>(cur.r0);  // plane 0 of the tile
     const int dc = kFusedThreads % tl, dpg = kFusedThreads / tl;
@@ -713,7 +716,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
         }
       }
       float sm[kFusedWin] = {};
-      window_sums<kFusedWin>(lds + kFusedWin * pg * f.sy + c, f.sy, tw_p, 2 * Rp + 1, sm);
+      window_sums<kFusedWin>(ys + c * f.sy + kFusedWin * pg, 1, tw_p, 2 * Rp + 1, sm);
 #pragma unroll
       for (int j = 0; j < kFusedWin; ++j)
         if (kFusedWin * pg + j < np)
@@ -728,7 +731,6 @@ __global__ void __launch_bounds__(kFusedThreads, 1) smooth_rad_plane(FusedArgs f
       }
     }
     if (un >= f.n_units) break;
-    __syncthreads();  // the plane sums have read the rows the next staging overwrites
     u = un;
     cur = nxt;
   }
@@ -827,10 +829,10 @@ FusedPlan plan_rad_plane(const PostParams& g, int radial_radius, int plane_radiu
     if (radial_items > static_cast<int64_t>(kFusedThreads) * kFusedItems) continue;
     if (static_cast<int64_t>(g.n_plane) * (tl + 2 * radial_radius) > kFusedStage) continue;
     const int sx = (tl + 2 * radial_radius + kFusedWin - 1) | 1;
-    const int sy = tl | 1;
+    const int sy = (g.n_plane + 2 * plane_radius + kFusedWin - 1) | 1;
     const size_t x_floats = static_cast<size_t>(g.n_plane) * sx;
-    const size_t y_floats = static_cast<size_t>(g.n_plane + 2 * plane_radius + kFusedWin - 1) * sy;
-    const size_t lds = (x_floats > y_floats ? x_floats : y_floats) * sizeof(float);
+    const size_t y_floats = static_cast<size_t>(tl) * sy;
+    const size_t lds = (x_floats + y_floats) * sizeof(float);
     if (lds <= lds_max) {
       pl.tl = tl;
       pl.n_tiles = n_tiles;
@@ -895,7 +897,7 @@ hipError_t launch_smooth_rad_plane(const PostParams& g, const FusedPlan& pl, con
   if (units == 0) return hipSuccess;
   if (units > 0xffffffffull) return hipErrorInvalidValue;
   FusedArgs f{SmoothArgs{g, in, scale, norm_in, out, norm_out, sens, sens_tof, radial, 0, ratio_w}, plane, pl.tl,
-              pl.n_tiles, pl.sx, pl.sy, static_cast<uint32_t>(units)};
+              pl.n_tiles, pl.sx, pl.sy, g.n_plane * pl.sx, static_cast<uint32_t>(units)};
   // one block per CU (a multiple of 8: a block's units stay on its XCD)
   uint64_t blocks = static_cast<uint64_t>(device_cus() + 7) / 8 * 8;
   if (blocks > units) blocks = (units + 7) / 8 * 8;
