@@ -23,11 +23,11 @@
 //
 // Forward: four threads per LOR of the requested views, each over a share
 // of its samples, their TOF bins accumulated in private LDS columns and
-// added in a fixed order.  Back: one thread per pixel, which
-// finds the LORs of each view whose samples read it (a window of radial
-// indices around the pixel's distance from the view's centre LOR) and takes
-// exactly the weights the forward sample computes, so the pair is a transpose
-// up to the order of binary32 sums.  Binary32 throughout.
+// added in a fixed order.  Back: one thread per pixel and group of planes,
+// which finds the LORs of each view whose samples read the pixel (a window
+// of radial indices around the pixel's distance from the view's centre LOR)
+// and takes exactly the weights the forward sample computes, so the pair is
+// a transpose up to the order of binary32 sums.  Binary32 throughout.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -182,20 +182,27 @@ __global__ void __launch_bounds__(kReconThreads) project_kernel(ReconGeom g, con
   }
 }
 
-// Back projection: thread per (plane, iy, ix) pixel.
+// Back projection: thread per (iy, ix) pixel and group of kBackPlanes
+// planes.  A plane's LORs read only its own slice and the geometry is the
+// same in every plane, so the window, the Joseph weights and the TOF
+// weights of a (pixel, LOR) pair are computed once for the group and
+// applied to each of its planes' sinogram values, each plane summing in
+// the order a thread per pixel would.
+constexpr int kBackPlanes = 4;
 __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g, SinoIn in, float* __restrict__ img,
                                                                     int tof) {
   const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t npix = static_cast<uint64_t>(g.nx) * g.ny;
-  if (id >= npix * g.n_plane) return;
+  const int n_groups = (g.n_plane + kBackPlanes - 1) / kBackPlanes;
+  if (id >= npix * n_groups) return;
   const int ix = static_cast<int>(id % g.nx);
   const int iy = static_cast<int>((id / g.nx) % g.ny);
-  const int plane = static_cast<int>(id / npix);
+  const int p0 = static_cast<int>(id / npix) * kBackPlanes;
+  const int np = g.n_plane - p0 < kBackPlanes ? g.n_plane - p0 : kBackPlanes;  // planes of the group
   const float px = g.lox + (static_cast<float>(ix) + 0.5f) * g.vx;
   const float py = g.loy + (static_cast<float>(iy) + 0.5f) * g.vy;
   const int half = (g.n_rad - 1) / 2;
-  const int nt = tof ? g.n_tof : 1;
-  float total = 0.0f;
+  float total[kBackPlanes] = {};
   for (int sv = 0; sv < g.n_sv; ++sv) {
     const int view = g.subset + sv * g.n_subsets;
     // the pixel's distance from the view's centre LOR (normal and sign of
@@ -223,29 +230,42 @@ __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g,
       if (o.i0 == minor) wt = 1.0f - o.w1;
       else if (o.i0 + 1 == minor) wt = o.w1;
       else continue;
-      const uint64_t base = static_cast<uint64_t>(plane) * in.ps + static_cast<uint64_t>(sv) * in.vs + rad;
-      float a = 0.0f;
+      const float* src = in.p + static_cast<uint64_t>(p0) * in.ps + static_cast<uint64_t>(sv) * in.vs + rad;
+      float a[kBackPlanes] = {};
       if (!tof) {
-        a = in.p[base];
+#pragma unroll
+        for (int k = 0; k < kBackPlanes; ++k)
+          if (k < np) a[k] = src[static_cast<uint64_t>(k) * in.ps];
       } else if (g.tof_sigma <= 0.0f) {
         int jlo, jhi;
         tof_range(g, o.s, jlo, jhi);
-        if (jlo <= jhi) a = in.p[base + static_cast<uint64_t>(jlo) * in.ts];
+        if (jlo <= jhi) {
+#pragma unroll
+          for (int k = 0; k < kBackPlanes; ++k)
+            if (k < np) a[k] = src[static_cast<uint64_t>(k) * in.ps + static_cast<uint64_t>(jlo) * in.ts];
+        }
       } else {
         int jlo, jhi;
         tof_range(g, o.s, jlo, jhi);
         float lo = edge_cdf(g, jlo, o.s);
         for (int j = jlo; j <= jhi; ++j) {
           const float hi = edge_cdf(g, j + 1, o.s);
-          a += (hi - lo) * in.p[base + static_cast<uint64_t>(j) * in.ts];
+          const float wj = hi - lo;
+          const float* sj = src + static_cast<uint64_t>(j) * in.ts;
+#pragma unroll
+          for (int k = 0; k < kBackPlanes; ++k)
+            if (k < np) a[k] += wj * sj[static_cast<uint64_t>(k) * in.ps];
           lo = hi;
         }
       }
-      (void)nt;
-      total += wt * o.dl * a;
+#pragma unroll
+      for (int k = 0; k < kBackPlanes; ++k) total[k] += wt * o.dl * a[k];
     }
   }
-  img[id] = total;
+  float* dst = img + static_cast<uint64_t>(p0) * npix + static_cast<uint64_t>(iy) * g.nx + ix;
+#pragma unroll
+  for (int k = 0; k < kBackPlanes; ++k)
+    if (k < np) dst[static_cast<uint64_t>(k) * npix] = total[k];
 }
 
 // ratio[b] = m y / (m fp + a) over a subset's bins (compact layout of fp and
@@ -327,7 +347,7 @@ hipError_t launch_project(const ReconGeom& g, const float* img, const SinoOut& o
 }
 
 hipError_t launch_backproject(const ReconGeom& g, const SinoIn& in, float* img, int tof, hipStream_t s) {
-  const uint64_t n = static_cast<uint64_t>(g.nx) * g.ny * g.n_plane;
+  const uint64_t n = static_cast<uint64_t>(g.nx) * g.ny * ((g.n_plane + kBackPlanes - 1) / kBackPlanes);
   hipLaunchKernelGGL(backproject_kernel, dim3(static_cast<unsigned>((n + kReconThreads - 1) / kReconThreads)),
                      dim3(kReconThreads), 0, s, g, in, img, tof);
   return hipGetLastError();
