@@ -189,6 +189,7 @@ __global__ void __launch_bounds__(kReconThreads) project_kernel(ReconGeom g, con
 // applied to each of its planes' sinogram values, each plane summing in
 // the order a thread per pixel would.
 constexpr int kBackPlanes = 4;
+constexpr int kTofBlock = 4;  // TOF bins whose reads are issued together
 __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g, SinoIn in, float* __restrict__ img,
                                                                     int tof) {
   const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -245,17 +246,32 @@ __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g,
             if (k < np) a[k] = src[static_cast<uint64_t>(k) * in.ps + static_cast<uint64_t>(jlo) * in.ts];
         }
       } else {
+        // the bins in blocks of kTofBlock, every table and sinogram read of
+        // a block issued before any is used (indices clamped into range,
+        // values past the last bin or plane unused), so that a block costs
+        // one memory latency rather than one per bin
         int jlo, jhi;
         tof_range(g, o.s, jlo, jhi);
         float lo = edge_cdf(g, jlo, o.s);
-        for (int j = jlo; j <= jhi; ++j) {
-          const float hi = edge_cdf(g, j + 1, o.s);
-          const float wj = hi - lo;
-          const float* sj = src + static_cast<uint64_t>(j) * in.ts;
+        for (int j0 = jlo; j0 <= jhi; j0 += kTofBlock) {
+          float ed[kTofBlock];
+          float v[kTofBlock][kBackPlanes];
 #pragma unroll
-          for (int k = 0; k < kBackPlanes; ++k)
-            if (k < np) a[k] += wj * sj[static_cast<uint64_t>(k) * in.ps];
-          lo = hi;
+          for (int i = 0; i < kTofBlock; ++i) {
+            const int j = j0 + i <= jhi ? j0 + i : jhi;
+            ed[i] = edge_cdf(g, j + 1, o.s);
+            const float* sj = src + static_cast<uint64_t>(j) * in.ts;
+#pragma unroll
+            for (int k = 0; k < kBackPlanes; ++k) v[i][k] = sj[static_cast<uint64_t>(k < np ? k : np - 1) * in.ps];
+          }
+#pragma unroll
+          for (int i = 0; i < kTofBlock; ++i) {
+            if (j0 + i > jhi) break;
+            const float wj = ed[i] - lo;
+#pragma unroll
+            for (int k = 0; k < kBackPlanes; ++k) a[k] += wj * v[i][k];
+            lo = ed[i];
+          }
         }
       }
 #pragma unroll
