@@ -221,10 +221,21 @@ __global__ void __launch_bounds__(kReconThreads) backproject_kernel(ReconGeom g,
     const int w = static_cast<int>(ceilf(g.win_num / fmaxf(c1, 1e-3f))) + 1;
     const int rc = static_cast<int>(rintf(rho_est)) + half;
     const int r0 = rc - w < 0 ? 0 : rc - w, r1 = rc + w > g.n_rad - 1 ? g.n_rad - 1 : rc + w;
+    // each candidate's LOR entry is read one candidate ahead (the first
+    // read clamped into the row: the window is empty, r0 > r1, for pixels
+    // outside the field of view, where r0 may pass the last radial index)
+    const int rp = r0 < g.n_rad - 1 ? r0 : g.n_rad - 1;
+    float4 ln = lor_at(g, view, rp);
+    bool mn = g.major[static_cast<uint64_t>(view) * g.n_rad + rp] != 0;
     for (int rad = r0; rad <= r1; ++rad) {
-      const float4 l = lor_at(g, view, rad);
+      const float4 l = ln;
+      const bool mx = mn;
+      {
+        const int rn = rad < r1 ? rad + 1 : rad;
+        ln = lor_at(g, view, rn);
+        mn = g.major[static_cast<uint64_t>(view) * g.n_rad + rn] != 0;
+      }
       if (l.z == 0.0f && l.w == 0.0f) continue;
-      const bool mx = g.major[static_cast<uint64_t>(view) * g.n_rad + rad] != 0;
       const Sample o = lor_sample(g, l.x, l.y, l.z, l.w, mx, mx ? ix : iy);
       const int minor = mx ? iy : ix;
       float wt;
