@@ -22,11 +22,14 @@ struct AliasWork {
   std::vector<float> act;
   uint2* staging = nullptr;
   uint64_t staging_cap = 0;
+  float* image = nullptr;  // pinned copy of a reconstructed image (image to activity)
+  uint64_t image_cap = 0;
   AliasWork() = default;
   AliasWork(const AliasWork&) = delete;
   AliasWork& operator=(const AliasWork&) = delete;
   ~AliasWork() {
     if (staging) (void)hipHostFree(staging);
+    if (image) (void)hipHostFree(image);
   }
 };
 

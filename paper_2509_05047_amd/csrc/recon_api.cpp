@@ -301,18 +301,31 @@ sse_status sse_image_to_activity(sse_ctx* c, sse_phantom_id id, const float* ima
   HIP_TRY(hipSetDevice(c->device), "set device");
   const sse_phantom_desc& d = ph->desc;
   const uint64_t slice = static_cast<uint64_t>(d.nx) * d.ny, np = c->sn.n_plane;
-  std::vector<float> im(slice * np);
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  HIP_TRY(hipMemcpyAsync(im.data(), image, im.size() * sizeof(float), hipMemcpyDeviceToHost, s), "copy image");
+  // the image copy (pinned) and the activity are kept with the phantom's
+  // alias-table workspace, so that repeated updates reuse their pages
+  if (!ph->alias_work) ph->alias_work = std::make_shared<AliasWork>();
+  AliasWork& w = *ph->alias_work;
+  if (w.image_cap < slice * np) {
+    if (w.image) (void)hipHostFree(w.image);
+    w.image = nullptr;
+    w.image_cap = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.image), slice * np * sizeof(float), hipHostMallocDefault),
+            "allocate pinned image copy");
+    w.image_cap = slice * np;
+  }
+  const float* im = w.image;
+  HIP_TRY(hipMemcpyAsync(w.image, image, slice * np * sizeof(float), hipMemcpyDeviceToHost, s), "copy image");
   HIP_TRY(hipStreamSynchronize(s), "synchronise image copy");
   // phantom slice iz takes the image slice of the plane nearest its centre
   const double half_pitch = 0.5 * static_cast<double>(c->sc.length_mm) / c->sc.n_rings;
-  std::vector<float> act(slice * static_cast<uint64_t>(d.nz));
+  std::vector<float>& act = w.act;
+  act.resize(slice * static_cast<uint64_t>(d.nz));
   for (int iz = 0; iz < d.nz; ++iz) {
     const double z = d.lo_mm[2] + (iz + 0.5) * static_cast<double>(d.voxel_mm[2]);
     double fp = std::nearbyint((z + 0.5 * c->sc.length_mm) / half_pitch - 1.0);
     fp = fp < 0.0 ? 0.0 : (fp > static_cast<double>(np - 1) ? static_cast<double>(np - 1) : fp);
-    const float* src = im.data() + static_cast<uint64_t>(fp) * slice;
+    const float* src = im + static_cast<uint64_t>(fp) * slice;
     float* dst = act.data() + static_cast<uint64_t>(iz) * slice;
     for (uint64_t i = 0; i < slice; ++i) dst[i] = src[i] > 0.0f && std::isfinite(src[i]) ? src[i] : 0.0f;
   }
