@@ -272,14 +272,31 @@ bool build_alias(const float* act, uint64_t n, AliasWork& w, uint2* out, double*
     if (mass[i] < T) small[ns++] = static_cast<uint32_t>(i);
     else large[nl++] = static_cast<uint32_t>(i);
   }
+  // Vose's pairing, one pop of each stack per column: g, on top of the large
+  // stack, pairs with the small columns popped one by one and keeps its
+  // remaining mass in a register until it falls below 2^32 (pushed on the
+  // small stack, so that it is the next small column) or the small stack
+  // runs out (pushed back on the large one) -- the same pops and pushes as
+  // popping both stacks for every column.
   while (ns && nl) {
-    const uint32_t l = small[--ns], g = large[--nl];
-    const uint64_t ml = mass[l];
-    out[l] = make_uint2(static_cast<uint32_t>(ml), g);
-    const uint64_t mg = mass[g] - (T - ml);
-    mass[g] = mg;
-    if (mg < T) small[ns++] = g;
-    else large[nl++] = g;
+    const uint32_t g = large[--nl];
+    uint64_t mg = mass[g];
+    for (;;) {
+      const uint32_t l = small[--ns];
+      const uint64_t ml = mass[l];
+      out[l] = make_uint2(static_cast<uint32_t>(ml), g);
+      mg -= T - ml;
+      if (mg < T) {
+        mass[g] = mg;
+        small[ns++] = g;
+        break;
+      }
+      if (ns == 0) {
+        mass[g] = mg;
+        large[nl++] = g;
+        break;
+      }
+    }
   }
   while (nl) {
     const uint32_t g = large[--nl];
