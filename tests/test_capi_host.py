@@ -62,6 +62,33 @@ def test_host_alias_table_equals_oracle(seed):
     assert np.array_equal(th, oth) and np.array_equal(al, oal)
 
 
+@pytest.mark.parametrize("kind", ["few_heavy", "one_hot", "uniform", "heavy_last", "ragged_threads"])
+def test_host_alias_table_equals_oracle_on_skewed_activity(kind):
+    """Pairing extremes: a few heavy voxels among many empty ones (one large
+    column pairs with long runs of small ones), a single active voxel, all
+    masses equal (no pairing at all), the heavy voxel last, and a size past
+    the threaded quantisation's threshold with ranges of unequal length."""
+    rng = np.random.default_rng(5)
+    if kind == "few_heavy":
+        act = np.zeros(5000, np.float32)
+        act[rng.choice(5000, 7, replace=False)] = rng.uniform(1, 100, 7).astype(np.float32)
+    elif kind == "one_hot":
+        act = np.zeros(777, np.float32)
+        act[400] = 2.5
+    elif kind == "uniform":
+        act = np.full(1024, 0.75, np.float32)
+    elif kind == "heavy_last":
+        act = rng.uniform(0, 1, 2000).astype(np.float32)
+        act[-1] = 1e4
+    else:
+        n = (1 << 20) + 12345
+        act = rng.uniform(0, 2, n).astype(np.float32)
+        act[rng.random(n) < 0.5] = 0.0
+    th, al = sse.build_alias_table(act)
+    oth, oal = O.build_alias(act)
+    assert np.array_equal(th, oth) and np.array_equal(al, oal)
+
+
 def test_host_alias_table_equals_oracle_on_clinical_phantom():
     _, _, act = W.clinical_body()
     th, al = sse.build_alias_table(act)
