@@ -91,3 +91,45 @@ def test_smoothing_normalisation_matches_oracle_in_every_route(shape, which):
         assert np.all(got == 1.0)
     rel = np.abs(got - ref) / np.abs(ref)
     assert rel.max() < 1e-5, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
+
+
+# The clinical plane count (89) with 181 radial bins and one TOF bin: at
+# three times the paper's FWHM the fused pass takes two radial tiles of 91
+# positions, whose staged input and smoothed columns take 139 KB of LDS (the
+# clinical shape: 141 KB), above 128 KB.
+DEEP = (W.Scanner(n_crystals=182, n_rings=45, radius_mm=312.0, length_mm=250.0, crystals_per_module=7,
+                  rings_per_block=5),
+        W.Sinogram(n_rad=181, n_view=91, n_plane=89, n_tof=1, tof_bin_mm=624.0, tof_sigma_mm=0.0))
+
+
+@pytest.mark.parametrize("which", ["all", "rad_plane"])
+def test_fused_pass_with_large_lds_tiles_matches_oracle(which):
+    """Smoothing and the smoothing normalisation at three times the paper's
+    FWHM with the clinical plane count, against the oracle on the whole
+    sinogram."""
+    import paper_2509_05047_amd as sse
+    scanner, sino = DEEP
+    sigma = NORM_SIGMAS[which]
+    rng = np.random.default_rng(13)
+    Wd = rng.uniform(0.2, 2.0, sino.shape)
+    Wd[0, 0, 0, :5] = 0.0
+    ref_s = post.gaussian_smooth(Wd.astype(np.float32), sigma).reshape(sino.shape)
+    ref_n = post.smoothing_normalisation(Wd, 0.75, sigma)
+    ctx = sse.Context(scanner, sino, dict(W.PHYSICS_DEFAULT))
+    try:
+        x = torch.from_numpy(Wd.astype(np.float32).ravel()).cuda()
+        out = torch.empty_like(x)
+        ctx.gaussian_smooth(x, out, sigma)
+        dw = torch.from_numpy(Wd.ravel()).cuda()
+        norm = torch.empty(sino.n_bins, dtype=torch.float32, device="cuda")
+        ctx.smoothing_normalisation(dw, 0.75, norm, sigma)
+        torch.cuda.synchronize()
+        got_s = out.cpu().numpy().reshape(sino.shape)
+        got_n = norm.cpu().numpy().reshape(sino.shape)
+    finally:
+        ctx.close()
+    rel = np.abs(got_s - ref_s) / np.abs(ref_s)
+    assert rel.max() < 1e-5, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
+    assert np.all(got_n[Wd == 0.0] == 1.0)
+    rel = np.abs(got_n - ref_n) / np.abs(ref_n)
+    assert rel.max() < 1e-5, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
